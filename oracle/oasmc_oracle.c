@@ -1,0 +1,1060 @@
+/*
+ * oasmc_oracle.c -- plain, slow, fp64 CPU oracle for Optimised Annealed SMC
+ * (OASMC) and its annealed-importance-sampling special case (OAIS), written
+ * from "Optimised Annealed Sequential Monte Carlo Samplers" (Syed,
+ * Bouchard-Cote, Chern, Doucet, arXiv 2408.12057).
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  The product (the HIP
+ * library under paper_2408_12057_amd/) never includes, links or calls it, and
+ * this file includes nothing from the product.
+ *
+ * Everything is IEEE binary64.  The one concession to the fp32 state that the
+ * benchmarked configurations prescribe is the `state_f32` option: when set,
+ * every stored particle coordinate is rounded to binary32 right after it is
+ * produced (initial draw, proposal), and all arithmetic stays fp64.
+ *
+ * Sections of the paper each function follows:
+ *   asmc()            -- Alg. 1 (ASMC): init from eta, propagate with a
+ *                        pi_beta-invariant MCMC kernel, incremental weight of
+ *                        the quasi-reversal backward kernel at the PRE-move
+ *                        state, moments g_hat_{t,i}, reweight, optional
+ *                        resampling, Z_hat = prod_r mean(w_{tau_r^-}).
+ *   the AIS branch    -- Sec. "Optimised AIS (OAIS)": particle loop outside
+ *                        the time loop (no resampling, particles independent).
+ *   moments           -- eq. (CESS): g_hat_{t,i} = sum_n w_{t-1}^n (g_t^n)^i.
+ *   optimise_schedule -- Alg. 3 with a monotone (Fritsch-Carlson PCHIP)
+ *                        interpolant of the knots (Lambda_hat_t, beta_t).
+ *   run()             -- Alg. 2 (OASMC round loop) with the Budget rules of
+ *                        Sec. "Increasing the number of particles and ASMC
+ *                        iterations" and the across-round kernel adaptation of
+ *                        the appendix on exploration kernels.
+ *   Philox4x32-10     -- Salmon, Moraes, Dror, Shaw, "Parallel random
+ *                        numbers: as easy as 1, 2, 3", SC'11 (its published
+ *                        definition), used for common random numbers.
+ *
+ * Readings of the paper where it is silent are listed in the design notes;
+ * the ones that shape this code are restated next to the code they shape.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+/* ------------------------------------------------------------------------ */
+/* Status codes (same meaning as the product's, defined independently).     */
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-3)
+#define ORC_ENONFINITE (-4)
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon et al., SC'11).                                     */
+/* ------------------------------------------------------------------------ */
+static const uint32_t PHILOX_MUL0 = 0xD2511F53u;
+static const uint32_t PHILOX_MUL1 = 0xCD9E8D57u;
+static const uint32_t PHILOX_WEYL0 = 0x9E3779B9u;
+static const uint32_t PHILOX_WEYL1 = 0xBB67AE85u;
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {            /* key schedule: Weyl sequence */
+            k0 += PHILOX_WEYL0;
+            k1 += PHILOX_WEYL1;
+        }
+        uint64_t prod0 = (uint64_t)PHILOX_MUL0 * (uint64_t)x0;
+        uint64_t prod1 = (uint64_t)PHILOX_MUL1 * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y1 = lo1;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        uint32_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/*
+ * Counter layout (the paper only asks for split generators so that CPU and
+ * GPU produce the same realisation; this layout is the reading adopted):
+ *   key  = (seed low 32 bits, seed high 32 bits)
+ *   c0   = particle index n (global), c1 = annealing step t (0 = initial draw)
+ *   c2   = (round k & 0xFFFF) | (problem id << 16)
+ *   c3   = (stream << 24) | (substep << 16) | block
+ * streams: 0 initial normals, 1 move normals, 2 accept uniform,
+ *          3 resampling uniform.
+ */
+enum { STREAM_INIT = 0, STREAM_MOVE = 1, STREAM_ACCEPT = 2, STREAM_RESAMPLE = 3 };
+
+typedef struct {
+    uint64_t seed;
+    uint32_t round_k;
+    uint32_t problem;
+} rng_key;
+
+static void draw_block(const rng_key* K, uint32_t n, uint32_t t, uint32_t stream,
+                       uint32_t substep, uint32_t block, uint32_t out[4])
+{
+    uint32_t ctr[4], key[2];
+    ctr[0] = n;
+    ctr[1] = t;
+    ctr[2] = (K->round_k & 0xFFFFu) | (K->problem << 16);
+    ctr[3] = (stream << 24) | ((substep & 0xFFu) << 16) | (block & 0xFFFFu);
+    key[0] = (uint32_t)(K->seed & 0xFFFFFFFFu);
+    key[1] = (uint32_t)(K->seed >> 32);
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* A 32-bit word w maps to the open-interval uniform (w + 1/2) 2^-32. */
+static double word_to_uniform(uint32_t w)
+{
+    return ((double)w + 0.5) * (1.0 / 4294967296.0);
+}
+
+/*
+ * Standard normals by the Box-Muller transform: block b supplies normals
+ * 4b..4b+3; words (w0,w1) give 4b (cosine) and 4b+1 (sine), words (w2,w3)
+ * give 4b+2 and 4b+3.  r = sqrt(-2 log u_a), angle = 2 pi u_b.
+ */
+static void draw_normals(const rng_key* K, uint32_t n, uint32_t t, uint32_t stream,
+                         uint32_t substep, int count, double* z)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int j = 0; j < count; j += 4) {
+        uint32_t w[4];
+        draw_block(K, n, t, stream, substep, (uint32_t)(j / 4), w);
+        for (int pair = 0; pair < 2; ++pair) {
+            double ua = word_to_uniform(w[2 * pair]);
+            double ub = word_to_uniform(w[2 * pair + 1]);
+            double r = sqrt(-2.0 * log(ua));
+            double ang = two_pi * ub;
+            int j0 = j + 2 * pair;
+            if (j0 < count) z[j0] = r * cos(ang);
+            if (j0 + 1 < count) z[j0 + 1] = r * sin(ang);
+        }
+    }
+}
+
+static double draw_uniform(const rng_key* K, uint32_t n, uint32_t t, uint32_t stream,
+                           uint32_t substep)
+{
+    uint32_t w[4];
+    draw_block(K, n, t, stream, substep, 0u, w);
+    return word_to_uniform(w[0]);
+}
+
+/* Exported for the RNG pins. */
+void orc_normals(uint64_t seed, uint32_t round_k, uint32_t problem, uint32_t n, uint32_t t,
+                 uint32_t stream, uint32_t substep, int count, double* z)
+{
+    rng_key K = {seed, round_k, problem};
+    draw_normals(&K, n, t, stream, substep, count, z);
+}
+
+double orc_uniform(uint64_t seed, uint32_t round_k, uint32_t problem, uint32_t n, uint32_t t,
+                   uint32_t stream, uint32_t substep)
+{
+    rng_key K = {seed, round_k, problem};
+    return draw_uniform(&K, n, t, stream, substep);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Targets, reference, annealing path.                                       */
+/* ------------------------------------------------------------------------ */
+enum { FAM_GAUSS = 1, FAM_LOGREG = 2, FAM_GMM = 3 };
+enum { MOVE_RWMH = 1, MOVE_MALA = 2, MOVE_HMC = 3, MOVE_EXACT = 4, MOVE_IDENTITY = 5 };
+/* MOVE_EXACT (Gaussian family only) draws X ~ pi_beta exactly, the idealised
+ * kernel under which the efficient-local-exploration assumption holds;
+ * MOVE_IDENTITY leaves X unchanged (AIS then reduces to importance sampling
+ * from eta).  Both exist only to pin the oracle against closed forms. */
+
+typedef struct {
+    int family;
+    int d;
+    /* FAM_GAUSS: gamma(x) = exp(-|x - mu|^2 / (2 sigma2)) */
+    const double* mu;
+    double sigma2;
+    /* FAM_LOGREG: gamma(x) = eta(x) prod_i sigmoid(z_i)^y_i (1-sigmoid(z_i))^(1-y_i),
+     * z_i = X_i . x, X row-major n x d, y in {0,1} */
+    const double* X;
+    const double* y;
+    int n;
+    /* FAM_GMM: gamma(x) = (1/K) sum_k exp(-|x - m_k|^2 / (2 exp(2 s_k))) */
+    int K;
+    const double* means;      /* K x d */
+    const double* log_scales; /* K */
+    /* reference eta = N(ref_mean, ref_sigma2 I), normalised (Z_0 = 1) */
+    const double* ref_mean;   /* may be NULL: zero mean */
+    double ref_sigma2;
+} orc_problem;
+
+static double ref_mean_at(const orc_problem* P, int i)
+{
+    return P->ref_mean ? P->ref_mean[i] : 0.0;
+}
+
+/* log eta(x), the normalised reference density. */
+static double log_eta(const orc_problem* P, const double* x)
+{
+    const double log_two_pi = 1.8378770664093454835606594728112;
+    double ss = 0.0;
+    for (int i = 0; i < P->d; ++i) {
+        double r = x[i] - ref_mean_at(P, i);
+        ss += r * r;
+    }
+    return -ss / (2.0 * P->ref_sigma2) - 0.5 * P->d * (log_two_pi + log(P->ref_sigma2));
+}
+
+static void grad_log_eta(const orc_problem* P, const double* x, double* g)
+{
+    for (int i = 0; i < P->d; ++i) g[i] = -(x[i] - ref_mean_at(P, i)) / P->ref_sigma2;
+}
+
+static double softplus(double z)
+{
+    return (z > 0.0 ? z : 0.0) + log1p(exp(-fabs(z)));
+}
+
+static double sigmoid(double z)
+{
+    if (z >= 0.0) return 1.0 / (1.0 + exp(-z));
+    double e = exp(z);
+    return e / (1.0 + e);
+}
+
+/* log gamma(x) for the Gaussian and mixture families. */
+static double log_gamma_closed(const orc_problem* P, const double* x)
+{
+    if (P->family == FAM_GAUSS) {
+        double ss = 0.0;
+        for (int i = 0; i < P->d; ++i) {
+            double r = x[i] - P->mu[i];
+            ss += r * r;
+        }
+        return -ss / (2.0 * P->sigma2);
+    }
+    /* FAM_GMM: log of the equal-weight average of unnormalised components */
+    double mx = -INFINITY;
+    double* e = (double*)malloc(sizeof(double) * P->K);
+    for (int k = 0; k < P->K; ++k) {
+        double ss = 0.0;
+        for (int i = 0; i < P->d; ++i) {
+            double r = x[i] - P->means[(size_t)k * P->d + i];
+            ss += r * r;
+        }
+        e[k] = -ss / (2.0 * exp(2.0 * P->log_scales[k]));
+        if (e[k] > mx) mx = e[k];
+    }
+    double s = 0.0;
+    for (int k = 0; k < P->K; ++k) s += exp(e[k] - mx);
+    free(e);
+    return mx + log(s) - log((double)P->K);
+}
+
+/*
+ * ell(x) = log gamma(x) - log eta(x): the sufficient statistic V of the
+ * linear (geometric) path, so that log gamma_beta = log eta + beta * ell.
+ * For the logistic-regression family gamma = eta * likelihood, so ell is the
+ * log-likelihood itself.
+ */
+static double ell(const orc_problem* P, const double* x)
+{
+    if (P->family == FAM_LOGREG) {
+        double ll = 0.0;
+        for (int i = 0; i < P->n; ++i) {
+            const double* row = P->X + (size_t)i * P->d;
+            double z = 0.0;
+            for (int j = 0; j < P->d; ++j) z += row[j] * x[j];
+            ll += P->y[i] * z - softplus(z);
+        }
+        return ll;
+    }
+    return log_gamma_closed(P, x) - log_eta(P, x);
+}
+
+/* Gradient of ell. */
+static void grad_ell(const orc_problem* P, const double* x, double* g)
+{
+    int d = P->d;
+    if (P->family == FAM_LOGREG) {
+        for (int j = 0; j < d; ++j) g[j] = 0.0;
+        for (int i = 0; i < P->n; ++i) {
+            const double* row = P->X + (size_t)i * d;
+            double z = 0.0;
+            for (int j = 0; j < d; ++j) z += row[j] * x[j];
+            double r = P->y[i] - sigmoid(z);
+            for (int j = 0; j < d; ++j) g[j] += r * row[j];
+        }
+        return;
+    }
+    double* ge = (double*)malloc(sizeof(double) * d);
+    grad_log_eta(P, x, ge);
+    if (P->family == FAM_GAUSS) {
+        for (int i = 0; i < d; ++i) g[i] = -(x[i] - P->mu[i]) / P->sigma2 - ge[i];
+    } else {
+        /* mixture: responsibilities r_k = softmax_k(-|x - m_k|^2 / (2 v_k)) */
+        double* e = (double*)malloc(sizeof(double) * P->K);
+        double mx = -INFINITY;
+        for (int k = 0; k < P->K; ++k) {
+            double ss = 0.0;
+            for (int i = 0; i < d; ++i) {
+                double r = x[i] - P->means[(size_t)k * d + i];
+                ss += r * r;
+            }
+            e[k] = -ss / (2.0 * exp(2.0 * P->log_scales[k]));
+            if (e[k] > mx) mx = e[k];
+        }
+        double s = 0.0;
+        for (int k = 0; k < P->K; ++k) {
+            e[k] = exp(e[k] - mx);
+            s += e[k];
+        }
+        for (int i = 0; i < d; ++i) g[i] = -ge[i];
+        for (int k = 0; k < P->K; ++k) {
+            double rk = e[k] / s;
+            double v = exp(2.0 * P->log_scales[k]);
+            for (int i = 0; i < d; ++i) g[i] += rk * (P->means[(size_t)k * d + i] - x[i]) / v;
+        }
+        free(e);
+    }
+    free(ge);
+}
+
+/* log pi_beta(x) up to the constant -log Z_beta, for the linear path. */
+static double log_anneal(const orc_problem* P, double beta, const double* x, double ell_x)
+{
+    return log_eta(P, x) + beta * ell_x;
+}
+
+static void grad_log_anneal(const orc_problem* P, double beta, const double* x,
+                            const double* gell, double* g)
+{
+    grad_log_eta(P, x, g);
+    for (int i = 0; i < P->d; ++i) g[i] += beta * gell[i];
+}
+
+static double store(double v, int state_f32)
+{
+    return state_f32 ? (double)(float)v : v;
+}
+
+/* ------------------------------------------------------------------------ */
+/* pi_beta-invariant Metropolis-Hastings moves (forward kernel K_beta).      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int move;         /* MOVE_RWMH / MOVE_MALA / MOVE_HMC */
+    int leapfrog;     /* HMC: number of leapfrog steps per trajectory */
+    int resample;     /* 0: AIS (no resampling), 1: adaptive resampling */
+    int trigger;      /* 0: ESS < nu N, 1: CESS < nu N */
+    double nu;
+    int state_f32;
+    int nthreads;     /* 0: OpenMP default */
+} orc_opts;
+
+typedef struct {
+    double* x;      /* d */
+    double ell;     /* ell(x) */
+    double* gell;   /* d: gradient of ell at x (MALA, HMC) */
+} particle;
+
+/*
+ * One MH step targeting pi_beta from particle p, with step size eps (RWMH:
+ * proposal standard deviation; MALA: Langevin step; HMC: leapfrog step).
+ * Draws: d normals (stream 1) and one uniform (stream 2), keyed (n, t).
+ * Returns 1 when accepted.  *margin receives log alpha - log u.
+ */
+static int mh_step(const orc_problem* P, const orc_opts* O, const rng_key* K, uint32_t n,
+                   uint32_t t, double beta, double eps, particle* p, double* work,
+                   double* margin)
+{
+    int d = P->d;
+    double* xi = work;          /* d */
+    double* xp = work + d;      /* d: proposal */
+    double* gp = work + 2 * d;  /* d: grad ell at proposal */
+    double* ga = work + 3 * d;  /* d: grad log pi_beta */
+    double* mom = work + 4 * d; /* d: HMC momentum */
+    draw_normals(K, n, t, STREAM_MOVE, 0, d, xi);
+    if (O->move == MOVE_IDENTITY || O->move == MOVE_EXACT) {
+        if (O->move == MOVE_EXACT) {
+            /* pi_beta for Gaussian eta and gamma: precision lam, mean m_beta */
+            double lam = (1.0 - beta) / P->ref_sigma2 + beta / P->sigma2;
+            for (int i = 0; i < d; ++i) {
+                double mb = ((1.0 - beta) * ref_mean_at(P, i) / P->ref_sigma2 +
+                             beta * P->mu[i] / P->sigma2) / lam;
+                p->x[i] = store(mb + xi[i] / sqrt(lam), O->state_f32);
+            }
+            p->ell = ell(P, p->x);
+        }
+        if (margin) *margin = INFINITY;
+        return 1;
+    }
+    double log_alpha;
+    double ell_p = 0.0;
+
+    if (O->move == MOVE_RWMH) {
+        for (int i = 0; i < d; ++i) xp[i] = store(p->x[i] + eps * xi[i], O->state_f32);
+        ell_p = ell(P, xp);
+        log_alpha = log_anneal(P, beta, xp, ell_p) - log_anneal(P, beta, p->x, p->ell);
+    } else if (O->move == MOVE_MALA) {
+        /* x' = x + (eps^2/2) grad log pi_beta(x) + eps xi */
+        double h = 0.5 * eps * eps;
+        grad_log_anneal(P, beta, p->x, p->gell, ga);
+        for (int i = 0; i < d; ++i) xp[i] = store(p->x[i] + h * ga[i] + eps * xi[i], O->state_f32);
+        ell_p = ell(P, xp);
+        grad_ell(P, xp, gp);
+        /* log q(x'|x) with q(y|x) = N(y; x + h grad log pi_beta(x), eps^2 I) */
+        double fwd = 0.0, bwd = 0.0;
+        for (int i = 0; i < d; ++i) {
+            double r = xp[i] - p->x[i] - h * ga[i];
+            fwd += r * r;
+        }
+        grad_log_anneal(P, beta, xp, gp, ga);
+        for (int i = 0; i < d; ++i) {
+            double r = p->x[i] - xp[i] - h * ga[i];
+            bwd += r * r;
+        }
+        log_alpha = log_anneal(P, beta, xp, ell_p) - log_anneal(P, beta, p->x, p->ell)
+                    - bwd / (2.0 * eps * eps) + fwd / (2.0 * eps * eps);
+    } else {
+        /* HMC: H(x, p) = -log pi_beta(x) + |p|^2 / 2, L leapfrog steps of size eps
+         * (half momentum step, full position step, half momentum step).  Each
+         * position is a stored state, so it is rounded like one. */
+        int L = O->leapfrog;
+        double kin0 = 0.0;
+        for (int i = 0; i < d; ++i) {
+            mom[i] = xi[i];
+            kin0 += 0.5 * mom[i] * mom[i];
+            xp[i] = p->x[i];
+        }
+        grad_log_anneal(P, beta, p->x, p->gell, ga);
+        for (int i = 0; i < d; ++i) gp[i] = p->gell[i];
+        for (int l = 0; l < L; ++l) {
+            for (int i = 0; i < d; ++i) mom[i] += 0.5 * eps * ga[i];
+            for (int i = 0; i < d; ++i) xp[i] = store(xp[i] + eps * mom[i], O->state_f32);
+            grad_ell(P, xp, gp);
+            grad_log_anneal(P, beta, xp, gp, ga);
+            for (int i = 0; i < d; ++i) mom[i] += 0.5 * eps * ga[i];
+        }
+        ell_p = ell(P, xp);
+        double kin1 = 0.0;
+        for (int i = 0; i < d; ++i) kin1 += 0.5 * mom[i] * mom[i];
+        log_alpha = (log_anneal(P, beta, xp, ell_p) - kin1)
+                    - (log_anneal(P, beta, p->x, p->ell) - kin0);
+    }
+
+    double log_u = log(draw_uniform(K, n, t, STREAM_ACCEPT, 0));
+    if (margin) *margin = log_alpha - log_u;
+    int accept = (log_u < log_alpha); /* NaN log_alpha rejects */
+    if (accept) {
+        for (int i = 0; i < d; ++i) p->x[i] = xp[i];
+        p->ell = ell_p;
+        if (O->move != MOVE_RWMH)
+            for (int i = 0; i < d; ++i) p->gell[i] = gp[i];
+    }
+    return accept;
+}
+
+/* Particle initialisation X_0 ~ eta (stream 0, t = 0). */
+static void init_particle(const orc_problem* P, const orc_opts* O, const rng_key* K,
+                          uint32_t n, particle* p, double* work)
+{
+    int d = P->d;
+    draw_normals(K, n, 0u, STREAM_INIT, 0, d, work);
+    double s = sqrt(P->ref_sigma2);
+    for (int i = 0; i < d; ++i) p->x[i] = store(ref_mean_at(P, i) + s * work[i], O->state_f32);
+    p->ell = ell(P, p->x);
+    if (O->move != MOVE_RWMH) grad_ell(P, p->x, p->gell);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Plain log-sum-exp helpers (two-pass: max, then shifted sum).              */
+/* ------------------------------------------------------------------------ */
+static double logsumexp(const double* v, int64_t m, int64_t stride)
+{
+    double mx = -INFINITY;
+    for (int64_t j = 0; j < m; ++j) {
+        double a = v[j * stride];
+        if (a > mx) mx = a;
+    }
+    if (mx == -INFINITY) return -INFINITY;
+    if (!isfinite(mx)) return mx; /* +inf or NaN propagate */
+    double s = 0.0;
+    for (int64_t j = 0; j < m; ++j) s += exp(v[j * stride] - mx);
+    return mx + log(s);
+}
+
+/*
+ * Moments of eq. (CESS) in log space from the weights before the reweight
+ * (w_{t-1}) and the incremental weights g_t:
+ *   log g_hat_{t,i} = logsumexp_n (log w_{t-1}^n + i log g_t^n), i = 0, 1, 2.
+ */
+static void moments(int64_t N, const double* lw_prev, const double* lg, double* out3, double* tmp)
+{
+    for (int i = 0; i < 3; ++i) {
+        for (int64_t n = 0; n < N; ++n) tmp[n] = lw_prev[n] + (double)i * lg[n];
+        out3[i] = logsumexp(tmp, N, 1);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Systematic resampling with an exact integer CDF.                          */
+/* ------------------------------------------------------------------------ */
+/*
+ * The paper names systematic resampling without defining it; the reading:
+ * one uniform U per event, points (n + U)/N, ancestor a_n = min{m : C_m > p_n}
+ * where C is the cumulative normalised weight.  To make the ancestors an
+ * exact function of the log-weights, weights are quantised to integers
+ *   q_m = floor(exp(lw_m - max lw) * 2^B),  B = 62 - ceil(log2 N),
+ * the CDF is the exact integer prefix sum, and the points are
+ *   p_n = floor(S (2 (n 2^32 + u) + 1) / (N 2^33)),  S = sum q,
+ * which is floor(S (n + U)/N) with U = (u + 1/2) 2^-32 taken exactly.
+ */
+static int quant_bits(int64_t N)
+{
+    int lg = 0;
+    while (((int64_t)1 << lg) < N) ++lg;
+    return 62 - lg;
+}
+
+int orc_systematic(int64_t N, const double* lw, uint32_t u, int32_t* anc)
+{
+    if (N <= 0) return ORC_EINVAL;
+    double mx = -INFINITY;
+    for (int64_t m = 0; m < N; ++m)
+        if (lw[m] > mx) mx = lw[m];
+    if (!(mx > -INFINITY) || !isfinite(mx)) return ORC_ENONFINITE;
+    int B = quant_bits(N);
+    uint64_t* C = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)N);
+    if (!C) return ORC_ENOMEM;
+    uint64_t run = 0;
+    double scale = ldexp(1.0, B);
+    for (int64_t m = 0; m < N; ++m) {
+        double e = exp(lw[m] - mx);
+        uint64_t q = (lw[m] == lw[m]) ? (uint64_t)floor(e * scale) : 0u;
+        run += q;
+        C[m] = run;
+    }
+    uint64_t S = run;
+    int64_t m = 0;
+    for (int64_t n = 0; n < N; ++n) {
+        unsigned __int128 num = (unsigned __int128)S *
+                                (unsigned __int128)(2u * (((uint64_t)n << 32) | (uint64_t)u) + 1u);
+        unsigned __int128 den = (unsigned __int128)N << 33;
+        uint64_t pn = (uint64_t)(num / den);
+        /* points increase with n, so the search resumes where it stopped */
+        while (C[m] <= pn) ++m;
+        anc[n] = (int32_t)m;
+    }
+    free(C);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 1: ASMC(N, B_T).                                                      */
+/* ------------------------------------------------------------------------ */
+/*
+ * Outputs (all host arrays owned by the caller):
+ *   log_g[3*T]   log g_hat_{t,i} at [i*T + t-1]
+ *   acc[T]       fraction of particles whose move at t was accepted
+ *   logZ         log Z_hat
+ *   lw_out[N]    final log-weights, x_out[N*d] final states
+ *   n_resample   number of resampling events strictly before T
+ * Optional (NULL to skip):
+ *   accept[N*T]  per particle and step accept flag, margin[N*T] log alpha - log u
+ *   resampled[T] 1 where a resampling event happened at t
+ *   ess[T]       relative ESS of w_{t^-}
+ * subset/n_subset (AIS only): run only these global particle indices; every
+ *   per-particle output is then indexed by position in the subset and every
+ *   cross-particle statistic is over the subset.
+ */
+int orc_asmc(const orc_problem* P, const orc_opts* O, int64_t N, int T, const double* beta,
+             const double* eps, uint64_t seed, uint32_t round_k, uint32_t problem_id,
+             double* log_g, double* acc, double* logZ, double* lw_out, double* x_out,
+             int* n_resample, unsigned char* accept, double* margin, int* resampled,
+             double* ess, const int64_t* subset, int64_t n_subset)
+{
+    if (!P || !O || T < 1 || P->d < 1 || !beta || !eps) return ORC_EINVAL;
+    if (beta[0] != 0.0 || beta[T] != 1.0) return ORC_EINVAL;
+    for (int t = 1; t <= T; ++t)
+        if (!(beta[t] > beta[t - 1])) return ORC_EINVAL;
+    int64_t M = subset ? n_subset : N;
+    if (M < 1) return ORC_EINVAL;
+    if (subset && O->resample) return ORC_EINVAL;
+    int d = P->d;
+    rng_key K = {seed, round_k, problem_id};
+    if (O->nthreads > 0) omp_set_num_threads(O->nthreads);
+
+    double* X = (double*)malloc(sizeof(double) * (size_t)M * d);
+    double* G = (double*)malloc(sizeof(double) * (size_t)M * d);
+    double* L = (double*)malloc(sizeof(double) * (size_t)M);
+    double* LW = (double*)calloc((size_t)M * (T + 1), sizeof(double)); /* lw before step t */
+    double* LG = (double*)malloc(sizeof(double) * (size_t)M * T);
+    unsigned char* A = (unsigned char*)malloc((size_t)M * T);
+    if (!X || !G || !L || !LW || !LG || !A) {
+        free(X); free(G); free(L); free(LW); free(LG); free(A);
+        return ORC_ENOMEM;
+    }
+    int status = ORC_OK;
+    int nres = 0;
+    double log_z = 0.0;
+
+    if (!O->resample) {
+        /* OAIS: the particle loop is outside the time loop (loop swap). */
+#pragma omp parallel
+        {
+            double* work = (double*)malloc(sizeof(double) * 6 * d);
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t j = 0; j < M; ++j) {
+                uint32_t n = (uint32_t)(subset ? subset[j] : j);
+                particle p = {X + (size_t)j * d, 0.0, G + (size_t)j * d};
+                init_particle(P, O, &K, n, &p, work);
+                double lw = 0.0;
+                for (int t = 1; t <= T; ++t) {
+                    /* incremental weight at the pre-move state:
+                     * log g_t = log gamma_{beta_t}(x) - log gamma_{beta_{t-1}}(x) */
+                    double lg = (beta[t] - beta[t - 1]) * p.ell;
+                    LG[(size_t)j * T + (t - 1)] = lg;
+                    lw += lg;
+                    LW[(size_t)j * (T + 1) + t] = lw;
+                    double mg = 0.0;
+                    A[(size_t)j * T + (t - 1)] =
+                        (unsigned char)mh_step(P, O, &K, n, (uint32_t)t, beta[t], eps[t - 1], &p,
+                                               work, &mg);
+                    if (margin) margin[(size_t)j * T + (t - 1)] = mg;
+                }
+                L[j] = p.ell;
+            }
+            free(work);
+        }
+        double* tmp = (double*)malloc(sizeof(double) * (size_t)M * 2);
+        double* col = tmp + M;
+        for (int t = 1; t <= T; ++t) {
+            double* lwp = (double*)malloc(sizeof(double) * (size_t)M);
+            double* lgt = (double*)malloc(sizeof(double) * (size_t)M);
+            for (int64_t j = 0; j < M; ++j) {
+                lwp[j] = LW[(size_t)j * (T + 1) + (t - 1)];
+                lgt[j] = LG[(size_t)j * T + (t - 1)];
+            }
+            double m3[3];
+            moments(M, lwp, lgt, m3, tmp);
+            for (int i = 0; i < 3; ++i) log_g[i * T + (t - 1)] = m3[i];
+            if (ess) {
+                for (int64_t j = 0; j < M; ++j) col[j] = 2.0 * (lwp[j] + lgt[j]);
+                ess[t - 1] = exp(2.0 * m3[1] - logsumexp(col, M, 1) - log((double)M));
+            }
+            if (resampled) resampled[t - 1] = 0;
+            free(lwp);
+            free(lgt);
+        }
+        for (int64_t j = 0; j < M; ++j) tmp[j] = LW[(size_t)j * (T + 1) + T];
+        /* Z_hat = (1/N) sum_n w_T^n (a single final event, R = 1) */
+        log_z = logsumexp(tmp, M, 1) - log((double)M);
+        free(tmp);
+    } else {
+        /* ASMC with adaptive resampling: time loop outside. */
+        double* lw = (double*)calloc((size_t)M, sizeof(double));
+        double* lg = (double*)malloc(sizeof(double) * (size_t)M);
+        double* tmp = (double*)malloc(sizeof(double) * (size_t)M);
+        int32_t* anc = (int32_t*)malloc(sizeof(int32_t) * (size_t)M);
+        double* X2 = (double*)malloc(sizeof(double) * (size_t)M * d);
+        double* G2 = (double*)malloc(sizeof(double) * (size_t)M * d);
+        double* L2 = (double*)malloc(sizeof(double) * (size_t)M);
+#pragma omp parallel
+        {
+            double* work = (double*)malloc(sizeof(double) * 6 * d);
+#pragma omp for schedule(static)
+            for (int64_t j = 0; j < M; ++j) {
+                particle p = {X + (size_t)j * d, 0.0, G + (size_t)j * d};
+                init_particle(P, O, &K, (uint32_t)j, &p, work);
+                L[j] = p.ell;
+            }
+            free(work);
+        }
+        for (int t = 1; t <= T && status == ORC_OK; ++t) {
+            for (int64_t j = 0; j < M; ++j) lg[j] = (beta[t] - beta[t - 1]) * L[j];
+            double m3[3];
+            moments(M, lw, lg, m3, tmp);
+            for (int i = 0; i < 3; ++i) log_g[i * T + (t - 1)] = m3[i];
+            for (int64_t j = 0; j < M; ++j) lw[j] += lg[j];
+            int na = 0;
+#pragma omp parallel reduction(+ : na)
+            {
+                double* work = (double*)malloc(sizeof(double) * 6 * d);
+#pragma omp for schedule(static)
+                for (int64_t j = 0; j < M; ++j) {
+                    particle p = {X + (size_t)j * d, L[j], G + (size_t)j * d};
+                    double mg = 0.0;
+                    int a = mh_step(P, O, &K, (uint32_t)j, (uint32_t)t, beta[t], eps[t - 1], &p,
+                                    work, &mg);
+                    L[j] = p.ell;
+                    A[(size_t)j * T + (t - 1)] = (unsigned char)a;
+                    if (margin) margin[(size_t)j * T + (t - 1)] = mg;
+                    na += a;
+                }
+                free(work);
+            }
+            (void)na;
+            /* relative ESS of w_{t^-} and the conditional ESS of eq. (CESS) */
+            for (int64_t j = 0; j < M; ++j) tmp[j] = 2.0 * lw[j];
+            double log_sum_w = m3[1]; /* sum_n w_{t-1} g_t = sum_n w_{t^-} */
+            double rel_ess = exp(2.0 * log_sum_w - logsumexp(tmp, M, 1) - log((double)M));
+            double rel_cess = exp(-(m3[2] - 2.0 * m3[1] + m3[0]));
+            if (ess) ess[t - 1] = rel_ess;
+            int fire = (O->trigger == 0) ? (rel_ess < O->nu) : (rel_cess < O->nu);
+            if (resampled) resampled[t - 1] = 0;
+            if (t == T) {
+                /* the final event at tau_R = T: no resampling needed for Z_hat */
+                log_z += logsumexp(lw, M, 1) - log((double)M);
+            } else if (fire) {
+                log_z += logsumexp(lw, M, 1) - log((double)M);
+                uint32_t w[4];
+                draw_block(&K, 0xFFFFFFFFu, (uint32_t)t, STREAM_RESAMPLE, 0, 0, w);
+                int rs = orc_systematic(M, lw, w[0], anc);
+                if (rs != ORC_OK) {
+                    status = rs;
+                    break;
+                }
+                for (int64_t j = 0; j < M; ++j) {
+                    memcpy(X2 + (size_t)j * d, X + (size_t)anc[j] * d, sizeof(double) * d);
+                    memcpy(G2 + (size_t)j * d, G + (size_t)anc[j] * d, sizeof(double) * d);
+                    L2[j] = L[anc[j]];
+                }
+                memcpy(X, X2, sizeof(double) * (size_t)M * d);
+                memcpy(G, G2, sizeof(double) * (size_t)M * d);
+                memcpy(L, L2, sizeof(double) * (size_t)M);
+                for (int64_t j = 0; j < M; ++j) lw[j] = 0.0;
+                ++nres;
+                if (resampled) resampled[t - 1] = 1;
+            }
+        }
+        for (int64_t j = 0; j < M; ++j) LW[(size_t)j * (T + 1) + T] = lw[j];
+        free(lw); free(lg); free(tmp); free(anc); free(X2); free(G2); free(L2);
+    }
+
+    if (status == ORC_OK) {
+        for (int t = 1; t <= T; ++t) {
+            int64_t cnt = 0;
+            for (int64_t j = 0; j < M; ++j) cnt += A[(size_t)j * T + (t - 1)];
+            acc[t - 1] = (double)cnt / (double)M;
+        }
+        for (int64_t j = 0; j < M; ++j) {
+            lw_out[j] = LW[(size_t)j * (T + 1) + T];
+            memcpy(x_out + (size_t)j * d, X + (size_t)j * d, sizeof(double) * d);
+        }
+        if (accept) memcpy(accept, A, (size_t)M * T);
+        *logZ = log_z;
+        if (n_resample) *n_resample = nres;
+        if (!isfinite(log_z)) status = ORC_ENONFINITE;
+    }
+    free(X); free(G); free(L); free(LW); free(LG); free(A);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 3: OptimiseSchedule.                                                  */
+/* ------------------------------------------------------------------------ */
+/* Fritsch-Carlson monotone piecewise-cubic Hermite interpolation (PCHIP):
+ * knot slopes by the weighted harmonic mean of adjacent secants (zero at a
+ * change of sign), shape-preserving three-point end slopes. */
+static void pchip_slopes(int m, const double* xs, const double* ys, double* s)
+{
+    if (m == 2) {
+        s[0] = s[1] = (ys[1] - ys[0]) / (xs[1] - xs[0]);
+        return;
+    }
+    double* h = (double*)malloc(sizeof(double) * (m - 1));
+    double* del = (double*)malloc(sizeof(double) * (m - 1));
+    for (int k = 0; k < m - 1; ++k) {
+        h[k] = xs[k + 1] - xs[k];
+        del[k] = (ys[k + 1] - ys[k]) / h[k];
+    }
+    for (int k = 1; k < m - 1; ++k) {
+        if (del[k - 1] == 0.0 || del[k] == 0.0 || (del[k - 1] > 0.0) != (del[k] > 0.0)) {
+            s[k] = 0.0;
+        } else {
+            double w1 = 2.0 * h[k] + h[k - 1];
+            double w2 = h[k] + 2.0 * h[k - 1];
+            s[k] = (w1 + w2) / (w1 / del[k - 1] + w2 / del[k]);
+        }
+    }
+    /* end slopes: non-centred three-point formula, then shape preservation */
+    for (int end = 0; end < 2; ++end) {
+        double h0, h1, d0, d1;
+        if (end == 0) {
+            h0 = h[0]; h1 = h[1]; d0 = del[0]; d1 = del[1];
+        } else {
+            h0 = h[m - 2]; h1 = h[m - 3]; d0 = del[m - 2]; d1 = del[m - 3];
+        }
+        double sl = ((2.0 * h0 + h1) * d0 - h0 * d1) / (h0 + h1);
+        if ((sl > 0.0) != (d0 > 0.0) || sl == 0.0) {
+            sl = 0.0;
+        } else if ((d0 > 0.0) != (d1 > 0.0) && fabs(sl) > fabs(3.0 * d0)) {
+            sl = 3.0 * d0;
+        }
+        if (end == 0) s[0] = sl; else s[m - 1] = sl;
+    }
+    free(h);
+    free(del);
+}
+
+static double hermite_eval(int m, const double* xs, const double* ys, const double* s, double x)
+{
+    int k = 0;
+    if (x <= xs[0]) return ys[0];
+    if (x >= xs[m - 1]) return ys[m - 1];
+    while (k < m - 2 && x >= xs[k + 1]) ++k;
+    double h = xs[k + 1] - xs[k];
+    double u = (x - xs[k]) / h;
+    double u2 = u * u, u3 = u2 * u;
+    double h00 = 2.0 * u3 - 3.0 * u2 + 1.0;
+    double h10 = u3 - 2.0 * u2 + u;
+    double h01 = -2.0 * u3 + 3.0 * u2;
+    double h11 = u3 - u2;
+    return h00 * ys[k] + h10 * h * s[k] + h01 * ys[k + 1] + h11 * h * s[k + 1];
+}
+
+/* Exported so the interpolant can be pinned against a library PCHIP. */
+void orc_pchip_eval(int m, const double* xs, const double* ys, int q, const double* xq,
+                    double* yq)
+{
+    double* s = (double*)malloc(sizeof(double) * m);
+    pchip_slopes(m, xs, ys, s);
+    for (int j = 0; j < q; ++j) yq[j] = hermite_eval(m, xs, ys, s, xq[j]);
+    free(s);
+}
+
+static void uniform_schedule(int Tn, double* b)
+{
+    for (int t = 0; t <= Tn; ++t) b[t] = (double)t / (double)Tn;
+    b[Tn] = 1.0;
+}
+
+/*
+ * D_hat_t = log g_hat_{t,2} - 2 log g_hat_{t,1} + log g_hat_{t,0} (clamped at 0:
+ * non-negative by Cauchy-Schwarz, a negative value is roundoff),
+ * Lambda_hat_t = sum_{s<=t} sqrt(D_hat_s), knots (Lambda_hat_t, beta_t) with
+ * repeated abscissae removed (first kept, the final knot always kept),
+ * beta*_{t'} = Lambda_hat^{-1}(Lambda_hat_T t'/T').
+ * interp: 0 PCHIP, 1 piecewise linear.
+ */
+int orc_optimise_schedule(int T, const double* beta, const double* log_g, int T_new, int interp,
+                          double* beta_new, double* Lambda)
+{
+    if (T < 1 || T_new < 1 || !beta || !log_g || !beta_new) return ORC_EINVAL;
+    double* Lam = (double*)malloc(sizeof(double) * (T + 1));
+    Lam[0] = 0.0;
+    int finite = 1;
+    for (int t = 1; t <= T; ++t) {
+        double D = log_g[2 * T + t - 1] - 2.0 * log_g[T + t - 1] + log_g[t - 1];
+        if (!isfinite(D)) finite = 0;
+        if (!(D > 0.0)) D = 0.0;
+        Lam[t] = Lam[t - 1] + sqrt(D);
+    }
+    if (Lambda) memcpy(Lambda, Lam, sizeof(double) * (T + 1));
+    if (!finite || !(Lam[T] > 0.0)) {
+        uniform_schedule(T_new, beta_new);
+        free(Lam);
+        return finite ? ORC_OK : ORC_ENONFINITE;
+    }
+    /* knots with strictly increasing abscissa */
+    double* kx = (double*)malloc(sizeof(double) * (T + 1));
+    double* ky = (double*)malloc(sizeof(double) * (T + 1));
+    int m = 0;
+    for (int t = 0; t <= T; ++t) {
+        if (m > 0 && !(Lam[t] > kx[m - 1])) {
+            if (t == T) { /* the final knot replaces an equal-abscissa one */
+                kx[m - 1] = Lam[t];
+                ky[m - 1] = beta[t];
+            }
+            continue;
+        }
+        kx[m] = Lam[t];
+        ky[m] = beta[t];
+        ++m;
+    }
+    for (int tp = 0; tp <= T_new; ++tp) {
+        double u = Lam[T] * (double)tp / (double)T_new;
+        double b;
+        if (interp == 1) {
+            int k = 0;
+            while (k < m - 2 && u >= kx[k + 1]) ++k;
+            double w = (u - kx[k]) / (kx[k + 1] - kx[k]);
+            if (w < 0.0) w = 0.0;
+            if (w > 1.0) w = 1.0;
+            b = ky[k] + w * (ky[k + 1] - ky[k]);
+        } else {
+            orc_pchip_eval(m, kx, ky, 1, &u, &b);
+        }
+        beta_new[tp] = b;
+    }
+    /* endpoints exact, strictly increasing interior */
+    beta_new[0] = 0.0;
+    beta_new[T_new] = 1.0;
+    for (int tp = 1; tp < T_new; ++tp) {
+        if (!(beta_new[tp] > beta_new[tp - 1])) beta_new[tp] = nextafter(beta_new[tp - 1], 2.0);
+    }
+    for (int tp = T_new - 1; tp >= 1; --tp) {
+        if (!(beta_new[tp] < beta_new[tp + 1])) beta_new[tp] = nextafter(beta_new[tp + 1], -1.0);
+    }
+    free(kx);
+    free(ky);
+    free(Lam);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 2: OASMC round loop with Budget and step-size adaptation.            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int budget;          /* 0 fixed, 1 double N, 2 double T (capped), 3 sqrt2 then double T */
+    int T1, Tmax;
+    int64_t Nmax;
+    int eps_adapt;       /* 0: eps_t = eps0; 1: adapt across rounds */
+    double eps0, eps_kappa, accept_target;
+    int interp;
+} orc_run_opts;
+
+/*
+ * Budget(N_k, T_k) -> (N_{k+1}, T_{k+1}).
+ *  1: N doubles, T fixed.  2: N fixed, T doubles up to Tmax.
+ *  3: the heuristic of the Budget section: N and T grow by sqrt 2 until N
+ *     would exceed Nmax, then N stays and T doubles (T capped at Tmax).
+ */
+static void budget_next(const orc_run_opts* R, int64_t N, int T, int64_t* Nn, int* Tn)
+{
+    *Nn = N;
+    *Tn = T;
+    if (R->budget == 1) {
+        *Nn = 2 * N;
+    } else if (R->budget == 2) {
+        *Tn = 2 * T;
+    } else if (R->budget == 3) {
+        int64_t Ng = (int64_t)llround((double)N * sqrt(2.0));
+        if (Ng <= R->Nmax) {
+            *Nn = Ng;
+            int Tg = (int)lround((double)T * sqrt(2.0));
+            *Tn = Tg > T ? Tg : T + 1;
+        } else {
+            *Tn = 2 * T;
+        }
+    }
+    if (R->Tmax > 0 && *Tn > R->Tmax) *Tn = R->Tmax;
+}
+
+/* Piecewise-linear interpolation on knots (bx[j], by[j]), j < m, constant beyond. */
+static double pl_interp(int m, const double* bx, const double* by, double x)
+{
+    if (x <= bx[0]) return by[0];
+    if (x >= bx[m - 1]) return by[m - 1];
+    int k = 0;
+    while (k < m - 2 && x >= bx[k + 1]) ++k;
+    double w = (x - bx[k]) / (bx[k + 1] - bx[k]);
+    return by[k] + w * (by[k + 1] - by[k]);
+}
+
+/*
+ * Step sizes: round 1 uses eps_t = eps0 (1 + beta_t kappa)^(-1/2), a scale
+ * that follows the posterior width along the path for Gaussian-like targets.
+ * Afterwards log eps^{(k+1)}(beta) = log eps^{(k)}(beta) + (acc^{(k)}(beta) - a*),
+ * as a piecewise-linear function of beta through the knots beta_t, t >= 1.
+ */
+static void eps_first(const orc_run_opts* R, int T, const double* beta, double* eps)
+{
+    for (int t = 1; t <= T; ++t)
+        eps[t - 1] = R->eps_adapt ? R->eps0 / sqrt(1.0 + beta[t] * R->eps_kappa) : R->eps0;
+}
+
+static void eps_next(const orc_run_opts* R, int T, const double* beta, const double* eps,
+                     const double* acc, int Tn, const double* beta_n, double* eps_n)
+{
+    if (!R->eps_adapt) {
+        for (int t = 0; t < Tn; ++t) eps_n[t] = R->eps0;
+        return;
+    }
+    double* kx = (double*)malloc(sizeof(double) * T);
+    double* ky = (double*)malloc(sizeof(double) * T);
+    for (int t = 1; t <= T; ++t) {
+        kx[t - 1] = beta[t];
+        ky[t - 1] = log(eps[t - 1]) + (acc[t - 1] - R->accept_target);
+    }
+    for (int t = 1; t <= Tn; ++t) eps_n[t - 1] = exp(pl_interp(T, kx, ky, beta_n[t]));
+    free(kx);
+    free(ky);
+}
+
+/*
+ * Rounds k = 1..rounds.  Round k uses counter field round_k = k.  Outputs are
+ * indexed by round with row capacity Tcap: beta[k][Tcap+1], Lambda[k][Tcap+1],
+ * log_g[k][3][Tcap], acc[k][Tcap], eps[k][Tcap].
+ */
+int orc_run(const orc_problem* P, const orc_opts* O, const orc_run_opts* R, int64_t N1,
+            int rounds, uint64_t seed, uint32_t problem_id, int Tcap, double* logZ,
+            int64_t* Ns, int* Ts, double* beta_out, double* Lambda_out, double* log_g_out,
+            double* acc_out, double* eps_out, int* nres_out)
+{
+    if (!P || !O || !R || N1 < 1 || rounds < 1 || R->T1 < 1 || R->T1 > Tcap) return ORC_EINVAL;
+    int64_t N = N1;
+    int T = R->T1;
+    double* beta = (double*)malloc(sizeof(double) * (Tcap + 1));
+    double* eps = (double*)malloc(sizeof(double) * Tcap);
+    double* lg = (double*)malloc(sizeof(double) * 3 * Tcap);
+    double* acc = (double*)malloc(sizeof(double) * Tcap);
+    uniform_schedule(T, beta);
+    eps_first(R, T, beta, eps);
+    int status = ORC_OK;
+    for (int k = 1; k <= rounds; ++k) {
+        double* lw = (double*)malloc(sizeof(double) * (size_t)N);
+        double* xo = (double*)malloc(sizeof(double) * (size_t)N * P->d);
+        double lz = 0.0;
+        int nres = 0;
+        status = orc_asmc(P, O, N, T, beta, eps, seed, (uint32_t)k, problem_id, lg, acc, &lz, lw,
+                          xo, &nres, NULL, NULL, NULL, NULL, NULL, 0);
+        free(lw);
+        free(xo);
+        if (status != ORC_OK && status != ORC_ENONFINITE) break;
+        int r = k - 1;
+        logZ[r] = lz;
+        Ns[r] = N;
+        Ts[r] = T;
+        nres_out[r] = nres;
+        memcpy(beta_out + (size_t)r * (Tcap + 1), beta, sizeof(double) * (T + 1));
+        memcpy(log_g_out + (size_t)r * 3 * Tcap, lg, sizeof(double) * 3 * T);
+        memcpy(acc_out + (size_t)r * Tcap, acc, sizeof(double) * T);
+        memcpy(eps_out + (size_t)r * Tcap, eps, sizeof(double) * T);
+        /* Lambda_hat of this round and the next round's schedule (Alg. 3) */
+        int64_t Nn;
+        int Tn;
+        budget_next(R, N, T, &Nn, &Tn);
+        if (Tn > Tcap) Tn = Tcap;
+        double* bn = (double*)malloc(sizeof(double) * (Tn + 1));
+        double* en = (double*)malloc(sizeof(double) * Tn);
+        int s2 = orc_optimise_schedule(T, beta, lg, Tn, R->interp, bn,
+                                       Lambda_out + (size_t)r * (Tcap + 1));
+        if (status == ORC_OK && s2 != ORC_OK) status = s2;
+        eps_next(R, T, beta, eps, acc, Tn, bn, en);
+        memcpy(beta, bn, sizeof(double) * (Tn + 1));
+        memcpy(eps, en, sizeof(double) * Tn);
+        free(bn);
+        free(en);
+        N = Nn;
+        T = Tn;
+        if (status != ORC_OK) break;
+    }
+    free(beta);
+    free(eps);
+    free(lg);
+    free(acc);
+    return status;
+}
+
+/* Evaluate ell and its gradient (exported for the gradient pins). */
+double orc_ell(const orc_problem* P, const double* x, double* grad_or_null)
+{
+    if (grad_or_null) grad_ell(P, x, grad_or_null);
+    return ell(P, x);
+}
