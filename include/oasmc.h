@@ -1,0 +1,232 @@
+/*
+ * oasmc.h -- C ABI of the MI355X (gfx950) implementation of Optimised Annealed
+ * SMC (OASMC) and Optimised Annealed Importance Sampling (OAIS), from
+ * "Optimised Annealed Sequential Monte Carlo Samplers" (Syed, Bouchard-Cote,
+ * Chern, Doucet, arXiv 2408.12057).
+ *
+ * Conventions for every entry point:
+ *   - Plain C types only.  "device" pointers are HIP device memory owned by the
+ *     caller; "host" pointers are host memory owned by the caller.  The library
+ *     never returns memory it allocated; the only memory it owns is the
+ *     workspace cached inside an oasmc_handle (released by
+ *     oasmc_handle_destroy).
+ *   - Every call returns an oasmc_status.  On failure nothing is thrown; a
+ *     thread-local message is available from oasmc_last_error().  Arguments are
+ *     validated before any device work (0 = beta_0 < ... < beta_T = 1, N >= 1,
+ *     supported (family, move, d), finite scalars).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is enqueued on it.  Calls that return host results
+ *     (oasmc_asmc, oasmc_run) synchronise that stream before returning.
+ *   - Annealing path: the linear (geometric) path
+ *       log gamma_beta(x) = log eta(x) + beta * ell(x),  ell = log gamma - log eta
+ *     (Sec. 2; the linear-path example of the appendix on forward/backward
+ *     kernels).  eta is the normalised Gaussian reference N(ref_mean, ref_sigma2 I).
+ *   - Randomness: Philox4x32-10 (Salmon et al., SC'11) keyed by the 64-bit seed,
+ *     counter (particle n, step t, round k | problem << 16,
+ *     stream << 24 | substep << 16 | block); normals by Box-Muller in binary64
+ *     from the words of each block.  Equal inputs give bitwise equal outputs.
+ */
+#ifndef OASMC_H
+#define OASMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OASMC_OK = 0,
+    OASMC_EINVAL = -1,       /* invalid argument (message says which) */
+    OASMC_EHIP = -2,         /* a HIP runtime call failed */
+    OASMC_ENOMEM = -3,       /* workspace allocation failed */
+    OASMC_ENONFINITE = -4,   /* log Z_hat or the moments are not finite */
+    OASMC_EUNSUPPORTED = -5  /* (family, move, d) combination not built */
+} oasmc_status;
+
+typedef enum { OASMC_GAUSS = 1, OASMC_LOGREG = 2, OASMC_GMM = 3 } oasmc_family;
+typedef enum { OASMC_RWMH = 1, OASMC_MALA = 2, OASMC_HMC = 3 } oasmc_move;
+
+/*
+ * Target gamma and reference eta.  All array pointers are DEVICE pointers to
+ * fp32 data, read-only during the call.
+ *   OASMC_GAUSS : gamma(x) = exp(-|x - mu|^2 / (2 sigma2))             mu[d]
+ *   OASMC_LOGREG: gamma(x) = eta(x) prod_i s(z_i)^y_i (1 - s(z_i))^(1-y_i),
+ *                 z_i = X[i,:] . x, s the logistic function;  X[n][d]
+ *                 row-major, y[n] in {0, 1}.  ell is the log-likelihood.
+ *   OASMC_GMM   : gamma(x) = (1/K) sum_k exp(-|x - means[k]|^2 / (2 exp(2 log_scales[k])))
+ *                 means[K][d], log_scales[K].
+ *   eta         : N(ref_mean, ref_sigma2 I); ref_mean may be NULL (zero mean).
+ */
+typedef struct {
+    int32_t family;
+    int32_t d;
+    const float* mu;
+    double sigma2;
+    const float* X;
+    const float* y;
+    int32_t n;
+    int32_t K;
+    const float* means;
+    const float* log_scales;
+    const float* ref_mean;
+    double ref_sigma2;
+} oasmc_problem;
+
+/*
+ * Forward kernel and resampling (Alg. 1).
+ *   move     : pi_beta-invariant MH kernel K_{beta_t} (one step per t).
+ *   leapfrog : HMC leapfrog steps per trajectory (>= 1).
+ *   resample : 0 = AIS (no intermediate resampling; particle and time loops
+ *              swapped, Sec. "Optimised AIS"), 1 = adaptive resampling.
+ *   trigger  : 0 = relative ESS of w_{t^-} < nu, 1 = CESS_t / N < nu
+ *              (CESS of the section connecting to online CESS optimisation).
+ *   nu       : threshold in (0, 1).
+ */
+typedef struct {
+    int32_t move;
+    int32_t leapfrog;
+    int32_t resample;
+    int32_t trigger;
+    double nu;
+} oasmc_kernel;
+
+/* Outputs of one ASMC pass.  Host arrays sized by the caller; NULL skips. */
+typedef struct {
+    double* log_g;        /* host [3*T]: log g_hat_{t,i} at [i*T + t-1]  (eq. CESS) */
+    double* accept;       /* host [T]: fraction of moves accepted at step t */
+    double* ess;          /* host [T] or NULL: relative ESS of w_{t^-} */
+    int32_t* resampled;   /* host [T] or NULL: 1 where step t resampled */
+    double logZ;          /* out: log Z_hat (estimator_Z) */
+    int32_t n_resample;   /* out: resampling events before T */
+    double* lw;           /* device [N] or NULL: final log-weights */
+    float* x;             /* device [N*d] or NULL: final states, row-major */
+    uint32_t* accept_bits;/* device [N * ceil(T/32)] or NULL: bit (t-1)%32 of word
+                             n*ceil(T/32) + (t-1)/32 is set when particle n's
+                             move at step t was accepted */
+} oasmc_round_out;
+
+typedef struct oasmc_handle_s oasmc_handle;
+
+/* Create a handle bound to HIP device `device`; owns the workspace. */
+int oasmc_handle_create(oasmc_handle** h, int device);
+/* Free the workspace and the handle.  NULL is accepted. */
+int oasmc_handle_destroy(oasmc_handle* h);
+/* Message for the last failure on the calling thread ("" if none). */
+const char* oasmc_last_error(void);
+
+/*
+ * Alg. 1, ASMC(N, B_T): one pass with schedule beta[0..T] (host, strictly
+ * increasing, beta[0] = 0, beta[T] = 1) and per-step step sizes eps[0..T-1]
+ * (host; RWMH proposal standard deviation, MALA Langevin step, HMC leapfrog
+ * step).  Particles start iid from eta, carry binary32 states and binary64
+ * log-weights; the incremental weight is evaluated at the pre-move state,
+ *   log g_t = (beta_t - beta_{t-1}) ell(X_{t-1}),
+ * then one MH move targeting pi_{beta_t} is applied.  round_k and problem_id
+ * only select random-number streams.
+ */
+int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel* kernel,
+               int64_t N, int32_t T, const double* beta, const double* eps, uint64_t seed,
+               uint32_t round_k, uint32_t problem_id, oasmc_round_out* out, void* stream);
+
+/*
+ * Alg. 3, OptimiseSchedule(T_new, B_T, g_hat) on the host:
+ *   D_hat_t = log g_hat_{t,2} - 2 log g_hat_{t,1} + log g_hat_{t,0} (negative
+ *   roundoff clamped to 0), Lambda_hat_t = sum_{s<=t} sqrt(D_hat_s), a monotone
+ *   interpolant of the knots (Lambda_hat_t, beta_t), beta*_{t'} =
+ *   Lambda_hat^{-1}(Lambda_hat_T t'/T_new).
+ * beta[T+1], log_g[3*T] (layout of oasmc_round_out.log_g) in; beta_new[T_new+1]
+ * and Lambda_hat[T+1] (may be NULL) out, all host.  interp: 0 = monotone
+ * piecewise cubic (Fritsch-Carlson), 1 = piecewise linear.  A zero or
+ * non-finite Lambda_hat_T yields the uniform schedule (status OASMC_ENONFINITE
+ * when non-finite).
+ */
+int oasmc_adapt_schedule(int32_t T, const double* beta, const double* log_g, int32_t T_new,
+                         int32_t interp, double* beta_new, double* Lambda_hat);
+
+/*
+ * Budget rule between rounds (Alg. 2, Sec. on increasing N and T):
+ *   OASMC_BUDGET_FIXED   : N, T unchanged
+ *   OASMC_BUDGET_DOUBLE_N: N doubles, T unchanged
+ *   OASMC_BUDGET_DOUBLE_T: N unchanged, T doubles
+ *   OASMC_BUDGET_SQRT2   : N and T grow by sqrt(2) until N would exceed
+ *                          N_max, then N stays and T doubles
+ * T is capped at T_max when T_max > 0.
+ */
+typedef enum {
+    OASMC_BUDGET_FIXED = 0,
+    OASMC_BUDGET_DOUBLE_N = 1,
+    OASMC_BUDGET_DOUBLE_T = 2,
+    OASMC_BUDGET_SQRT2 = 3
+} oasmc_budget;
+
+/*
+ * Round-loop options.  Round 1 uses the uniform schedule with T1 steps.
+ * Step sizes: eps_adapt = 0 keeps eps_t = eps0; eps_adapt = 1 starts from
+ * eps0 (1 + beta_t eps_kappa)^(-1/2) and between rounds moves
+ * log eps(beta) by (acceptance(beta) - accept_target), piecewise linear in beta
+ * (kernel adaptation across rounds, appendix on exploration kernels).
+ */
+typedef struct {
+    int32_t budget;
+    int32_t T1;
+    int32_t T_max;
+    int64_t N_max;
+    int32_t eps_adapt;
+    double eps0;
+    double eps_kappa;
+    double accept_target;
+    int32_t interp;
+} oasmc_run_opts;
+
+/* Per-round outputs (host arrays sized by the caller, row capacity Tcap). */
+typedef struct {
+    int32_t rounds;       /* in: number of rounds */
+    int32_t Tcap;         /* in: row capacity, >= every T_k */
+    double* logZ;         /* [rounds] */
+    int64_t* N;           /* [rounds] */
+    int32_t* T;           /* [rounds] */
+    double* beta;         /* [rounds][Tcap+1] */
+    double* Lambda_hat;   /* [rounds][Tcap+1] */
+    double* log_g;        /* [rounds][3][Tcap] */
+    double* accept;       /* [rounds][Tcap] */
+    double* eps;          /* [rounds][Tcap] */
+    int32_t* n_resample;  /* [rounds] */
+    int32_t rounds_done;  /* out: rounds whose outputs are valid (anytime property) */
+} oasmc_run_out;
+
+/*
+ * Alg. 2, OASMC: rounds k = 1..rounds of oasmc_asmc (random streams keyed by
+ * round k), each followed by Budget and OptimiseSchedule.  Each round's log
+ * Z_hat is unbiased and available at a predictable time; on error the rounds
+ * already completed stay valid (rounds_done).
+ */
+int oasmc_run(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel* kernel,
+              const oasmc_run_opts* opts, int64_t N1, uint64_t seed, uint32_t problem_id,
+              oasmc_run_out* out, void* stream);
+
+/*
+ * Systematic resampling (Alg. 1 resample step): given device log-weights
+ * lw[N] and a 32-bit uniform word u, writes device ancestors anc[N] with
+ * Pr[a = m] = W_m.  Weights are quantised to q_m = floor(exp(lw_m - max) 2^B),
+ * B = 62 - ceil(log2 N); the CDF is their exact integer prefix sum and point n
+ * is floor(S (2 (n 2^32 + u) + 1) / (N 2^33)); a_n = min{m : C_m > p_n}.
+ * Weights below 2^-B of the largest are never chosen.  OASMC_ENONFINITE if no
+ * weight is finite.
+ */
+int oasmc_resample(oasmc_handle* h, int64_t N, const double* lw, uint32_t u, int32_t* anc,
+                   void* stream);
+
+/*
+ * Raw Philox4x32-10 blocks on the device (used to check the generator):
+ * out[4*i .. 4*i+3] = Philox4x32-10(ctr[4*i .. 4*i+3], key = (seed lo, seed hi)).
+ * ctr and out are device arrays of 4*count uint32.
+ */
+int oasmc_philox(oasmc_handle* h, uint64_t seed, const uint32_t* ctr, uint32_t* out,
+                 int64_t count, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OASMC_H */

@@ -1,0 +1,290 @@
+"""Python binding of include/oasmc.h (ctypes).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboasmc.so")
+
+OK, EINVAL, EHIP, ENOMEM, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+GAUSS, LOGREG, GMM = 1, 2, 3
+MOVES = {"rwmh": 1, "mala": 2, "hmc": 3}
+TRIGGERS = {"ess": 0, "cess": 1}
+BUDGETS = {"fixed": 0, "double_n": 1, "double_t": 2, "sqrt2": 3}
+
+
+class OasmcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"oasmc status {code}: {msg}")
+        self.code = code
+
+
+class _Problem(C.Structure):
+    _fields_ = [
+        ("family", C.c_int32), ("d", C.c_int32), ("mu", C.c_void_p), ("sigma2", C.c_double),
+        ("X", C.c_void_p), ("y", C.c_void_p), ("n", C.c_int32), ("K", C.c_int32),
+        ("means", C.c_void_p), ("log_scales", C.c_void_p), ("ref_mean", C.c_void_p),
+        ("ref_sigma2", C.c_double),
+    ]
+
+
+class _Kernel(C.Structure):
+    _fields_ = [("move", C.c_int32), ("leapfrog", C.c_int32), ("resample", C.c_int32),
+                ("trigger", C.c_int32), ("nu", C.c_double)]
+
+
+class _RoundOut(C.Structure):
+    _fields_ = [
+        ("log_g", C.c_void_p), ("accept", C.c_void_p), ("ess", C.c_void_p),
+        ("resampled", C.c_void_p), ("logZ", C.c_double), ("n_resample", C.c_int32),
+        ("lw", C.c_void_p), ("x", C.c_void_p), ("accept_bits", C.c_void_p),
+    ]
+
+
+class _RunOpts(C.Structure):
+    _fields_ = [
+        ("budget", C.c_int32), ("T1", C.c_int32), ("T_max", C.c_int32), ("N_max", C.c_int64),
+        ("eps_adapt", C.c_int32), ("eps0", C.c_double), ("eps_kappa", C.c_double),
+        ("accept_target", C.c_double), ("interp", C.c_int32),
+    ]
+
+
+class _RunOut(C.Structure):
+    _fields_ = [
+        ("rounds", C.c_int32), ("Tcap", C.c_int32), ("logZ", C.c_void_p), ("N", C.c_void_p),
+        ("T", C.c_void_p), ("beta", C.c_void_p), ("Lambda_hat", C.c_void_p),
+        ("log_g", C.c_void_p), ("accept", C.c_void_p), ("eps", C.c_void_p),
+        ("n_resample", C.c_void_p), ("rounds_done", C.c_int32),
+    ]
+
+
+_lib = None
+_handles = {}
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise OasmcError(EINVAL, f"HIP library not built: {_LIB_PATH} is missing "
+                                 "(run paper_2408_12057_amd/build.py)")
+    L = C.CDLL(_LIB_PATH)
+    vp = C.c_void_p
+    L.oasmc_last_error.restype = C.c_char_p
+    L.oasmc_handle_create.argtypes = [C.POINTER(vp), C.c_int]
+    L.oasmc_handle_destroy.argtypes = [vp]
+    L.oasmc_asmc.argtypes = [vp, C.POINTER(_Problem), C.POINTER(_Kernel), C.c_int64, C.c_int32,
+                             vp, vp, C.c_uint64, C.c_uint32, C.c_uint32, C.POINTER(_RoundOut), vp]
+    L.oasmc_adapt_schedule.argtypes = [C.c_int32, vp, vp, C.c_int32, C.c_int32, vp, vp]
+    L.oasmc_run.argtypes = [vp, C.POINTER(_Problem), C.POINTER(_Kernel), C.POINTER(_RunOpts),
+                            C.c_int64, C.c_uint64, C.c_uint32, C.POINTER(_RunOut), vp]
+    L.oasmc_resample.argtypes = [vp, C.c_int64, vp, C.c_uint32, vp, vp]
+    L.oasmc_philox.argtypes = [vp, C.c_uint64, vp, vp, C.c_int64, vp]
+    for f in ("oasmc_handle_create", "oasmc_handle_destroy", "oasmc_asmc", "oasmc_adapt_schedule",
+              "oasmc_run", "oasmc_resample", "oasmc_philox"):
+        getattr(L, f).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(code: int):
+    if code != OK:
+        raise OasmcError(code, _load().oasmc_last_error().decode())
+
+
+def _handle(device: int):
+    if device not in _handles:
+        h = C.c_void_p()
+        _check(_load().oasmc_handle_create(C.byref(h), device))
+        _handles[device] = h
+    return _handles[device]
+
+
+def _stream(device: torch.device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev_f32(t, device) -> Optional[torch.Tensor]:
+    if t is None:
+        return None
+    return torch.as_tensor(t, dtype=torch.float32).to(device).contiguous()
+
+
+def _host_f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _np_ptr(a: Optional[np.ndarray]):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+@dataclass
+class Problem:
+    """Target gamma and Gaussian reference eta = N(ref_mean, ref_sigma2 I) on a device.
+
+    Build with ``Problem.gauss``, ``Problem.logreg`` or ``Problem.gmm``; array
+    fields are fp32 device tensors (kept alive by this object)."""
+    family: int
+    d: int
+    device: torch.device
+    mu: Optional[torch.Tensor] = None
+    sigma2: float = 1.0
+    X: Optional[torch.Tensor] = None
+    y: Optional[torch.Tensor] = None
+    means: Optional[torch.Tensor] = None
+    log_scales: Optional[torch.Tensor] = None
+    ref_mean: Optional[torch.Tensor] = None
+    ref_sigma2: float = 1.0
+
+    @staticmethod
+    def gauss(mu, sigma2: float, ref_sigma2: float = 1.0, ref_mean=None, device="cuda"):
+        dev = torch.device(device)
+        mu = _dev_f32(mu, dev)
+        return Problem(GAUSS, int(mu.numel()), dev, mu=mu, sigma2=float(sigma2),
+                       ref_mean=_dev_f32(ref_mean, dev), ref_sigma2=float(ref_sigma2))
+
+    @staticmethod
+    def logreg(X, y, ref_sigma2: float = 1.0, ref_mean=None, device="cuda"):
+        dev = torch.device(device)
+        X = _dev_f32(X, dev)
+        return Problem(LOGREG, int(X.shape[1]), dev, X=X, y=_dev_f32(y, dev),
+                       ref_mean=_dev_f32(ref_mean, dev), ref_sigma2=float(ref_sigma2))
+
+    @staticmethod
+    def gmm(means, log_scales, ref_sigma2: float = 1.0, ref_mean=None, device="cuda"):
+        dev = torch.device(device)
+        means = _dev_f32(means, dev)
+        return Problem(GMM, int(means.shape[1]), dev, means=means,
+                       log_scales=_dev_f32(log_scales, dev), ref_mean=_dev_f32(ref_mean, dev),
+                       ref_sigma2=float(ref_sigma2))
+
+    def c(self) -> _Problem:
+        def p(t):
+            return None if t is None else C.c_void_p(t.data_ptr())
+        return _Problem(self.family, self.d, p(self.mu), self.sigma2, p(self.X), p(self.y),
+                        0 if self.X is None else int(self.X.shape[0]),
+                        0 if self.means is None else int(self.means.shape[0]),
+                        p(self.means), p(self.log_scales), p(self.ref_mean), self.ref_sigma2)
+
+
+def _kernel(move, leapfrog, resample_, trigger, nu) -> _Kernel:
+    return _Kernel(MOVES[move] if isinstance(move, str) else int(move), int(leapfrog),
+                   int(bool(resample_)), TRIGGERS[trigger] if isinstance(trigger, str)
+                   else int(trigger), float(nu))
+
+
+def asmc(problem: Problem, N: int, beta, eps, seed: int, round_k: int = 1, problem_id: int = 0,
+         move="rwmh", leapfrog: int = 5, resample_: bool = False, trigger="ess",
+         nu: float = 0.5, return_state: bool = True, accept_bits: bool = False) -> dict:
+    """Alg. 1, ASMC(N, B_T): one pass with schedule ``beta`` (T+1) and step sizes ``eps`` (T)."""
+    dev = problem.device
+    beta = _host_f64(beta)
+    T = beta.shape[0] - 1
+    eps = _host_f64(np.broadcast_to(np.asarray(eps, dtype=np.float64), (T,)))
+    log_g = np.zeros(3 * T)
+    acc = np.zeros(T)
+    ess = np.zeros(T)
+    res = np.zeros(T, dtype=np.int32)
+    out = _RoundOut()
+    out.log_g, out.accept, out.ess, out.resampled = (_np_ptr(log_g), _np_ptr(acc), _np_ptr(ess),
+                                                     _np_ptr(res))
+    lw = x = bits = None
+    if return_state:
+        lw = torch.empty(N, dtype=torch.float64, device=dev)
+        x = torch.empty((N, problem.d), dtype=torch.float32, device=dev)
+        out.lw, out.x = lw.data_ptr(), x.data_ptr()
+    if accept_bits:
+        bits = torch.zeros((N, (T + 31) // 32), dtype=torch.int32, device=dev)
+        out.accept_bits = bits.data_ptr()
+    P = problem.c()
+    K = _kernel(move, leapfrog, resample_, trigger, nu)
+    code = _load().oasmc_asmc(_handle(dev.index or 0), C.byref(P), C.byref(K), int(N), int(T),
+                              _np_ptr(beta), _np_ptr(eps), int(seed) & (2 ** 64 - 1),
+                              int(round_k), int(problem_id), C.byref(out), _stream(dev))
+    _check(code)
+    r = dict(log_g=log_g.reshape(3, T), accept=acc, ess=ess, resampled=res, logZ=out.logZ,
+             n_resample=out.n_resample)
+    if return_state:
+        r["lw"], r["x"] = lw, x
+    if accept_bits:
+        r["accept_bits"] = bits
+    return r
+
+
+def adapt_schedule(beta, log_g, T_new: int, interp: int = 0):
+    """Alg. 3 (host): returns (beta_new[T_new+1], Lambda_hat[T+1])."""
+    beta = _host_f64(beta)
+    T = beta.shape[0] - 1
+    lg = _host_f64(np.asarray(log_g).reshape(3 * T))
+    bn = np.zeros(T_new + 1)
+    lam = np.zeros(T + 1)
+    code = _load().oasmc_adapt_schedule(T, _np_ptr(beta), _np_ptr(lg), int(T_new), int(interp),
+                                        _np_ptr(bn), _np_ptr(lam))
+    if code not in (OK, ENONFINITE):
+        _check(code)
+    return bn, lam
+
+
+def run(problem: Problem, N1: int, rounds: int, seed: int, problem_id: int = 0, move="rwmh",
+        leapfrog: int = 5, resample_: bool = False, trigger="ess", nu: float = 0.5,
+        budget="double_n", T1: int = 64, T_max: int = 0, N_max: int = 1 << 40,
+        eps0: float = 0.1, eps_adapt: bool = False, eps_kappa: float = 0.0,
+        accept_target: float = 0.574, interp: int = 0, Tcap: Optional[int] = None) -> dict:
+    """Alg. 2, OASMC: `rounds` rounds with Budget and OptimiseSchedule between them."""
+    dev = problem.device
+    b = BUDGETS[budget] if isinstance(budget, str) else int(budget)
+    if Tcap is None:
+        Tcap = T1 if b in (0, 1) else max(T1, T_max)
+    R = int(rounds)
+    logZ = np.full(R, np.nan)
+    Ns = np.zeros(R, dtype=np.int64)
+    Ts = np.zeros(R, dtype=np.int32)
+    beta = np.zeros((R, Tcap + 1))
+    lam = np.zeros((R, Tcap + 1))
+    lg = np.zeros((R, 3, Tcap))
+    acc = np.zeros((R, Tcap))
+    eps = np.zeros((R, Tcap))
+    nres = np.zeros(R, dtype=np.int32)
+    out = _RunOut(R, Tcap, _np_ptr(logZ), _np_ptr(Ns), _np_ptr(Ts), _np_ptr(beta), _np_ptr(lam),
+                  _np_ptr(lg), _np_ptr(acc), _np_ptr(eps), _np_ptr(nres), 0)
+    ro = _RunOpts(b, int(T1), int(T_max), int(N_max), int(bool(eps_adapt)), float(eps0),
+                  float(eps_kappa), float(accept_target), int(interp))
+    P = problem.c()
+    K = _kernel(move, leapfrog, resample_, trigger, nu)
+    code = _load().oasmc_run(_handle(dev.index or 0), C.byref(P), C.byref(K), C.byref(ro),
+                             int(N1), int(seed) & (2 ** 64 - 1), int(problem_id), C.byref(out),
+                             _stream(dev))
+    _check(code)
+    return dict(logZ=logZ, N=Ns, T=Ts, beta=beta, Lambda=lam, log_g=lg, acc=acc, eps=eps,
+                n_resample=nres, rounds_done=out.rounds_done)
+
+
+def resample(lw: torch.Tensor, u: int) -> torch.Tensor:
+    """Systematic resampling of device log-weights (float64) with 32-bit uniform word u."""
+    lw = lw.to(torch.float64).contiguous()
+    anc = torch.empty(lw.numel(), dtype=torch.int32, device=lw.device)
+    _check(_load().oasmc_resample(_handle(lw.device.index or 0), int(lw.numel()),
+                                  C.c_void_p(lw.data_ptr()), int(u) & 0xFFFFFFFF,
+                                  C.c_void_p(anc.data_ptr()), _stream(lw.device)))
+    return anc
+
+
+def philox(seed: int, ctr: torch.Tensor) -> torch.Tensor:
+    """Raw Philox4x32-10 blocks for device counters ctr [count, 4] (int32 bit patterns)."""
+    ctr = ctr.contiguous()
+    out = torch.empty_like(ctr)
+    _check(_load().oasmc_philox(_handle(ctr.device.index or 0), int(seed) & (2 ** 64 - 1),
+                                C.c_void_p(ctr.data_ptr()), C.c_void_p(out.data_ptr()),
+                                int(ctr.shape[0]), _stream(ctr.device)))
+    return out

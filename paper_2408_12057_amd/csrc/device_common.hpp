@@ -1,0 +1,110 @@
+// device_common.hpp -- device-side building blocks shared by the gfx950 kernels:
+// the Philox4x32-10 counter-based generator (Salmon et al., SC'11), binary64
+// Box-Muller normals, log-domain accumulation helpers and lane-group
+// reductions for 64-wide wavefronts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace oasmc {
+
+constexpr int kWave = 64;
+
+// Random-number streams (the fourth counter word carries stream, substep and
+// block): initial draw from eta, move normals, accept uniform, resampling.
+enum Stream : uint32_t { kStreamInit = 0, kStreamMove = 1, kStreamAccept = 2, kStreamResample = 3 };
+
+struct RngKey {
+    uint32_t k0, k1;  // seed low / high words
+    uint32_t c2;      // (round & 0xFFFF) | (problem << 16)
+};
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint4 draw_block(const RngKey& key, uint32_t n, uint32_t t,
+                                            uint32_t stream, uint32_t substep, uint32_t block)
+{
+    const uint4 ctr = make_uint4(n, t, key.c2, (stream << 24) | ((substep & 0xFFu) << 16) |
+                                                   (block & 0xFFFFu));
+    return philox4x32_10(ctr, key.k0, key.k1);
+}
+
+// Open-interval uniform from one 32-bit word: (w + 1/2) 2^-32, exact in binary64.
+__device__ __forceinline__ double word_uniform(uint32_t w)
+{
+    return ((double)w + 0.5) * 0x1p-32;
+}
+
+// Box-Muller in binary64: (wa, wb) -> (r cos 2 pi u_b, r sin 2 pi u_b), r = sqrt(-2 log u_a).
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& zc, double& zs)
+{
+    const double r = sqrt(-2.0 * log(word_uniform(wa)));
+    double s, c;
+    sincospi(2.0 * word_uniform(wb), &s, &c);
+    zc = r * c;
+    zs = r * s;
+}
+
+// Normals 4b .. 4b+3 of a (particle, step, stream) sequence.
+__device__ __forceinline__ void normals4(const RngKey& key, uint32_t n, uint32_t t,
+                                        uint32_t stream, uint32_t block, double z[4])
+{
+    const uint4 w = draw_block(key, n, t, stream, 0u, block);
+    box_muller(w.x, w.y, z[0], z[1]);
+    box_muller(w.z, w.w, z[2], z[3]);
+}
+
+// log(exp(a) + exp(b)) with -inf handled.
+__device__ __forceinline__ double log_add(double a, double b)
+{
+    const double m = fmax(a, b);
+    if (m == -INFINITY) return -INFINITY;
+    return m + log1p(exp(-fabs(a - b)));
+}
+
+// (max, scaled sum) pair merge for streaming log-sum-exp.
+__device__ __forceinline__ void lse_merge(double& m, double& s, double m2, double s2)
+{
+    const double M = fmax(m, m2);
+    if (M == -INFINITY) {
+        m = -INFINITY;
+        s = 0.0;
+        return;
+    }
+    s = s * exp(m - M) + s2 * exp(m2 - M);
+    m = M;
+}
+
+__device__ __forceinline__ double lse_value(double m, double s)
+{
+    return (s > 0.0) ? m + log(s) : -INFINITY;
+}
+
+// Sum over aligned groups of G lanes (G a power of two <= 64).  All lanes of a
+// group end with the same bits: the butterfly adds the same operands in the
+// same order on every lane of a pair.
+template <int G>
+__device__ __forceinline__ double group_sum(double v)
+{
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+}  // namespace oasmc

@@ -1,0 +1,99 @@
+// kernels.hpp -- interface between the host driver (oasmc_api.hip) and the
+// gfx950 kernels.  Plain structs of device pointers; no torch types.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.hpp"
+
+namespace oasmc {
+
+enum Family { kGauss = 1, kLogreg = 2, kGmm = 3 };
+enum Move { kRwmh = 1, kMala = 2, kHmc = 3 };
+
+constexpr int kMaxK = 16;      // mixture components handled by the VALU kernels
+constexpr int kMaxDValu = 256; // dimension handled by the VALU kernels
+constexpr int kMaxDLogreg = 64;
+
+// Device description of the target and reference (all pointers device, fp32).
+struct TargetDev {
+    int family, d, K, n;
+    const float* mu;
+    double sigma2;
+    const float* X;
+    const float* y;
+    const float* means;
+    const float* log_scales;
+    const float* ref_mean;  // may be null
+    double ref_sigma2;
+};
+
+// Arguments of one annealing pass.
+struct SweepArgs {
+    TargetDev tg;
+    int move, leapfrog;
+    int64_t N;
+    int T;
+    const double* beta;  // device [T+1]
+    const double* eps;   // device [T]
+    RngKey key;
+    // per-slot log-domain partials [S][T+1][4]: lse(lw), lse(lw+lg), lse(lw+2lg), count
+    double* part;
+    int64_t S;
+    int64_t ntiles;
+    double* lw_out;        // device [N] or null
+    float* x_out;          // device [N*d] or null
+    uint32_t* acc_bits;    // device [N*acc_words] or null
+    int acc_words;
+};
+
+// State of the particle system between steps of the resampling variant.
+struct AsmcState {
+    float* X;          // [N*d] current states
+    float* X2;         // [N*d] gather target
+    double* ell;       // [N]
+    double* ell2;      // [N]
+    double* lw;        // [N]
+    uint32_t* accw;    // [N] accept bits of the current 32-step word
+    double* tile_part; // [ntiles*8]
+    // scalars updated on the device
+    double* scal;      // [0] log Z_hat, [1] max(lw) at event, [2] flag, [3] u word
+    int* nres;         // [1]
+    double* log_g;     // [3*T] device
+    double* ess;       // [T]
+    int* resampled;    // [T]
+    double* accept;    // [T] accepted count
+    // resampler scratch
+    uint64_t* C;       // [N] block-local inclusive prefix of q
+    uint64_t* btot;    // [nblocks] inclusive block totals after the scan
+};
+
+// Validated launch configuration of a VALU sweep.
+struct ValuShape {
+    int lpp;  // lanes per particle
+    int dpl;  // dimensions per lane
+};
+
+bool valu_shape(int d, ValuShape* s);
+int64_t valu_tiles(int64_t N, const ValuShape& s);
+
+hipError_t launch_oais_valu(const SweepArgs& a, const ValuShape& s, int grid_waves,
+                            hipStream_t st);
+hipError_t launch_asmc_init(const SweepArgs& a, const ValuShape& s, const AsmcState& z,
+                            hipStream_t st);
+hipError_t launch_asmc_step(const SweepArgs& a, const ValuShape& s, const AsmcState& z, int t,
+                            int trigger, double nu, hipStream_t st);
+hipError_t launch_resample_step(const SweepArgs& a, const AsmcState& z, int t, hipStream_t st);
+hipError_t launch_merge_slots(const double* part, int64_t S, int T, int64_t N, double* log_g,
+                              double* acc, double* logZ, hipStream_t st);
+hipError_t launch_resample_plain(int64_t N, const double* lw, uint32_t u, int32_t* anc,
+                                 uint64_t* C, uint64_t* btot, double* scal, hipStream_t st);
+hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t count,
+                         hipStream_t st);
+
+int64_t resample_blocks(int64_t N);
+// Clears small device scalars with a kernel (no memset nodes, so callers may capture it).
+hipError_t launch_zero(double* a, int na, int* b, int nb, hipStream_t st);
+
+}  // namespace oasmc

@@ -1,0 +1,412 @@
+// sweep_common.hip -- the kernels shared by every annealing pass: the
+// slot-order merge of streamed moments, the per-step merge and trigger of the
+// resampling variant, the integer-CDF systematic resampler, raw Philox blocks,
+// and the host-side dispatch to the per-(family, move) sweep instantiations.
+#include "kernels.hpp"
+
+namespace oasmc {
+
+// Merge the S slot partials per entry in slot order (deterministic):
+// log_g[i*T + e] for e < T, accept fraction, and log Z_hat from entry T.
+__global__ void k_merge_slots(const double* __restrict__ part, int64_t S, int T, int64_t N,
+                              double* log_g, double* acc, double* logZ)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e > T) return;
+    double L[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double cnt = 0.0;
+    for (int64_t s = 0; s < S; ++s) {
+        const double* p = part + ((size_t)s * (T + 1) + e) * 4;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) L[i] = log_add(L[i], p[i]);
+        cnt += p[3];
+    }
+    if (e < T) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) log_g[(size_t)i * T + e] = L[i];
+        acc[e] = cnt / (double)N;
+    } else {
+        logZ[0] = L[0] - log((double)N);
+    }
+}
+
+// One block: merge the tile statistics of step t in tile order, record the
+// moments, ESS, the event decision and the log Z_hat increment.
+__global__ void __launch_bounds__(256) k_asmc_merge(SweepArgs a, AsmcState z, int t, int trigger,
+                                                    double nu)
+{
+    __shared__ double sh[256][6];
+    const int tid = threadIdx.x;
+    double L[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    double mx = -INFINITY, cnt = 0.0;
+    for (int64_t k = tid; k < a.ntiles; k += 256) {
+        const double* tp = z.tile_part + (size_t)k * 8;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) L[i] = log_add(L[i], tp[i]);
+        mx = fmax(mx, tp[4]);
+        cnt += tp[5];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sh[tid][i] = L[i];
+    sh[tid][4] = mx;
+    sh[tid][5] = cnt;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sh[tid][i] = log_add(sh[tid][i], sh[tid + st][i]);
+            sh[tid][4] = fmax(sh[tid][4], sh[tid + st][4]);
+            sh[tid][5] += sh[tid + st][5];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int T = a.T;
+        const double logN = log((double)a.N);
+        for (int i = 0; i < 3; ++i) z.log_g[(size_t)i * T + (t - 1)] = sh[0][i];
+        z.accept[t - 1] = sh[0][5];
+        const double rel_ess = exp(2.0 * sh[0][1] - sh[0][3] - logN);
+        const double rel_cess = exp(-(sh[0][2] - 2.0 * sh[0][1] + sh[0][0]));
+        z.ess[t - 1] = rel_ess;
+        const bool fire = (trigger == 0) ? (rel_ess < nu) : (rel_cess < nu);
+        z.resampled[t - 1] = 0;
+        z.scal[2] = 0.0;
+        if (t == T) {
+            z.scal[0] += sh[0][1] - logN;
+        } else if (fire) {
+            z.scal[0] += sh[0][1] - logN;
+            z.scal[1] = sh[0][4];
+            z.scal[2] = 1.0;
+            const uint4 w = draw_block(a.key, 0xFFFFFFFFu, (uint32_t)t, kStreamResample, 0u, 0u);
+            z.scal[3] = (double)w.x;
+            z.resampled[t - 1] = 1;
+            z.nres[0] += 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Systematic resampling with an exact integer CDF.
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = kScanThreads * kScanItems;
+
+int64_t resample_blocks(int64_t N) { return (N + kScanBlock - 1) / kScanBlock; }
+
+__device__ __forceinline__ int quant_bits(int64_t N)
+{
+    int lg = 0;
+    while (((int64_t)1 << lg) < N) ++lg;
+    return 62 - lg;
+}
+
+// q_m and the block-local inclusive prefix; block totals into btot.
+__global__ void __launch_bounds__(kScanThreads) k_rs_quant_scan(int64_t N, const double* lw,
+                                                                const double* scal, uint64_t* C,
+                                                                uint64_t* btot)
+{
+    if (scal[2] == 0.0) return;
+    __shared__ uint64_t sh[kScanThreads];
+    const double mx = scal[1];
+    const double scale = ldexp(1.0, quant_bits(N));
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    uint64_t q[kScanItems];
+    uint64_t run = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t m = base + k;
+        q[k] = 0;
+        if (m < N) {
+            const double v = lw[m];
+            if (v == v) q[k] = (uint64_t)floor(exp(v - mx) * scale);
+        }
+        run += q[k];
+        q[k] = run;
+    }
+    sh[threadIdx.x] = run;
+    __syncthreads();
+    // inclusive Hillis-Steele scan of the per-thread totals (integer: exact)
+    for (int o = 1; o < kScanThreads; o <<= 1) {
+        const uint64_t v = (threadIdx.x >= (unsigned)o) ? sh[threadIdx.x - o] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    const uint64_t before = (threadIdx.x > 0) ? sh[threadIdx.x - 1] : 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t m = base + k;
+        if (m < N) C[m] = before + q[k];
+    }
+    if (threadIdx.x == kScanThreads - 1) btot[blockIdx.x] = sh[threadIdx.x];
+}
+
+// Inclusive scan of the block totals (one block, sequential chunks).
+__global__ void __launch_bounds__(kScanThreads) k_rs_scan_blocks(int64_t nb, const double* scal,
+                                                                 uint64_t* btot)
+{
+    if (scal[2] == 0.0) return;
+    __shared__ uint64_t sh[kScanThreads];
+    uint64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+        const int64_t b = b0 + threadIdx.x;
+        sh[threadIdx.x] = (b < nb) ? btot[b] : 0;
+        __syncthreads();
+        for (int o = 1; o < kScanThreads; o <<= 1) {
+            const uint64_t v = (threadIdx.x >= (unsigned)o) ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (b < nb) btot[b] = sh[threadIdx.x] + carry;
+        __syncthreads();
+        carry += sh[kScanThreads - 1];
+        __syncthreads();
+    }
+}
+
+// floor(num_hi:num_lo / den) for a quotient below 2^64 (restoring division).
+__device__ __forceinline__ uint64_t div128_64(uint64_t hi, uint64_t lo, uint64_t den)
+{
+    uint64_t q = 0;
+    uint64_t rem = hi;  // hi < den is guaranteed by the caller
+    for (int b = 63; b >= 0; --b) {
+        const bool top = (rem >> 63) != 0;
+        rem = (rem << 1) | ((lo >> b) & 1u);
+        if (top || rem >= den) {
+            rem -= den;
+            q |= (uint64_t)1 << b;
+        }
+    }
+    return q;
+}
+
+// Ancestor of slot n: min{m : C_m > p_n}, p_n = floor(S (2(n 2^32 + u) + 1) / (N 2^33)).
+__device__ __forceinline__ int64_t find_ancestor(int64_t n, int64_t N, uint32_t u,
+                                                 const uint64_t* C, const uint64_t* btot,
+                                                 int64_t nb)
+{
+    const uint64_t S = btot[nb - 1];
+    const uint64_t mult = 2u * (((uint64_t)n << 32) | (uint64_t)u) + 1u;
+    const unsigned __int128 prod = (unsigned __int128)S * (unsigned __int128)mult;
+    const uint64_t den = (uint64_t)N << 33;
+    const uint64_t pn = div128_64((uint64_t)(prod >> 64), (uint64_t)prod, den);
+    // block: first b with btot[b] > pn
+    int64_t lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (btot[mid] > pn) hi = mid; else lo = mid + 1;
+    }
+    const uint64_t off = (lo > 0) ? btot[lo - 1] : 0;
+    int64_t a = lo * kScanBlock;
+    int64_t b = (lo + 1) * kScanBlock - 1;
+    if (b > N - 1) b = N - 1;
+    while (a < b) {
+        const int64_t mid = (a + b) >> 1;
+        if (C[mid] + off > pn) b = mid; else a = mid + 1;
+    }
+    return a;
+}
+
+__global__ void k_rs_gather(int64_t N, int d, AsmcState z, int64_t nb)
+{
+    if (z.scal[2] == 0.0) return;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
+    if (n >= N) return;
+    const uint32_t u = (uint32_t)z.scal[3];
+    const int64_t an = find_ancestor(n, N, u, z.C, z.btot, nb);
+    for (int i = threadIdx.x; i < d; i += blockDim.x) z.X2[(size_t)n * d + i] = z.X[(size_t)an * d + i];
+    if (threadIdx.x == 0) z.ell2[n] = z.ell[an];
+}
+
+__global__ void k_rs_commit(int64_t N, int d, AsmcState z)
+{
+    if (z.scal[2] == 0.0) return;
+    const int64_t total = N * (int64_t)d;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        z.X[i] = z.X2[i];
+        if (i < N) {
+            z.ell[i] = z.ell2[i];
+            z.lw[i] = 0.0;
+        }
+    }
+}
+
+__global__ void k_rs_ancestors(int64_t N, const double* scal, const uint64_t* C,
+                               const uint64_t* btot, int64_t nb, int32_t* anc)
+{
+    if (scal[2] == 0.0) return;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    anc[n] = (int32_t)find_ancestor(n, N, (uint32_t)scal[3], C, btot, nb);
+}
+
+// Max of lw, the flag and the word for the plain resampling entry point.
+__global__ void k_rs_prepare(int64_t N, const double* lw, uint32_t u, double* scal)
+{
+    __shared__ double sh[256];
+    double mx = -INFINITY;
+    for (int64_t m = threadIdx.x; m < N; m += 256) {
+        const double v = lw[m];
+        if (v > mx) mx = v;
+    }
+    sh[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double m = sh[0];
+        const bool ok = (m > -INFINITY) && (m < INFINITY);
+        scal[1] = m;
+        scal[2] = ok ? 1.0 : 0.0;
+        scal[3] = (double)u;
+    }
+}
+
+__global__ void k_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, uint32_t* out,
+                         int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const uint4 c = make_uint4(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]);
+    const uint4 o = philox4x32_10(c, k0, k1);
+    out[4 * i] = o.x;
+    out[4 * i + 1] = o.y;
+    out[4 * i + 2] = o.z;
+    out[4 * i + 3] = o.w;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side dispatch.
+// ---------------------------------------------------------------------------
+bool valu_shape(int d, ValuShape* s)
+{
+    if (d < 1 || d > kMaxDValu) return false;
+    if (d <= 24) {
+        s->lpp = 1;
+        s->dpl = ((d + 3) / 4) * 4;
+    } else if (d <= 32) {
+        s->lpp = 2; s->dpl = 16;
+    } else if (d <= 64) {
+        s->lpp = 4; s->dpl = 16;
+    } else if (d <= 128) {
+        s->lpp = 8; s->dpl = 16;
+    } else {
+        s->lpp = 16; s->dpl = 16;
+    }
+    return true;
+}
+
+int64_t valu_tiles(int64_t N, const ValuShape& s)
+{
+    const int64_t P = kWave / s.lpp;
+    return (N + P - 1) / P;
+}
+
+template <int FAM, int MOVE>
+hipError_t valu_dispatch(int what, const SweepArgs& a, const ValuShape& s, int gw,
+                         const AsmcState* z, int t, hipStream_t st);
+static hipError_t dispatch_all(int what, const SweepArgs& a, const ValuShape& s, int gw,
+                               const AsmcState* z, int t, hipStream_t st)
+{
+    const int fam = a.tg.family, mv = a.move;
+    if (fam == kGauss && mv == kRwmh) return valu_dispatch<kGauss, kRwmh>(what, a, s, gw, z, t, st);
+    if (fam == kGauss && mv == kMala) return valu_dispatch<kGauss, kMala>(what, a, s, gw, z, t, st);
+    if (fam == kGauss && mv == kHmc) return valu_dispatch<kGauss, kHmc>(what, a, s, gw, z, t, st);
+    if (fam == kGmm && mv == kRwmh) return valu_dispatch<kGmm, kRwmh>(what, a, s, gw, z, t, st);
+    if (fam == kGmm && mv == kMala) return valu_dispatch<kGmm, kMala>(what, a, s, gw, z, t, st);
+    if (fam == kGmm && mv == kHmc) return valu_dispatch<kGmm, kHmc>(what, a, s, gw, z, t, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_oais_valu(const SweepArgs& a, const ValuShape& s, int grid_waves, hipStream_t st)
+{
+    return dispatch_all(0, a, s, grid_waves, nullptr, 0, st);
+}
+
+hipError_t launch_asmc_init(const SweepArgs& a, const ValuShape& s, const AsmcState& z,
+                            hipStream_t st)
+{
+    return dispatch_all(1, a, s, 0, &z, 0, st);
+}
+
+hipError_t launch_asmc_step(const SweepArgs& a, const ValuShape& s, const AsmcState& z, int t,
+                            int trigger, double nu, hipStream_t st)
+{
+    hipError_t e = dispatch_all(2, a, s, 0, &z, t, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_asmc_merge, dim3(1), dim3(256), 0, st, a, z, t, trigger, nu);
+    return hipGetLastError();
+}
+
+hipError_t launch_resample_step(const SweepArgs& a, const AsmcState& z, int t, hipStream_t st)
+{
+    (void)t;
+    const int64_t N = a.N;
+    const int64_t nb = resample_blocks(N);
+    hipLaunchKernelGGL(k_rs_quant_scan, dim3((unsigned)nb), dim3(kScanThreads), 0, st, N,
+                       (const double*)z.lw, (const double*)z.scal, z.C, z.btot);
+    hipLaunchKernelGGL(k_rs_scan_blocks, dim3(1), dim3(kScanThreads), 0, st, nb,
+                       (const double*)z.scal, z.btot);
+    const int d = a.tg.d;
+    const int tx = d >= 32 ? 32 : (d >= 16 ? 16 : (d >= 8 ? 8 : 4));
+    const int ty = 256 / tx;
+    hipLaunchKernelGGL(k_rs_gather, dim3((unsigned)((N + ty - 1) / ty)), dim3(tx, ty), 0, st, N,
+                       d, z, nb);
+    const int64_t total = N * (int64_t)d;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_rs_commit, dim3((unsigned)blocks), dim3(256), 0, st, N, d, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_slots(const double* part, int64_t S, int T, int64_t N, double* log_g,
+                              double* acc, double* logZ, hipStream_t st)
+{
+    const int threads = 128;
+    const int blocks = (T + 1 + threads - 1) / threads;
+    hipLaunchKernelGGL(k_merge_slots, dim3(blocks), dim3(threads), 0, st, part, S, T, N, log_g,
+                       acc, logZ);
+    return hipGetLastError();
+}
+
+hipError_t launch_resample_plain(int64_t N, const double* lw, uint32_t u, int32_t* anc,
+                                 uint64_t* C, uint64_t* btot, double* scal, hipStream_t st)
+{
+    const int64_t nb = resample_blocks(N);
+    hipLaunchKernelGGL(k_rs_prepare, dim3(1), dim3(256), 0, st, N, lw, u, scal);
+    hipLaunchKernelGGL(k_rs_quant_scan, dim3((unsigned)nb), dim3(kScanThreads), 0, st, N, lw,
+                       (const double*)scal, C, btot);
+    hipLaunchKernelGGL(k_rs_scan_blocks, dim3(1), dim3(kScanThreads), 0, st, nb,
+                       (const double*)scal, btot);
+    hipLaunchKernelGGL(k_rs_ancestors, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N,
+                       (const double*)scal, (const uint64_t*)C, (const uint64_t*)btot, nb, anc);
+    return hipGetLastError();
+}
+
+__global__ void k_zero(double* a, int na, int* b, int nb)
+{
+    const int i = threadIdx.x;
+    if (i < na) a[i] = 0.0;
+    if (i < nb) b[i] = 0;
+}
+
+hipError_t launch_zero(double* a, int na, int* b, int nb, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, a, na, b, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t count,
+                         hipStream_t st)
+{
+    hipLaunchKernelGGL(k_philox, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+                       (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), ctr, out, count);
+    return hipGetLastError();
+}
+
+}  // namespace oasmc

@@ -1,0 +1,638 @@
+// valu_sweep.hpp -- annealing sweeps for the closed-form targets (isotropic
+// Gaussian, equal-weight Gaussian mixture) with RWMH, MALA and HMC moves.
+//
+// These paths are bound by plain VALU arithmetic (Philox rounds, binary64
+// Box-Muller, distance and gradient sums), so the design keeps each particle in
+// registers: a particle occupies LPP adjacent lanes, each holding DPL of its
+// coordinates (fp32 state, binary64 arithmetic).  Per-particle scalars (ell,
+// log w, log alpha) are reduced over the LPP lanes with a butterfly so every
+// lane of the group holds the same bits and takes the same MH decision.
+//
+// Two drivers share the particle code:
+//  * k_oais_valu -- the AIS case with the particle loop outside the time loop
+//    (Sec. "Optimised AIS"): a wave owns a tile of 64/LPP particles for all T
+//    steps; the moments g_hat_{t,i} (eq. CESS) are streamed into a fixed number
+//    of slots S of O(T) memory each, independent of N and of the grid shape.
+//  * k_asmc_step / k_asmc_merge / resampler -- the adaptive-resampling case
+//    (Alg. 1 with AR): one launch per step t, state in HBM, a one-block merge
+//    that evaluates the trigger on the device, and the integer-CDF systematic
+//    resampler (launched every step, does nothing unless the trigger fired).
+#pragma once
+#include "kernels.hpp"
+
+namespace oasmc {
+
+
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Precomputed reference/target scalars.
+struct Consts {
+    double half_inv_s2r;  // 1 / (2 ref_sigma2)
+    double inv_s2r;       // 1 / ref_sigma2
+    double cst_eta;       // (d/2) log(2 pi ref_sigma2)
+    double sref;          // sqrt(ref_sigma2)
+    double half_inv_s2;   // Gaussian target: 1/(2 sigma2)
+    double inv_s2;        // Gaussian target: 1/sigma2
+    double logK;
+};
+
+__device__ __forceinline__ Consts make_consts(const TargetDev& tg)
+{
+    Consts c;
+    c.inv_s2r = 1.0 / tg.ref_sigma2;
+    c.half_inv_s2r = 0.5 / tg.ref_sigma2;
+    c.cst_eta = 0.5 * tg.d * (1.8378770664093454835606594728112 + log(tg.ref_sigma2));
+    c.sref = sqrt(tg.ref_sigma2);
+    c.half_inv_s2 = 0.5 / tg.sigma2;
+    c.inv_s2 = 1.0 / tg.sigma2;
+    c.logK = log((double)(tg.K > 0 ? tg.K : 1));
+    return c;
+}
+
+// Target parameters staged in LDS: reference mean [d], then the Gaussian mean
+// [d] or the mixture means [K*d], then the mixture 1/(2 v_k), 1/v_k.
+struct ParView {
+    const float* m;      // ref mean
+    const float* mu;     // gaussian mean or mixture means
+    const double* hiv;   // mixture 1/(2 v_k)
+    const double* iv;    // mixture 1/v_k
+};
+
+__device__ __forceinline__ ParView stage_params(const TargetDev& tg, char* sh)
+{
+    const int d = tg.d;
+    const int nmu = (tg.family == kGmm) ? tg.K * d : d;
+    double* hv = reinterpret_cast<double*>(sh);
+    double* iv = hv + kMaxK;
+    float* m = reinterpret_cast<float*>(iv + kMaxK);
+    float* mu = m + d;
+    for (int i = threadIdx.x; i < d; i += blockDim.x) m[i] = tg.ref_mean ? tg.ref_mean[i] : 0.f;
+    const float* src = (tg.family == kGmm) ? tg.means : tg.mu;
+    for (int i = threadIdx.x; i < nmu; i += blockDim.x) mu[i] = src[i];
+    if (tg.family == kGmm)
+        for (int k = threadIdx.x; k < tg.K; k += blockDim.x) {
+            const double v = exp(2.0 * (double)tg.log_scales[k]);
+            hv[k] = 0.5 / v;
+            iv[k] = 1.0 / v;
+        }
+    __syncthreads();
+    return ParView{m, mu, hv, iv};
+}
+
+inline size_t params_bytes(const TargetDev& tg)
+{
+    const int nmu = (tg.family == kGmm) ? tg.K * tg.d : tg.d;
+    return 2 * kMaxK * sizeof(double) + (size_t)(tg.d + nmu) * sizeof(float);
+}
+
+// ---------------------------------------------------------------------------
+// Particle arithmetic for one lane group.
+// ---------------------------------------------------------------------------
+template <int FAM, int LPP, int DPL>
+struct Particle {
+    // ell(x) = log gamma(x) - log eta(x); with GRAD also its gradient on this
+    // lane's coordinates.  r = lane index inside the group.
+    template <bool GRAD>
+    static __device__ __forceinline__ double eval(const TargetDev& tg, const Consts& c,
+                                                  const ParView& pv, int r, const float (&x)[DPL],
+                                                  double (&g)[DPL])
+    {
+        const int d = tg.d;
+        const int i0 = r * DPL;
+        if constexpr (FAM == kGauss) {
+            double ssg = 0.0, sse = 0.0;
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) {
+                const int i = i0 + j;
+                if (i < d) {
+                    const double xv = (double)x[j];
+                    const double a = xv - (double)pv.mu[i];
+                    const double b = xv - (double)pv.m[i];
+                    ssg = fma(a, a, ssg);
+                    sse = fma(b, b, sse);
+                    if (GRAD) g[j] = -a * c.inv_s2 + b * c.inv_s2r;
+                }
+            }
+            const double part = -ssg * c.half_inv_s2 + sse * c.half_inv_s2r;
+            return group_sum<LPP>(part) + c.cst_eta;
+        } else {
+            // equal-weight mixture of unnormalised isotropic components, streamed
+            // over k with a running maximum (log-sum-exp and responsibilities)
+            double sse = 0.0;
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) {
+                const int i = i0 + j;
+                if (i < d) {
+                    const double b = (double)x[j] - (double)pv.m[i];
+                    sse = fma(b, b, sse);
+                    if (GRAD) g[j] = 0.0;
+                }
+            }
+            sse = group_sum<LPP>(sse);
+            double mx = -INFINITY, s = 0.0;
+#pragma unroll 1
+            for (int k = 0; k < tg.K; ++k) {
+                double sq = 0.0;
+                const float* mk = pv.mu + k * d;
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) {
+                    const int i = i0 + j;
+                    if (i < d) {
+                        const double a = (double)x[j] - (double)mk[i];
+                        sq = fma(a, a, sq);
+                    }
+                }
+                const double ek = -group_sum<LPP>(sq) * pv.hiv[k];
+                double wk;
+                if (ek > mx) {
+                    const double sc = exp(mx - ek);  // 0 on the first component
+                    s *= sc;
+                    if (GRAD) {
+#pragma unroll
+                        for (int j = 0; j < DPL; ++j) g[j] *= sc;
+                    }
+                    mx = ek;
+                    wk = 1.0;
+                } else {
+                    wk = exp(ek - mx);
+                }
+                s += wk;
+                if (GRAD) {
+                    const double f = wk * pv.iv[k];
+#pragma unroll
+                    for (int j = 0; j < DPL; ++j) {
+                        const int i = i0 + j;
+                        if (i < d) g[j] = fma(f, (double)mk[i] - (double)x[j], g[j]);
+                    }
+                }
+            }
+            const double lse = mx + log(s) - c.logK;
+            if (GRAD) {
+                const double inv_s = 1.0 / s;
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) {
+                    const int i = i0 + j;
+                    if (i < d) g[j] = g[j] * inv_s + ((double)x[j] - (double)pv.m[i]) * c.inv_s2r;
+                }
+            }
+            return lse + sse * c.half_inv_s2r + c.cst_eta;
+        }
+    }
+
+    // d normals of one (particle, step, stream) split over the group's lanes.
+    static __device__ __forceinline__ void normals(const RngKey& key, uint32_t n, uint32_t t,
+                                                   uint32_t stream, int r, int d, double (&z)[DPL])
+    {
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) z[j] = 0.0;
+        if constexpr (LPP == 1) {
+#pragma unroll
+            for (int b = 0; b < (DPL + 3) / 4; ++b) {
+                if (4 * b < d) {
+                    double q[4];
+                    normals4(key, n, t, stream, (uint32_t)b, q);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (4 * b + u < DPL) z[4 * b + u] = q[u];
+                }
+            }
+        } else {
+            static_assert(DPL % 4 == 0, "multi-lane particles need 4-aligned lane slices");
+#pragma unroll
+            for (int bb = 0; bb < DPL / 4; ++bb) {
+                const int b = r * (DPL / 4) + bb;
+                if (4 * b < d) {
+                    double q[4];
+                    normals4(key, n, t, stream, (uint32_t)b, q);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) z[4 * bb + u] = q[u];
+                }
+            }
+        }
+    }
+
+    // X_0 ~ eta.
+    static __device__ __forceinline__ double init(const TargetDev& tg, const Consts& c,
+                                                  const ParView& pv, const RngKey& key, uint32_t n,
+                                                  int r, float (&x)[DPL], double (&g)[DPL],
+                                                  bool grad)
+    {
+        double z[DPL];
+        normals(key, n, 0u, kStreamInit, r, tg.d, z);
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) {
+            const int i = r * DPL + j;
+            x[j] = (i < tg.d) ? (float)((double)pv.m[i] + c.sref * z[j]) : 0.f;
+            g[j] = 0.0;
+        }
+        return grad ? eval<true>(tg, c, pv, r, x, g) : eval<false>(tg, c, pv, r, x, g);
+    }
+
+    // One MH step targeting pi_beta.  Returns the accept decision (the same on
+    // every lane of the group).
+    template <int MOVE>
+    static __device__ __forceinline__ bool move(const TargetDev& tg, const Consts& c,
+                                                const ParView& pv, const RngKey& key, uint32_t n,
+                                                uint32_t t, int r, int L, double beta, double eps,
+                                                float (&x)[DPL], double& ell, double (&g)[DPL])
+    {
+        const int d = tg.d;
+        const int i0 = r * DPL;
+        double z[DPL];
+        normals(key, n, t, kStreamMove, r, d, z);
+        float xp[DPL];
+        double gp[DPL];
+        double ellp;
+        double log_alpha;
+        if constexpr (MOVE == kRwmh) {
+            double dle = 0.0;
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) {
+                xp[j] = x[j];
+                if (i0 + j < d) {
+                    xp[j] = (float)((double)x[j] + eps * z[j]);
+                    const double a = (double)x[j] - (double)pv.m[i0 + j];
+                    const double b = (double)xp[j] - (double)pv.m[i0 + j];
+                    dle += a * a - b * b;
+                }
+            }
+            ellp = eval<false>(tg, c, pv, r, xp, gp);
+            log_alpha = group_sum<LPP>(dle) * c.half_inv_s2r + beta * (ellp - ell);
+        } else if constexpr (MOVE == kMala) {
+            const double h = 0.5 * eps * eps;
+            double dle = 0.0, fwd = 0.0, bwd = 0.0;
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) {
+                xp[j] = x[j];
+                if (i0 + j < d) {
+                    const double xv = (double)x[j];
+                    const double ga = -(xv - (double)pv.m[i0 + j]) * c.inv_s2r + beta * g[j];
+                    xp[j] = (float)(xv + h * ga + eps * z[j]);
+                    const double rr = (double)xp[j] - xv - h * ga;
+                    fwd = fma(rr, rr, fwd);
+                }
+            }
+            ellp = eval<true>(tg, c, pv, r, xp, gp);
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) {
+                if (i0 + j < d) {
+                    const double xv = (double)x[j];
+                    const double xpv = (double)xp[j];
+                    const double gap = -(xpv - (double)pv.m[i0 + j]) * c.inv_s2r + beta * gp[j];
+                    const double rr = xv - xpv - h * gap;
+                    bwd = fma(rr, rr, bwd);
+                    const double a = xv - (double)pv.m[i0 + j];
+                    const double b = xpv - (double)pv.m[i0 + j];
+                    dle += a * a - b * b;
+                }
+            }
+            const double inv2e2 = 1.0 / (2.0 * eps * eps);
+            log_alpha = group_sum<LPP>(dle) * c.half_inv_s2r + beta * (ellp - ell) -
+                        group_sum<LPP>(bwd) * inv2e2 + group_sum<LPP>(fwd) * inv2e2;
+        } else {
+            // HMC: unit mass, L leapfrog steps; positions are stored (rounded) states.
+            double mom[DPL];
+            double kin0 = 0.0;
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) {
+                mom[j] = z[j];
+                xp[j] = x[j];
+                gp[j] = g[j];
+                if (i0 + j < d) kin0 += 0.5 * mom[j] * mom[j];
+            }
+            ellp = ell;
+            const double he = 0.5 * eps;
+            for (int l = 0; l < L; ++l) {
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) {
+                    if (i0 + j < d) {
+                        const double xv = (double)xp[j];
+                        mom[j] += he * (-(xv - (double)pv.m[i0 + j]) * c.inv_s2r + beta * gp[j]);
+                        xp[j] = (float)(xv + eps * mom[j]);
+                    }
+                }
+                ellp = eval<true>(tg, c, pv, r, xp, gp);
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) {
+                    if (i0 + j < d)
+                        mom[j] += he * (-((double)xp[j] - (double)pv.m[i0 + j]) * c.inv_s2r +
+                                        beta * gp[j]);
+                }
+            }
+            double kin1 = 0.0, dle = 0.0;
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) {
+                if (i0 + j < d) {
+                    kin1 += 0.5 * mom[j] * mom[j];
+                    const double a = (double)x[j] - (double)pv.m[i0 + j];
+                    const double b = (double)xp[j] - (double)pv.m[i0 + j];
+                    dle += a * a - b * b;
+                }
+            }
+            log_alpha = group_sum<LPP>(dle) * c.half_inv_s2r + beta * (ellp - ell) -
+                        group_sum<LPP>(kin1) + group_sum<LPP>(kin0);
+        }
+        const uint4 w = draw_block(key, n, t, kStreamAccept, 0u, 0u);
+        const bool acc = log(word_uniform(w.x)) < log_alpha;
+        if (acc) {
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) {
+                x[j] = xp[j];
+                if (MOVE != kRwmh) g[j] = gp[j];
+            }
+            ell = ellp;
+        }
+        return acc;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// OAIS: persistent tiles, streamed moments.
+// ---------------------------------------------------------------------------
+constexpr int kTC = 8;      // steps buffered before a transposed reduction
+constexpr int kWavesPerBlock = 4;
+
+template <int FAM, int MOVE, int LPP, int DPL>
+__global__ void __launch_bounds__(256) k_oais_valu(SweepArgs a)
+{
+    constexpr int P = kWave / LPP;
+    constexpr int PP = (P + 7) / 8;  // particles per reduction lane
+    __shared__ double2 sh_rec[kWavesPerBlock][kTC][P];
+    __shared__ uint32_t sh_cnt[kWavesPerBlock][kTC];
+    extern __shared__ __align__(16) char sh_dyn[];
+    const ParView pv = stage_params(a.tg, sh_dyn);
+    const Consts c = make_consts(a.tg);
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int r = lane % LPP;
+    const int pl = lane / LPP;
+    const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+    const int64_t W = (int64_t)gridDim.x * kWavesPerBlock;
+    const int T = a.T;
+    const int d = a.tg.d;
+    const bool grad = (MOVE != kRwmh);
+
+    // Fold TC buffered steps of this tile into the slot's accumulators.
+    auto flush = [&](int64_t slot, bool first, int e0, int cnt) {
+        wave_sync();
+        const int tcl = lane % kTC;
+        const int part = lane / kTC;
+        double m[3] = {-INFINITY, -INFINITY, -INFINITY};
+        double s[3] = {0.0, 0.0, 0.0};
+        if (tcl < cnt) {
+#pragma unroll
+            for (int q = 0; q < PP; ++q) {
+                const int p = part * PP + q;
+                if (p < P) {
+                    const double2 v = sh_rec[wv][tcl][p];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) m[i] = fmax(m[i], v.x + (double)i * v.y);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < PP; ++q) {
+                const int p = part * PP + q;
+                if (p < P) {
+                    const double2 v = sh_rec[wv][tcl][p];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        if (m[i] > -INFINITY) s[i] += exp(v.x + (double)i * v.y - m[i]);
+                }
+            }
+        }
+#pragma unroll
+        for (int o = kTC; o < kWave; o <<= 1) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double m2 = __shfl_xor(m[i], o, kWave);
+                const double s2 = __shfl_xor(s[i], o, kWave);
+                lse_merge(m[i], s[i], m2, s2);
+            }
+        }
+        if (part == 0 && tcl < cnt) {
+            double* e = a.part + ((size_t)slot * (T + 1) + (size_t)(e0 + tcl)) * 4;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double L = lse_value(m[i], s[i]);
+                e[i] = first ? L : log_add(e[i], L);
+            }
+            e[3] = (first ? 0.0 : e[3]) + (double)sh_cnt[wv][tcl];
+        }
+        wave_sync();
+    };
+
+    for (int64_t slot = gw; slot < a.S; slot += W) {
+        for (int64_t tile = slot; tile < a.ntiles; tile += a.S) {
+            const bool first = (tile == slot);
+            const int64_t n64 = tile * P + pl;
+            const bool valid = n64 < a.N;
+            const uint32_t n = (uint32_t)n64;
+            float x[DPL];
+            double g[DPL];
+            double ell = Particle<FAM, LPP, DPL>::init(a.tg, c, pv, a.key, n, r, x, g, grad);
+            double lw = 0.0;
+            uint32_t accw = 0;
+            for (int t = 1; t <= T; ++t) {
+                const double lg = (a.beta[t] - a.beta[t - 1]) * ell;
+                const int tc = (t - 1) % kTC;
+                if (r == 0)
+                    sh_rec[wv][tc][pl] = valid ? make_double2(lw, lg) : make_double2(-INFINITY, 0.0);
+                lw += lg;
+                const bool acc = Particle<FAM, LPP, DPL>::template move<MOVE>(
+                    a.tg, c, pv, a.key, n, (uint32_t)t, r, a.leapfrog, a.beta[t], a.eps[t - 1], x,
+                    ell, g);
+                const uint64_t bal = __ballot(valid && acc && r == 0);
+                if (lane == 0) sh_cnt[wv][tc] = (uint32_t)__popcll(bal);
+                accw |= (acc ? 1u : 0u) << ((t - 1) & 31);
+                if (((t - 1) & 31) == 31 || t == T) {
+                    if (a.acc_bits && valid && r == 0)
+                        a.acc_bits[(size_t)n64 * a.acc_words + (t - 1) / 32] = accw;
+                    accw = 0;
+                }
+                if (tc == kTC - 1 || t == T) flush(slot, first, t - 1 - tc, tc + 1);
+            }
+            // final weights -> entry T (log-sum-exp of log w_T over the tile)
+            if (r == 0) sh_rec[wv][0][pl] = valid ? make_double2(lw, 0.0) : make_double2(-INFINITY, 0.0);
+            if (lane == 0) sh_cnt[wv][0] = 0u;
+            flush(slot, first, T, 1);
+            if (valid) {
+                if (a.lw_out && r == 0) a.lw_out[n64] = lw;
+                if (a.x_out) {
+#pragma unroll
+                    for (int j = 0; j < DPL; ++j) {
+                        const int i = r * DPL + j;
+                        if (i < d) a.x_out[(size_t)n64 * d + i] = x[j];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Adaptive-resampling variant: one launch per step.
+// ---------------------------------------------------------------------------
+template <int FAM, int MOVE, int LPP, int DPL>
+__global__ void __launch_bounds__(256) k_asmc_init(SweepArgs a, AsmcState z)
+{
+    constexpr int P = kWave / LPP;
+    extern __shared__ __align__(16) char sh_dyn[];
+    const ParView pv = stage_params(a.tg, sh_dyn);
+    const Consts c = make_consts(a.tg);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int r = lane % LPP, pl = lane / LPP;
+    const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t n64 = tile * P + pl;
+    if (tile >= a.ntiles || n64 >= a.N) return;
+    float x[DPL];
+    double g[DPL];
+    const double ell = Particle<FAM, LPP, DPL>::init(a.tg, c, pv, a.key, (uint32_t)n64, r, x, g,
+                                                     false);
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+        const int i = r * DPL + j;
+        if (i < a.tg.d) z.X[(size_t)n64 * a.tg.d + i] = x[j];
+    }
+    if (r == 0) {
+        z.ell[n64] = ell;
+        z.lw[n64] = 0.0;
+        z.accw[n64] = 0u;
+    }
+}
+
+template <int FAM, int MOVE, int LPP, int DPL>
+__global__ void __launch_bounds__(256) k_asmc_step(SweepArgs a, AsmcState z, int t)
+{
+    constexpr int P = kWave / LPP;
+    extern __shared__ __align__(16) char sh_dyn[];
+    const ParView pv = stage_params(a.tg, sh_dyn);
+    const Consts c = make_consts(a.tg);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int r = lane % LPP, pl = lane / LPP;
+    const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    if (tile >= a.ntiles) return;  // whole wave leaves together
+    const int64_t n64 = tile * P + pl;
+    const bool valid = n64 < a.N;
+    const int d = a.tg.d;
+    const int64_t nl = valid ? n64 : a.N - 1;  // invalid lanes work on a copy, write nothing
+    float x[DPL];
+    double g[DPL];
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+        const int i = r * DPL + j;
+        x[j] = (i < d) ? z.X[(size_t)nl * d + i] : 0.f;
+        g[j] = 0.0;
+    }
+    double ell;
+    if (MOVE != kRwmh)
+        ell = Particle<FAM, LPP, DPL>::template eval<true>(a.tg, c, pv, r, x, g);
+    else
+        ell = z.ell[nl];
+    double lw = z.lw[nl];
+    const double lg = (a.beta[t] - a.beta[t - 1]) * ell;
+    // tile statistics: lse of lw, lw+lg, lw+2lg, 2(lw+lg)
+    double m[4], s[4];
+    {
+        const double v[4] = {lw, lw + lg, lw + 2.0 * lg, 2.0 * (lw + lg)};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            m[i] = valid ? v[i] : -INFINITY;
+            s[i] = valid ? 1.0 : 0.0;
+        }
+    }
+#pragma unroll
+    for (int o = LPP; o < kWave; o <<= 1) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double m2 = __shfl_xor(m[i], o, kWave);
+            const double s2 = __shfl_xor(s[i], o, kWave);
+            lse_merge(m[i], s[i], m2, s2);
+        }
+    }
+    lw += lg;
+    const bool acc = Particle<FAM, LPP, DPL>::template move<MOVE>(
+        a.tg, c, pv, a.key, (uint32_t)nl, (uint32_t)t, r, a.leapfrog, a.beta[t], a.eps[t - 1], x,
+        ell, g);
+    const uint64_t bal = __ballot(valid && acc && r == 0);
+    if (lane == 0) {
+        double* tp = z.tile_part + (size_t)tile * 8;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) tp[i] = lse_value(m[i], s[i]);
+        tp[4] = m[1];  // max of log w_{t^-}
+        tp[5] = (double)__popcll(bal);
+    }
+    if (valid) {
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) {
+            const int i = r * DPL + j;
+            if (i < d) z.X[(size_t)n64 * d + i] = x[j];
+        }
+        if (r == 0) {
+            z.ell[n64] = ell;
+            z.lw[n64] = lw;
+            uint32_t w = z.accw[n64] | ((acc ? 1u : 0u) << ((t - 1) & 31));
+            if (((t - 1) & 31) == 31 || t == a.T) {
+                if (a.acc_bits) a.acc_bits[(size_t)n64 * a.acc_words + (t - 1) / 32] = w;
+                w = 0u;
+            }
+            z.accw[n64] = w;
+        }
+    }
+}
+
+template <int FAM, int MOVE, int LPP, int DPL>
+struct Launch {
+    static hipError_t oais(const SweepArgs& a, int grid_waves, hipStream_t st)
+    {
+        const int blocks = (grid_waves + kWavesPerBlock - 1) / kWavesPerBlock;
+        hipLaunchKernelGGL((k_oais_valu<FAM, MOVE, LPP, DPL>), dim3(blocks), dim3(256),
+                           params_bytes(a.tg), st, a);
+        return hipGetLastError();
+    }
+    static hipError_t init(const SweepArgs& a, const AsmcState& z, hipStream_t st)
+    {
+        const int64_t blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+        hipLaunchKernelGGL((k_asmc_init<FAM, MOVE, LPP, DPL>), dim3((unsigned)blocks), dim3(256),
+                           params_bytes(a.tg), st, a, z);
+        return hipGetLastError();
+    }
+    static hipError_t step(const SweepArgs& a, const AsmcState& z, int t, hipStream_t st)
+    {
+        const int64_t blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+        hipLaunchKernelGGL((k_asmc_step<FAM, MOVE, LPP, DPL>), dim3((unsigned)blocks), dim3(256),
+                           params_bytes(a.tg), st, a, z, t);
+        return hipGetLastError();
+    }
+};
+
+template <int FAM, int MOVE>
+hipError_t valu_dispatch(int what, const SweepArgs& a, const ValuShape& s, int gw,
+                           const AsmcState* z, int t, hipStream_t st)
+{
+#define OASMC_CASE(L, D)                                                     \
+    if (s.lpp == L && s.dpl == D) {                                          \
+        if (what == 0) return Launch<FAM, MOVE, L, D>::oais(a, gw, st);      \
+        if (what == 1) return Launch<FAM, MOVE, L, D>::init(a, *z, st);      \
+        return Launch<FAM, MOVE, L, D>::step(a, *z, t, st);                  \
+    }
+    OASMC_CASE(1, 4)
+    OASMC_CASE(1, 8)
+    OASMC_CASE(1, 12)
+    OASMC_CASE(1, 16)
+    OASMC_CASE(1, 20)
+    OASMC_CASE(1, 24)
+    OASMC_CASE(2, 16)
+    OASMC_CASE(4, 16)
+    OASMC_CASE(8, 16)
+    OASMC_CASE(16, 16)
+#undef OASMC_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace oasmc
