@@ -1,0 +1,185 @@
+"""Benchmark: particle-steps/s of the OAIS hot path on one MI355X.
+
+One step = one full Alg. 2 run (all rounds) of the Bayesian logistic
+regression workload: synthetic X in R^{10000 x 50} (fp32, iid N(0,1)),
+theta* ~ N(0, I), y ~ Bernoulli(sigmoid(X theta*)), prior eta = N(0, I_50),
+N = 16384 particles, T = 1, 2, 4, ..., 512, 1000 (11 rounds), MALA with
+adapted per-temperature step sizes, schedules rebuilt by Alg. 3 between rounds.
+Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line (rank 0).  --workload selects other synthetic workloads
+for extra measurements (not the headline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+# plain-ALU peak: 256 CUs x 64 lanes x 2.4 GHz lane-operations per second
+PEAK_VALU_LANE_OPS = 256 * 64 * 2.4e9
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def logreg_setup(oa, wl):
+    w = wl.logreg_n10000_d50()
+    prob = oa.Problem.logreg(w.params["X"], w.params["y"], w.ref_sigma2)
+    kw = dict(move="mala", budget="double_t", T1=1, T_max=1000, eps0=w.eps0, eps_adapt=True,
+              eps_kappa=w.params["X"].shape[0] / 4.0, accept_target=0.574, interp=0)
+    return w, prob, kw, 11
+
+
+def gauss_setup(oa, wl):
+    w = wl.gaussian_d10(N=1 << 22)
+    prob = oa.Problem.gauss(w.params["mu"], w.params["sigma2"], w.ref_sigma2)
+    kw = dict(move="rwmh", budget="fixed", T1=64, eps0=w.eps0)
+    return w, prob, kw, 4
+
+
+WORKLOADS = {"logreg": logreg_setup, "gauss": gauss_setup}
+
+
+def cpu_baseline(w, res, budget_s: float = 15.0) -> dict:
+    """The CPU oracle on a bounded sample of the same workload: a particle
+    subset of the last round (same schedule, step sizes and seed)."""
+    import oracle as orc
+
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    k = int(np.max(np.nonzero(res["T"])[0]))
+    T = int(res["T"][k])
+    beta = res["beta"][k][: T + 1]
+    eps = res["eps"][k][:T]
+    if w.family == "logreg":
+        P = orc.Problem(family=orc.FAM_LOGREG, d=w.d, X=w.params["X"], y=w.params["y"],
+                        ref_sigma2=w.ref_sigma2)
+        move = orc.MOVE_MALA
+    else:
+        P = orc.Problem(family=orc.FAM_GAUSS, d=w.d, mu=w.params["mu"], sigma2=w.params["sigma2"],
+                        ref_sigma2=w.ref_sigma2)
+        move = orc.MOVE_RWMH
+    opts = orc.Opts(move=move, state_f32=1, nthreads=cores)
+    # calibrate on a small sample, then size the timed sample to the budget
+    n0 = cores
+    t0 = time.perf_counter()
+    orc.asmc(P, opts, int(res["N"][k]), beta, eps, 1234, round_k=k + 1,
+             subset=np.arange(n0), traces=False)
+    dt0 = time.perf_counter() - t0
+    n1 = max(cores, int(n0 * budget_s / max(dt0, 1e-3)) // cores * cores)
+    n1 = min(n1, int(res["N"][k]))
+    t0 = time.perf_counter()
+    orc.asmc(P, opts, int(res["N"][k]), beta, eps, 1234, round_k=k + 1,
+             subset=np.arange(n1), traces=False)
+    dt = time.perf_counter() - t0
+    return {"value": n1 * T / dt, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n1} particles x T={T} (last round's schedule) of the same workload, "
+                      f"{dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="logreg", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=20240812)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB (3 times) and exit: "
+                         "the reference for scaling HBM byte counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
+              "multi-GPU path; run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2408_12057_amd as oa
+    from paper_2408_12057_amd import workloads as wl
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    if args.calibrate_copy_mib:
+        nbytes = args.calibrate_copy_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes, "repeats": 3}), flush=True)
+        return 0
+    w, prob, kw, rounds = WORKLOADS[args.workload](oa, wl)
+    log(f"workload {w.name}: N={w.N} d={w.d} rounds={rounds}")
+    res = None
+    for i in range(args.warmup):
+        res = oa.run(prob, w.N, rounds, seed=args.seed + i, **kw)
+    torch.cuda.synchronize()
+    oa.profile(True)
+    t0 = time.perf_counter()
+    steps_done = 0.0
+    for i in range(args.steps):
+        res = oa.run(prob, w.N, rounds, seed=args.seed + 1000 + i, **kw)
+        steps_done += float(np.sum(res["N"].astype(np.float64) * res["T"]))
+        log(f"step {i}: logZ per round {np.round(res['logZ'], 3).tolist()}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = oa.profile(False)
+    value = steps_done / elapsed
+    avg_ms = prof["kernel_ms"] / max(prof["launches"], 1)
+    if w.family == "logreg":
+        achieved = prof["flops"] / (prof["kernel_ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
+                "kernel": "k_oais_logreg", "avg_launch_ms": avg_ms,
+                "launches": prof["launches"]}
+    else:
+        rate = prof["particle_steps"] / (prof["kernel_ms"] * 1e-3)
+        roof = {"bound": "alu", "achieved": rate, "peak": None, "unit": "particle-steps/s",
+                "frac": None, "traffic": None, "kernel": "k_oais_valu",
+                "avg_launch_ms": avg_ms, "launches": prof["launches"]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample ...")
+        cpu = cpu_baseline(w, res)
+    line = {
+        "metric": "particle-steps/sec and fraction of roofline at matched log Z error",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 state / f32 MFMA contraction / f64 weights",
+        "data": "synthetic",
+        "config": {"workload": w.name, "N": w.N, "d": w.d, "rounds": rounds,
+                   "T_per_round": res["T"].tolist(),
+                   "n": int(w.params["X"].shape[0]) if w.family == "logreg" else None,
+                   "logZ_last_round": float(res["logZ"][-1]),
+                   "Lambda_hat_last_round": float(res["Lambda"][-1][res["T"][-1]]),
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

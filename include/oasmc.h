@@ -218,6 +218,28 @@ int oasmc_resample(oasmc_handle* h, int64_t N, const double* lw, uint32_t u, int
                    void* stream);
 
 /*
+ * The log-likelihood contraction of the logistic-regression family on its
+ * own: for N states theta[N][d] (device fp32, row-major) writes
+ * ell[n] = sum_i y_i z_ni - log(1 + exp(z_ni)), z = theta X^T (device binary64),
+ * and grad[n][:] = sum_i (y_i - s(z_ni)) X_i (device fp32), with the same FP32
+ * MFMA kernel the sweep uses.  Device-synchronous on `stream`.
+ */
+int oasmc_logreg_eval(oasmc_handle* h, const oasmc_problem* problem, int64_t N,
+                      const float* theta, double* ell, float* grad, void* stream);
+
+/*
+ * Live timing of the annealing-sweep kernels.  enable = 1 starts recording a
+ * HIP event pair around every sweep-kernel launch (on the launch stream) and
+ * clears the totals; enable = 0 stops.  Outputs (each may be NULL): summed
+ * kernel time in ms, number of launches, and the algorithmic work of those
+ * launches (particle-steps, and for the logistic-regression family the
+ * contraction flops 4 d n per particle and evaluation, evaluations = T + 1 per
+ * particle per pass).
+ */
+int oasmc_profile(oasmc_handle* h, int32_t enable, double* kernel_ms, int64_t* launches,
+                  double* particle_steps, double* flops);
+
+/*
  * Raw Philox4x32-10 blocks on the device (used to check the generator):
  * out[4*i .. 4*i+3] = Philox4x32-10(ctr[4*i .. 4*i+3], key = (seed lo, seed hi)).
  * ctr and out are device arrays of 4*count uint32.

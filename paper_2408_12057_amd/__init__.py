@@ -8,5 +8,6 @@ Importing the package does not load the library; the first call does, and it
 raises if the library is missing.
 """
 from .api import (  # noqa: F401
-    Problem, asmc, adapt_schedule, run, resample, philox, library_path, OasmcError,
+    Problem, asmc, adapt_schedule, run, resample, philox, logreg_eval, profile, library_path,
+    OasmcError,
 )

@@ -91,8 +91,12 @@ def _load():
                             C.c_int64, C.c_uint64, C.c_uint32, C.POINTER(_RunOut), vp]
     L.oasmc_resample.argtypes = [vp, C.c_int64, vp, C.c_uint32, vp, vp]
     L.oasmc_philox.argtypes = [vp, C.c_uint64, vp, vp, C.c_int64, vp]
+    L.oasmc_logreg_eval.argtypes = [vp, C.POINTER(_Problem), C.c_int64, vp, vp, vp, vp]
+    L.oasmc_profile.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for f in ("oasmc_handle_create", "oasmc_handle_destroy", "oasmc_asmc", "oasmc_adapt_schedule",
-              "oasmc_run", "oasmc_resample", "oasmc_philox"):
+              "oasmc_run", "oasmc_resample", "oasmc_philox", "oasmc_logreg_eval",
+              "oasmc_profile"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -288,3 +292,27 @@ def philox(seed: int, ctr: torch.Tensor) -> torch.Tensor:
                                 C.c_void_p(ctr.data_ptr()), C.c_void_p(out.data_ptr()),
                                 int(ctr.shape[0]), _stream(ctr.device)))
     return out
+
+
+def logreg_eval(problem: Problem, theta: torch.Tensor):
+    """Log-likelihood (float64) and its gradient (float32) at states theta [N, d]
+    with the sweep's FP32-MFMA contraction."""
+    theta = theta.to(device=problem.device, dtype=torch.float32).contiguous()
+    N = int(theta.shape[0])
+    ell = torch.empty(N, dtype=torch.float64, device=problem.device)
+    grad = torch.empty((N, problem.d), dtype=torch.float32, device=problem.device)
+    P = problem.c()
+    _check(_load().oasmc_logreg_eval(_handle(problem.device.index or 0), C.byref(P), N,
+                                     C.c_void_p(theta.data_ptr()), C.c_void_p(ell.data_ptr()),
+                                     C.c_void_p(grad.data_ptr()), _stream(problem.device)))
+    return ell, grad
+
+
+def profile(enable: bool, device: int = 0) -> dict:
+    """Start (enable=True, clears totals) or stop live timing of the sweep kernels;
+    returns the totals recorded so far."""
+    ms, n = C.c_double(), C.c_int64()
+    steps, flops = C.c_double(), C.c_double()
+    _check(_load().oasmc_profile(_handle(device), int(bool(enable)), C.byref(ms), C.byref(n),
+                                 C.byref(steps), C.byref(flops)))
+    return dict(kernel_ms=ms.value, launches=n.value, particle_steps=steps.value, flops=flops.value)

@@ -93,6 +93,16 @@ hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int6
                          hipStream_t st);
 
 int64_t resample_blocks(int64_t N);
+
+hipError_t launch_oais_logreg(const SweepArgs& a, int cus, void* ws, size_t ws_bytes,
+                              hipStream_t st);
+hipError_t launch_logreg_eval(const TargetDev& tg, const float* theta, int64_t N, double* ell,
+                              float* grad, void* ws, hipStream_t st);
+size_t logreg_workspace_bytes(const TargetDev& tg, int64_t N);
+size_t logreg_shared_bytes();
+// Packs X and y into the kernel's padded, column-permuted layout in ws.
+hipError_t logreg_prepare(const TargetDev& tg, void* ws, hipStream_t st);
+int64_t logreg_tiles(int64_t N);
 // Clears small device scalars with a kernel (no memset nodes, so callers may capture it).
 hipError_t launch_zero(double* a, int na, int* b, int nb, hipStream_t st);
 

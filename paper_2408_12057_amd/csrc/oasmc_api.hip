@@ -51,7 +51,13 @@ struct Buf {
 struct oasmc_handle_s {
     int device = 0;
     int cus = 256;
+    size_t lds_per_block = 0;
     std::vector<Buf> bufs;
+    // live kernel timing
+    bool prof = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double prof_ms = 0.0, prof_steps = 0.0, prof_flops = 0.0;
+    int64_t prof_launches = 0;
 
     // Returns a device buffer of at least `bytes` in slot `id` (grow-only).
     hipError_t get(int id, size_t bytes, void** out)
@@ -276,14 +282,6 @@ int adapt_schedule_impl(int T, const double* beta, const double* log_g, int Tn, 
 
 }  // namespace
 
-// Forward declaration of the logistic-regression (MFMA) sweep launcher.
-namespace oasmc {
-hipError_t launch_oais_logreg(const SweepArgs& a, int cus, void* ws, size_t ws_bytes,
-                              hipStream_t st);
-size_t logreg_workspace_bytes(const TargetDev& tg, int64_t N);
-int64_t logreg_tiles(int64_t N);
-}  // namespace oasmc
-
 extern "C" {
 
 const char* oasmc_last_error(void) { return g_err.c_str(); }
@@ -298,6 +296,7 @@ int oasmc_handle_create(oasmc_handle** h, int device)
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, device));
     oasmc_handle* p = new oasmc_handle();
+    p->lds_per_block = (size_t)prop.sharedMemPerBlock;
     p->device = device;
     p->cus = prop.multiProcessorCount;
     p->bufs.resize(B_COUNT);
@@ -310,6 +309,8 @@ int oasmc_handle_destroy(oasmc_handle* h)
 {
     if (!h) return OASMC_OK;
     hipSetDevice(h->device);
+    if (h->ev0) hipEventDestroy(h->ev0);
+    if (h->ev1) hipEventDestroy(h->ev1);
     for (auto& b : h->bufs)
         if (b.p) hipFree(b.p);
     delete h;
@@ -377,6 +378,9 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
         int64_t ntiles;
         ValuShape shape{};
         if (problem->family == OASMC_LOGREG) {
+            if (h->lds_per_block < logreg_shared_bytes())
+                return fail(OASMC_EUNSUPPORTED, "device offers %zu bytes of LDS per workgroup, need %zu",
+                            h->lds_per_block, logreg_shared_bytes());
             ntiles = logreg_tiles(N);
         } else {
             if (!valu_shape(problem->d, &shape))
@@ -389,20 +393,35 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
         a.part = part;
         a.S = S;
         a.ntiles = ntiles;
+        void* ws = nullptr;
+        size_t wb = 0;
         if (problem->family == OASMC_LOGREG) {
-            const size_t wb = logreg_workspace_bytes(a.tg, N);
-            void* ws;
+            wb = logreg_workspace_bytes(a.tg, N);
             HIP_TRY(h->get(B_LOGREG, wb, &ws));
+            HIP_TRY(logreg_prepare(a.tg, ws, st));
+        }
+        if (h->prof) HIP_TRY(hipEventRecord(h->ev0, st));
+        if (problem->family == OASMC_LOGREG) {
             HIP_TRY(launch_oais_logreg(a, h->cus, ws, wb, st));
         } else {
             const int grid_waves = (int)std::min<int64_t>(S, (int64_t)h->cus * 8);
             HIP_TRY(launch_oais_valu(a, shape, grid_waves, st));
         }
+        if (h->prof) HIP_TRY(hipEventRecord(h->ev1, st));
         HIP_TRY(launch_merge_slots(part, S, T, N, dlogg, dacc, dscal, st));
         HIP_TRY(hipMemcpyAsync(out->log_g, dlogg, sizeof(double) * 3 * T, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipMemcpyAsync(out->accept, dacc, sizeof(double) * T, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipMemcpyAsync(scal.data(), dscal, sizeof(double), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
+        if (h->prof) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+            h->prof_ms += ms;
+            h->prof_launches += 1;
+            h->prof_steps += (double)N * T;
+            if (problem->family == OASMC_LOGREG)
+                h->prof_flops += 4.0 * problem->d * (double)problem->n * (double)N * (T + 1);
+        }
         if (out->resampled) std::fill(out->resampled, out->resampled + T, 0);
         if (out->ess) {
             // relative ESS of w_{t^-} is not streamed by the AIS pass
@@ -456,6 +475,49 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
     out->logZ = scal[0];
     out->n_resample = nres;
     if (!std::isfinite(out->logZ)) return fail(OASMC_ENONFINITE, "log Z_hat is not finite");
+    g_err.clear();
+    return OASMC_OK;
+}
+
+int oasmc_logreg_eval(oasmc_handle* h, const oasmc_problem* problem, int64_t N,
+                      const float* theta, double* ell, float* grad, void* stream)
+{
+    if (!h || !problem || !theta || !ell || !grad) return fail(OASMC_EINVAL, "NULL argument");
+    if (problem->family != OASMC_LOGREG) return fail(OASMC_EINVAL, "problem is not logistic regression");
+    if (!problem->X || !problem->y || problem->n < 1) return fail(OASMC_EINVAL, "need X, y, n >= 1");
+    if (problem->d < 1 || problem->d > kMaxDLogreg)
+        return fail(OASMC_EUNSUPPORTED, "logistic regression supports 1 <= d <= %d", kMaxDLogreg);
+    if (N < 1 || N > ((int64_t)1 << 30)) return fail(OASMC_EINVAL, "N must lie in [1, 2^30]");
+    if (h->lds_per_block < logreg_shared_bytes())
+        return fail(OASMC_EUNSUPPORTED, "device offers %zu bytes of LDS per workgroup, need %zu",
+                    h->lds_per_block, logreg_shared_bytes());
+    HIP_TRY(hipSetDevice(h->device));
+    const TargetDev tg = target_dev(problem);
+    void* ws;
+    HIP_TRY(h->get(B_LOGREG, logreg_workspace_bytes(tg, N), &ws));
+    HIP_TRY(logreg_prepare(tg, ws, (hipStream_t)stream));
+    HIP_TRY(launch_logreg_eval(tg, theta, N, ell, grad, ws, (hipStream_t)stream));
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    g_err.clear();
+    return OASMC_OK;
+}
+
+int oasmc_profile(oasmc_handle* h, int32_t enable, double* kernel_ms, int64_t* launches,
+                  double* particle_steps, double* flops)
+{
+    if (!h) return fail(OASMC_EINVAL, "handle is NULL");
+    if (kernel_ms) *kernel_ms = h->prof_ms;
+    if (launches) *launches = h->prof_launches;
+    if (particle_steps) *particle_steps = h->prof_steps;
+    if (flops) *flops = h->prof_flops;
+    if (enable && !h->prof) {
+        HIP_TRY(hipSetDevice(h->device));
+        if (!h->ev0) HIP_TRY(hipEventCreate(&h->ev0));
+        if (!h->ev1) HIP_TRY(hipEventCreate(&h->ev1));
+        h->prof_ms = h->prof_steps = h->prof_flops = 0.0;
+        h->prof_launches = 0;
+    }
+    h->prof = enable != 0;
     g_err.clear();
     return OASMC_OK;
 }

@@ -1,0 +1,146 @@
+"""GPU parity of the logistic-regression path: the FP32-MFMA log-likelihood
+contraction against binary64 numpy, and the MALA sweep against the oracle.
+
+Tolerances come from the arithmetic.  The device forms z = X theta with fp32
+products accumulated in fp32 (a d-term dot product), the epilogue in fp32
+(exp, log, reciprocal), per-lane sums of 16 terms in fp32 and everything after
+that in binary64 (log-likelihood) or fp32 (gradient, 32-row MFMA chunks plus an
+8-way tree).  With u = 2^-24:
+  |dz_i|   <= gamma_d sum_k |x_ik theta_k|,            gamma_d = d u / (1 - d u)
+  |d ell|  <= sum_i [ |y_i - s(z_i)| |dz_i| + 4u (|term_i| + 1) ] + 16 u sum_i |term_i|
+  |d g_k|  <= sum_i |x_ik| (|dz_i|/4 + 4u) + (n/8 + 40) u sum_i |r_i x_ik|
+(s' <= 1/4; the last term is the fp32 accumulation over a wave's rows).
+An MH decision can differ from the oracle's only when the oracle's margin
+|log alpha - log u| is within a few of these errors; such particles are
+excused from trajectory comparison (first_flips)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+from parity_util import first_flips, unpack_bits
+from paper_2408_12057_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def oa():
+    import paper_2408_12057_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def _bounds(X, y, theta):
+    X64 = X.astype(np.float64)
+    th = theta.astype(np.float64)
+    n, d = X64.shape
+    z = th @ X64.T                                   # [N, n]
+    S = np.abs(th) @ np.abs(X64).T                   # sum_k |x_ik theta_k|
+    gd = d * U32 / (1 - d * U32)
+    dz = gd * S
+    sig = 1 / (1 + np.exp(-z))
+    term = y * z - np.logaddexp(0, z)
+    r = y - sig
+    b_ell = np.sum(np.abs(r) * dz + 4 * U32 * (np.abs(term) + 1), 1) + 16 * U32 * np.sum(np.abs(term), 1)
+    b_g = (dz / 4 + 4 * U32) @ np.abs(X64) + (n / 8 + 40) * U32 * (np.abs(r) @ np.abs(X64))
+    ell = np.sum(term, 1)
+    g = r @ X64
+    return ell, g, b_ell, b_g
+
+
+@pytest.mark.parametrize("n,d,N", [(1000, 50, 200), (777, 7, 64), (300, 64, 65), (5000, 33, 130),
+                                   (1, 1, 1)])
+def test_contraction_within_fp32_bound(oa, n, d, N):
+    X, y, th_star = wl.logreg_data(n, d, 1000 + n + d)
+    rng = np.random.default_rng(n)
+    theta = (th_star[None, :] + 0.3 * rng.normal(size=(N, d))).astype(np.float32)
+    prob = oa.Problem.logreg(X, y)
+    ell, grad = oa.logreg_eval(prob, torch.tensor(theta, device="cuda"))
+    ell = ell.cpu().numpy()
+    grad = grad.cpu().numpy().astype(np.float64)
+    e_ref, g_ref, b_ell, b_g = _bounds(X, y, theta)
+    assert np.all(np.abs(ell - e_ref) <= b_ell), np.max(np.abs(ell - e_ref) / b_ell)
+    assert np.all(np.abs(grad - g_ref) <= b_g), np.max(np.abs(grad - g_ref) / b_g)
+    # and the oracle's own evaluation agrees with numpy at binary64 level
+    P = orc.Problem(family=orc.FAM_LOGREG, d=d, X=X, y=y)
+    v, gg = orc.ell(P, theta[0])
+    assert abs(v - e_ref[0]) < 1e-9 * (1 + abs(v))
+    np.testing.assert_allclose(gg, g_ref[0], rtol=1e-9, atol=1e-9)
+
+
+def _round(oa, n, d, N, T, seed, subset=None, ref_mean=None):
+    X, y, _ = wl.logreg_data(n, d, 7 * n + d)
+    rng = np.random.default_rng(seed)
+    beta = np.concatenate([[0.0], np.sort(rng.random(T - 1)) ** 2, [1.0]])
+    eps = 0.5 * d ** (-1 / 6) / np.sqrt(1 + beta[1:] * n / 4)
+    prob = oa.Problem.logreg(X, y, ref_mean=ref_mean)
+    g = oa.asmc(prob, N, beta, eps, seed, round_k=2, move="mala", accept_bits=True)
+    P = orc.Problem(family=orc.FAM_LOGREG, d=d, X=X, y=y, ref_mean=ref_mean)
+    o = orc.asmc(P, orc.Opts(move=orc.MOVE_MALA, state_f32=1), N, beta, eps, seed, round_k=2,
+                 traces=True, subset=subset)
+    assert o["status"] == 0
+    return X, y, beta, g, o
+
+
+def _check(X, y, g, o, T, rows):
+    """rows: the particle indices the oracle ran (all, or a sample)."""
+    xg = g["x"].cpu().numpy()[rows]
+    acc_g = unpack_bits(g["accept_bits"].cpu().numpy(), T)[rows]
+    # decision tolerance: a few times the bound on |d log alpha| <= 2 beta max d ell
+    _, _, b_ell, _ = _bounds(X, y, np.concatenate([xg, o["x"].astype(np.float32)]))
+    tau = 4.0 * b_ell.max()
+    excused, bad = first_flips(acc_g, o["accept"], o["margin"], tau)
+    assert not bad, f"unexcused MH disagreements (particle, step, margin) tau={tau}: {bad[:5]}"
+    keep = np.ones(len(rows), dtype=bool)
+    for k, _, _ in excused:
+        keep[k] = False
+    assert keep.mean() > 0.8
+    np.testing.assert_allclose(xg[keep], o["x"][keep], rtol=1e-5, atol=1e-5)
+    lwg = g["lw"].cpu().numpy()[rows]
+    # log w_T = sum_t Delta beta_t ell(x_{t-1}): within the ell bound
+    np.testing.assert_allclose(lwg[keep], o["lw"][keep], rtol=0, atol=2 * b_ell.max())
+    return excused, tau
+
+
+@pytest.mark.parametrize("n,d,N,T", [(777, 50, 130, 6), (400, 7, 64, 9), (1500, 64, 70, 4),
+                                     (256, 25, 1, 3)])
+def test_mala_round_matches_oracle(oa, n, d, N, T):
+    X, y, beta, g, o = _round(oa, n, d, N, T, seed=n + d)
+    excused, tau = _check(X, y, g, o, T, np.arange(N))
+    if not excused:
+        np.testing.assert_allclose(g["accept"], o["acc"], atol=1e-15)
+        # log g_hat_{t,i} are log-sum-exps of weights within the ell bound
+        np.testing.assert_allclose(g["log_g"], o["log_g"], rtol=0, atol=2 * tau)
+        assert abs(g["logZ"] - o["logZ"]) < 2 * tau
+
+
+def test_mala_round_with_reference_mean(oa):
+    rm = np.linspace(-0.5, 0.5, 10).astype(np.float32)
+    X, y, beta, g, o = _round(oa, 600, 10, 100, 5, seed=3, ref_mean=rm)
+    _check(X, y, g, o, 5, np.arange(100))
+
+
+def test_full_size_sampled_particles(oa):
+    """The benchmark's launch configuration (N = 16384, n = 10000, d = 50) for
+    one T = 32 round: sampled particles (first/last of tiles, the last
+    particle) follow the oracle's trajectories; whole-population properties:
+    D_hat >= 0, finite moments, acceptance in (0, 1)."""
+    w = wl.logreg_n10000_d50()
+    T = 32
+    beta = np.linspace(0, 1, T + 1) ** 3
+    eps = w.eps0 / np.sqrt(1 + beta[1:] * 10000 / 4)
+    prob = oa.Problem.logreg(w.params["X"], w.params["y"])
+    g = oa.asmc(prob, w.N, beta, eps, 11, round_k=1, move="mala", accept_bits=True)
+    rows = np.array([0, 1, 63, 64, 5000, 8191, 12345, 16383])
+    P = orc.Problem(family=orc.FAM_LOGREG, d=50, X=w.params["X"], y=w.params["y"])
+    o = orc.asmc(P, orc.Opts(move=orc.MOVE_MALA, state_f32=1), w.N, beta, eps, 11, round_k=1,
+                 traces=True, subset=rows)
+    _check(w.params["X"], w.params["y"], g, o, T, rows)
+    lg = g["log_g"]
+    assert np.all(np.isfinite(lg))
+    assert np.all(lg[2] - 2 * lg[1] + lg[0] >= -1e-9)
+    assert np.all((g["accept"] > 0) & (g["accept"] <= 1))
+    assert np.isfinite(g["logZ"])
