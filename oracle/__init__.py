@@ -66,7 +66,7 @@ class _Opts(C.Structure):
     _fields_ = [
         ("move", C.c_int), ("leapfrog", C.c_int), ("resample", C.c_int),
         ("trigger", C.c_int), ("nu", C.c_double), ("state_f32", C.c_int),
-        ("nthreads", C.c_int),
+        ("nthreads", C.c_int), ("force_accept", C.c_void_p),
     ]
 
 
@@ -109,6 +109,12 @@ def _declare(L):
     L.orc_run.restype = C.c_int
     L.orc_ell.argtypes = [C.POINTER(_Problem), _dp, _dp]
     L.orc_ell.restype = C.c_double
+    L.orc_gmm_derivs.argtypes = [C.POINTER(_Problem), _dp, _dp, _dp, _dp]
+    L.orc_gmm_derivs.restype = None
+    L.orc_logZ_grad.argtypes = [C.POINTER(_Problem), C.POINTER(_Opts), C.c_int64, C.c_int, _dp,
+                                _dp, C.c_uint64, C.c_uint32, C.c_uint32, _dp,
+                                C.POINTER(C.c_double), C.POINTER(C.c_ubyte)]
+    L.orc_logZ_grad.restype = C.c_int
 
 
 def _f64(a) -> np.ndarray:
@@ -174,10 +180,15 @@ class Opts:
     nu: float = 0.5
     state_f32: int = 1
     nthreads: int = 0
+    force_accept: Optional[np.ndarray] = None  # uint8 [N, T]: replayed MH decisions (AIS)
 
     def c(self) -> _Opts:
+        fa = None
+        if self.force_accept is not None:
+            self._fa = np.ascontiguousarray(self.force_accept, dtype=np.uint8)
+            fa = self._fa.ctypes.data
         return _Opts(self.move, self.leapfrog, self.resample, self.trigger, self.nu,
-                     self.state_f32, self.nthreads)
+                     self.state_f32, self.nthreads, fa)
 
 
 @dataclass
@@ -310,3 +321,36 @@ def run(problem: Problem, opts: Opts, ropts: RunOpts, N1: int, rounds: int, seed
                        _ptr(acc), _ptr(eps), nres.ctypes.data_as(C.POINTER(C.c_int)))
     return dict(status=st, logZ=logZ, N=Ns, T=Ts, beta=beta, Lambda=lam, log_g=lg, acc=acc,
                 eps=eps, n_resample=nres)
+
+
+def gmm_derivs(problem: Problem, x):
+    """(H [d,d] hessian of ell, M [d, np] d grad ell / d theta, dl [np] d ell / d theta)."""
+    x = _f64(x)
+    d, K = problem.d, int(np.asarray(problem.means).shape[0])
+    npar = K * d + K
+    H = np.zeros((d, d))
+    M = np.zeros((d, npar))
+    dl = np.zeros(npar)
+    P = problem.c()
+    lib().orc_gmm_derivs(C.byref(P), _ptr(x), _ptr(H), _ptr(M), _ptr(dl))
+    return H, M, dl
+
+
+def logZ_grad(problem: Problem, opts: Opts, N: int, beta, eps, seed: int, round_k: int = 1,
+              problem_id: int = 0, want_accept: bool = False):
+    """Pathwise gradient of log Z_hat w.r.t. (means, log_scales) with fixed accept decisions."""
+    beta = _f64(beta)
+    T = beta.shape[0] - 1
+    eps = _f64(np.broadcast_to(np.asarray(eps, dtype=np.float64), (T,)))
+    K = int(np.asarray(problem.means).shape[0])
+    g = np.zeros(K * problem.d + K)
+    lz = C.c_double(0.0)
+    acc = np.zeros((N, T), dtype=np.uint8) if want_accept else None
+    P = problem.c()
+    O = opts.c()
+    st = lib().orc_logZ_grad(C.byref(P), C.byref(O), N, T, _ptr(beta), _ptr(eps), seed, round_k,
+                             problem_id, _ptr(g), C.byref(lz),
+                             None if acc is None else acc.ctypes.data_as(C.POINTER(C.c_ubyte)))
+    if st != 0:
+        raise RuntimeError(f"orc_logZ_grad status {st}")
+    return (lz.value, g, acc) if want_accept else (lz.value, g)

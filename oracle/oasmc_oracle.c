@@ -354,6 +354,7 @@ typedef struct {
     double nu;
     int state_f32;
     int nthreads;     /* 0: OpenMP default */
+    const unsigned char* force_accept; /* AIS only, [N*T] or NULL: replay these decisions */
 } orc_opts;
 
 typedef struct {
@@ -370,7 +371,7 @@ typedef struct {
  */
 static int mh_step(const orc_problem* P, const orc_opts* O, const rng_key* K, uint32_t n,
                    uint32_t t, double beta, double eps, particle* p, double* work,
-                   double* margin)
+                   double* margin, int forced)
 {
     int d = P->d;
     double* xi = work;          /* d */
@@ -450,6 +451,7 @@ static int mh_step(const orc_problem* P, const orc_opts* O, const rng_key* K, ui
     double log_u = log(draw_uniform(K, n, t, STREAM_ACCEPT, 0));
     if (margin) *margin = log_alpha - log_u;
     int accept = (log_u < log_alpha); /* NaN log_alpha rejects */
+    if (forced >= 0) accept = forced;   /* replayed decision (fixed masks) */
     if (accept) {
         for (int i = 0; i < d; ++i) p->x[i] = xp[i];
         p->ell = ell_p;
@@ -622,9 +624,10 @@ int orc_asmc(const orc_problem* P, const orc_opts* O, int64_t N, int T, const do
                     lw += lg;
                     LW[(size_t)j * (T + 1) + t] = lw;
                     double mg = 0.0;
+                    const int forced = O->force_accept ? O->force_accept[(size_t)j * T + (t - 1)] : -1;
                     A[(size_t)j * T + (t - 1)] =
                         (unsigned char)mh_step(P, O, &K, n, (uint32_t)t, beta[t], eps[t - 1], &p,
-                                               work, &mg);
+                                               work, &mg, forced);
                     if (margin) margin[(size_t)j * T + (t - 1)] = mg;
                 }
                 L[j] = p.ell;
@@ -690,7 +693,7 @@ int orc_asmc(const orc_problem* P, const orc_opts* O, int64_t N, int T, const do
                     particle p = {X + (size_t)j * d, L[j], G + (size_t)j * d};
                     double mg = 0.0;
                     int a = mh_step(P, O, &K, (uint32_t)j, (uint32_t)t, beta[t], eps[t - 1], &p,
-                                    work, &mg);
+                                    work, &mg, -1);
                     L[j] = p.ell;
                     A[(size_t)j * T + (t - 1)] = (unsigned char)a;
                     if (margin) margin[(size_t)j * T + (t - 1)] = mg;
@@ -1057,4 +1060,162 @@ double orc_ell(const orc_problem* P, const double* x, double* grad_or_null)
 {
     if (grad_or_null) grad_ell(P, x, grad_or_null);
     return ell(P, x);
+}
+
+
+/* ------------------------------------------------------------------------ */
+/* Derivatives of log Z_hat with respect to the mixture's parameters.        */
+/* ------------------------------------------------------------------------ */
+/*
+ * theta = (means[k][i] for k < K, i < d, then log_scales[k] for k < K).
+ * With a_k = (m_k - x)/v_k, v_k = exp(2 s_k), r = softmax_k(-|x - m_k|^2/(2 v_k)),
+ * g = sum_k r_k a_k, q_k = |x - m_k|^2 / v_k:
+ *   grad_x log gamma          = g
+ *   hess_x log gamma          = sum_k r_k (a_k a_k^T - I/v_k) - g g^T
+ *   d log gamma / d m_k       = -r_k a_k
+ *   d log gamma / d s_k       = r_k q_k
+ *   d g_i / d m_{k,l}         = r_k (delta_il / v_k - (a_k - g)_i a_{k,l})
+ *   d g_i / d s_k             = r_k q_k (a_k - g)_i - 2 r_k a_{k,i}
+ * eta does not depend on theta; hess_x ell = hess_x log gamma + I/ref_sigma2.
+ * Outputs: H[d*d] (hessian of ell), M[d*np] (d grad_x ell / d theta),
+ * dl[np] (d ell / d theta), np = K*d + K.
+ */
+void orc_gmm_derivs(const orc_problem* P, const double* x, double* H, double* M, double* dl)
+{
+    int d = P->d, K = P->K, np = K * d + K;
+    double* e = (double*)malloc(sizeof(double) * K);
+    double* r = (double*)malloc(sizeof(double) * K);
+    double* v = (double*)malloc(sizeof(double) * K);
+    double* q = (double*)malloc(sizeof(double) * K);
+    double* a = (double*)malloc(sizeof(double) * K * d);
+    double* g = (double*)calloc(d, sizeof(double));
+    double mx = -INFINITY;
+    for (int k = 0; k < K; ++k) {
+        v[k] = exp(2.0 * P->log_scales[k]);
+        double ss = 0.0;
+        for (int i = 0; i < d; ++i) {
+            double diff = x[i] - P->means[(size_t)k * d + i];
+            ss += diff * diff;
+            a[(size_t)k * d + i] = -diff / v[k];
+        }
+        q[k] = ss / v[k];
+        e[k] = -ss / (2.0 * v[k]);
+        if (e[k] > mx) mx = e[k];
+    }
+    double z = 0.0;
+    for (int k = 0; k < K; ++k) {
+        r[k] = exp(e[k] - mx);
+        z += r[k];
+    }
+    for (int k = 0; k < K; ++k) r[k] /= z;
+    for (int k = 0; k < K; ++k)
+        for (int i = 0; i < d; ++i) g[i] += r[k] * a[(size_t)k * d + i];
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double h = -g[i] * g[j];
+            for (int k = 0; k < K; ++k) {
+                h += r[k] * a[(size_t)k * d + i] * a[(size_t)k * d + j];
+                if (i == j) h -= r[k] / v[k];
+            }
+            if (i == j) h += 1.0 / P->ref_sigma2;
+            H[(size_t)i * d + j] = h;
+        }
+    for (int i = 0; i < d; ++i) {
+        for (int k = 0; k < K; ++k) {
+            for (int l = 0; l < d; ++l) {
+                double val = -r[k] * (a[(size_t)k * d + i] - g[i]) * a[(size_t)k * d + l];
+                if (i == l) val += r[k] / v[k];
+                M[(size_t)i * np + k * d + l] = val;
+            }
+            M[(size_t)i * np + K * d + k] =
+                r[k] * q[k] * (a[(size_t)k * d + i] - g[i]) - 2.0 * r[k] * a[(size_t)k * d + i];
+        }
+    }
+    for (int k = 0; k < K; ++k) {
+        for (int l = 0; l < d; ++l) dl[k * d + l] = -r[k] * a[(size_t)k * d + l];
+        dl[K * d + k] = r[k] * q[k];
+    }
+    free(e); free(r); free(v); free(q); free(a); free(g);
+}
+
+/*
+ * Pathwise gradient of log Z_hat (AIS, MALA, mixture target) with the accept
+ * decisions held fixed, by forward-mode (tangent) propagation of
+ * D x_t = dx_t/dtheta through every step:
+ *   log w_T = sum_t (beta_t - beta_{t-1}) ell(x_{t-1}),
+ *   x' = x + h (grad log eta(x) + beta grad ell(x)) + eps xi,  h = eps^2/2,
+ *   D x' = D x + h (-D x / ref_sigma2 + beta (H D x + M)),
+ *   x_t = x' and D x_t = D x' when accepted, else unchanged;
+ * grad log Z_hat = sum_n W_n D log w_T^n with W = softmax(log w_T).
+ * The rounding of stored states to binary32 is differentiated as the
+ * identity.  Decisions are the MH ones of this run unless force_accept is
+ * given.  Outputs grad[np], logZ, and optionally the decisions accept[N*T].
+ */
+int orc_logZ_grad(const orc_problem* P, const orc_opts* O, int64_t N, int T, const double* beta,
+                  const double* eps, uint64_t seed, uint32_t round_k, uint32_t problem_id,
+                  double* grad, double* logZ, unsigned char* accept)
+{
+    if (!P || !O || P->family != FAM_GMM || O->move != MOVE_MALA || O->resample) return ORC_EINVAL;
+    int d = P->d, np = P->K * d + P->K;
+    rng_key K = {seed, round_k, problem_id};
+    if (O->nthreads > 0) omp_set_num_threads(O->nthreads);
+    double* lw = (double*)malloc(sizeof(double) * (size_t)N);
+    double* dlw = (double*)calloc((size_t)N * np, sizeof(double));
+#pragma omp parallel
+    {
+        double* work = (double*)malloc(sizeof(double) * 6 * d);
+        double* x = (double*)malloc(sizeof(double) * d);
+        double* gx = (double*)malloc(sizeof(double) * d);
+        double* Dx = (double*)malloc(sizeof(double) * d * np);
+        double* Dxp = (double*)malloc(sizeof(double) * d * np);
+        double* H = (double*)malloc(sizeof(double) * d * d);
+        double* M = (double*)malloc(sizeof(double) * d * np);
+        double* dl = (double*)malloc(sizeof(double) * np);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t n = 0; n < N; ++n) {
+            particle p = {x, 0.0, gx};
+            init_particle(P, O, &K, (uint32_t)n, &p, work);
+            for (int c = 0; c < d * np; ++c) Dx[c] = 0.0;
+            double w = 0.0;
+            double* dw = dlw + (size_t)n * np;
+            for (int t = 1; t <= T; ++t) {
+                double db = beta[t] - beta[t - 1];
+                double h = 0.5 * eps[t - 1] * eps[t - 1];
+                orc_gmm_derivs(P, p.x, H, M, dl);
+                /* weight and its tangent at the pre-move state */
+                w += db * p.ell;
+                for (int c = 0; c < np; ++c) {
+                    double s = dl[c];
+                    for (int i = 0; i < d; ++i) s += p.gell[i] * Dx[(size_t)i * np + c];
+                    dw[c] += db * s;
+                }
+                /* tangent of the proposal from x_{t-1} */
+                for (int i = 0; i < d; ++i)
+                    for (int c = 0; c < np; ++c) {
+                        double hd = 0.0;
+                        for (int j = 0; j < d; ++j) hd += H[(size_t)i * d + j] * Dx[(size_t)j * np + c];
+                        Dxp[(size_t)i * np + c] = Dx[(size_t)i * np + c] +
+                            h * (-Dx[(size_t)i * np + c] / P->ref_sigma2 +
+                                 beta[t] * (hd + M[(size_t)i * np + c]));
+                    }
+                const int forced = O->force_accept ? O->force_accept[(size_t)n * T + (t - 1)] : -1;
+                int a = mh_step(P, O, &K, (uint32_t)n, (uint32_t)t, beta[t], eps[t - 1], &p, work,
+                                NULL, forced);
+                if (accept) accept[(size_t)n * T + (t - 1)] = (unsigned char)a;
+                if (a) memcpy(Dx, Dxp, sizeof(double) * d * np);
+            }
+            lw[n] = w;
+        }
+        free(work); free(x); free(gx); free(Dx); free(Dxp); free(H); free(M); free(dl);
+    }
+    double L = logsumexp(lw, N, 1);
+    *logZ = L - log((double)N);
+    for (int c = 0; c < np; ++c) grad[c] = 0.0;
+    for (int64_t n = 0; n < N; ++n) {
+        double Wn = exp(lw[n] - L);
+        for (int c = 0; c < np; ++c) grad[c] += Wn * dlw[(size_t)n * np + c];
+    }
+    free(lw);
+    free(dlw);
+    return isfinite(*logZ) ? ORC_OK : ORC_ENONFINITE;
 }
