@@ -206,6 +206,46 @@ int oasmc_run(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel*
               oasmc_run_out* out, void* stream);
 
 /*
+ * One problem of a batch: its target, kernel (resample must be 0), particle
+ * count, the number of steps T of its last round (round k of R uses
+ * max(1, T >> (R-1)) doubled each round and capped at T), step-size settings
+ * as in oasmc_run_opts, and its random streams (seed, problem_id).
+ */
+typedef struct {
+    oasmc_problem problem;
+    oasmc_kernel kernel;
+    int64_t N;
+    int32_t T;
+    int32_t eps_adapt;
+    double eps0;
+    double eps_kappa;
+    double accept_target;
+    uint64_t seed;
+    uint32_t problem_id;
+} oasmc_batch_problem;
+
+/* Outputs of a batch (host arrays [P][rounds]; Lambda_T and status may be NULL). */
+typedef struct {
+    double* logZ;        /* log Z_hat of every problem and round */
+    double* Lambda_T;    /* Lambda_hat_T (estimated global barrier) of every problem and round */
+    int32_t* status;     /* 1 where a round's moments were not finite */
+} oasmc_batch_out;
+
+/*
+ * Alg. 2 for P independent problems at once (AIS passes, N fixed, T doubling
+ * per round).  Problems are grouped by kernel class; each round launches one
+ * kernel per class over a work list of (problem, slot) items, then merges
+ * every problem's moments and runs Alg. 3 and the step-size update on the
+ * device, one workgroup per problem — no host round trip between rounds.
+ * use_graph = 1 captures all rounds as one hipGraph (kept in the handle and
+ * replayed while the batch is unchanged).  Each problem's results are bitwise
+ * those of oasmc_run on it alone (budget DOUBLE_T, T1 = max(1, T >> (R-1)),
+ * T_max = T, interp 0).  Synchronises `stream`.
+ */
+int oasmc_run_batch(oasmc_handle* h, const oasmc_batch_problem* problems, int32_t P,
+                    int32_t rounds, int32_t use_graph, oasmc_batch_out* out, void* stream);
+
+/*
  * Systematic resampling (Alg. 1 resample step): given device log-weights
  * lw[N] and a 32-bit uniform word u, writes device ancestors anc[N] with
  * Pr[a = m] = W_m.  Weights are quantised to q_m = floor(exp(lw_m - max) 2^B),
@@ -216,6 +256,24 @@ int oasmc_run(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel*
  */
 int oasmc_resample(oasmc_handle* h, int64_t N, const double* lw, uint32_t u, int32_t* anc,
                    void* stream);
+
+/*
+ * Gradient of log Z_hat with respect to the mixture target's parameters
+ * theta = (means[K][d], log_scales[K]) for one AIS pass with MALA moves
+ * (same arguments and random streams as oasmc_asmc), differentiating the
+ * whole T-step chain pathwise with every MH accept decision held at its
+ * forward value (binary32 rounding of the states differentiated as the
+ * identity).  The forward pass checkpoints the states every 16 steps; the
+ * reverse pass recomputes each segment from its checkpoint and applies the
+ * adjoint of every step (Hessian-vector and mixed products of the mixture
+ * log-density).  Outputs (host): *logZ, and grad[K*d + K] in binary64 in the
+ * order of theta.  Supported: OASMC_GMM, OASMC_MALA, resample = 0, d <= 32,
+ * K <= 8 (else OASMC_EUNSUPPORTED).  Synchronises `stream`.
+ */
+int oasmc_logZ_backward(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel* kernel,
+                        int64_t N, int32_t T, const double* beta, const double* eps,
+                        uint64_t seed, uint32_t round_k, uint32_t problem_id, double* logZ,
+                        double* grad, void* stream);
 
 /*
  * The log-likelihood contraction of the logistic-regression family on its

@@ -9,5 +9,5 @@ raises if the library is missing.
 """
 from .api import (  # noqa: F401
     Problem, asmc, adapt_schedule, run, resample, philox, logreg_eval, profile, library_path,
-    OasmcError,
+    OasmcError, logZ_backward, LogZ, BatchItem, run_batch,
 )

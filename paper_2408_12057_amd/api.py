@@ -55,6 +55,16 @@ class _RunOpts(C.Structure):
     ]
 
 
+class _BatchProblem(C.Structure):
+    _fields_ = [("problem", _Problem), ("kernel", _Kernel), ("N", C.c_int64), ("T", C.c_int32),
+                ("eps_adapt", C.c_int32), ("eps0", C.c_double), ("eps_kappa", C.c_double),
+                ("accept_target", C.c_double), ("seed", C.c_uint64), ("problem_id", C.c_uint32)]
+
+
+class _BatchOut(C.Structure):
+    _fields_ = [("logZ", C.c_void_p), ("Lambda_T", C.c_void_p), ("status", C.c_void_p)]
+
+
 class _RunOut(C.Structure):
     _fields_ = [
         ("rounds", C.c_int32), ("Tcap", C.c_int32), ("logZ", C.c_void_p), ("N", C.c_void_p),
@@ -91,12 +101,17 @@ def _load():
                             C.c_int64, C.c_uint64, C.c_uint32, C.POINTER(_RunOut), vp]
     L.oasmc_resample.argtypes = [vp, C.c_int64, vp, C.c_uint32, vp, vp]
     L.oasmc_philox.argtypes = [vp, C.c_uint64, vp, vp, C.c_int64, vp]
+    L.oasmc_logZ_backward.argtypes = [vp, C.POINTER(_Problem), C.POINTER(_Kernel), C.c_int64,
+                                      C.c_int32, vp, vp, C.c_uint64, C.c_uint32, C.c_uint32,
+                                      C.POINTER(C.c_double), vp, vp]
+    L.oasmc_run_batch.argtypes = [vp, C.POINTER(_BatchProblem), C.c_int32, C.c_int32, C.c_int32,
+                                  C.POINTER(_BatchOut), vp]
     L.oasmc_logreg_eval.argtypes = [vp, C.POINTER(_Problem), C.c_int64, vp, vp, vp, vp]
     L.oasmc_profile.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for f in ("oasmc_handle_create", "oasmc_handle_destroy", "oasmc_asmc", "oasmc_adapt_schedule",
               "oasmc_run", "oasmc_resample", "oasmc_philox", "oasmc_logreg_eval",
-              "oasmc_profile"):
+              "oasmc_profile", "oasmc_logZ_backward", "oasmc_run_batch"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -316,3 +331,89 @@ def profile(enable: bool, device: int = 0) -> dict:
     _check(_load().oasmc_profile(_handle(device), int(bool(enable)), C.byref(ms), C.byref(n),
                                  C.byref(steps), C.byref(flops)))
     return dict(kernel_ms=ms.value, launches=n.value, particle_steps=steps.value, flops=flops.value)
+
+
+def logZ_backward(problem: Problem, N: int, beta, eps, seed: int, round_k: int = 1,
+                  problem_id: int = 0):
+    """(log Z_hat, grad of log Z_hat w.r.t. (means.ravel(), log_scales)) for the mixture
+    target with MALA, accept decisions held fixed."""
+    dev = problem.device
+    beta = _host_f64(beta)
+    T = beta.shape[0] - 1
+    eps = _host_f64(np.broadcast_to(np.asarray(eps, dtype=np.float64), (T,)))
+    K = int(problem.means.shape[0])
+    grad = np.zeros(K * problem.d + K)
+    lz = C.c_double(0.0)
+    P = problem.c()
+    Kn = _kernel("mala", 1, False, "ess", 0.5)
+    _check(_load().oasmc_logZ_backward(_handle(dev.index or 0), C.byref(P), C.byref(Kn), int(N),
+                                       int(T), _np_ptr(beta), _np_ptr(eps),
+                                       int(seed) & (2 ** 64 - 1), int(round_k), int(problem_id),
+                                       C.byref(lz), _np_ptr(grad), _stream(dev)))
+    return lz.value, grad
+
+
+class LogZ(torch.autograd.Function):
+    """log Z_hat(means, log_scales) of the mixture target as a differentiable
+    torch function: forward and backward both run the HIP path (forward pass
+    with checkpoints, then the reverse pass).  Use ``LogZ.apply(means,
+    log_scales, ref_sigma2, N, beta, eps, seed)``."""
+
+    @staticmethod
+    def forward(ctx, means, log_scales, ref_sigma2, N, beta, eps, seed):
+        prob = Problem.gmm(means.detach(), log_scales.detach(), ref_sigma2, device=means.device)
+        lz, g = logZ_backward(prob, N, beta, eps, seed)
+        K, d = means.shape
+        ctx.save_for_backward(torch.tensor(g[:K * d].reshape(K, d), dtype=means.dtype,
+                                           device=means.device),
+                              torch.tensor(g[K * d:], dtype=log_scales.dtype,
+                                           device=log_scales.device))
+        return torch.tensor(lz, dtype=torch.float64, device=means.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        gm, gs = ctx.saved_tensors
+        go = grad_out.to(gm.dtype)
+        return go * gm, go * gs, None, None, None, None, None
+
+
+@dataclass
+class BatchItem:
+    """One problem of a batch (see oasmc_batch_problem)."""
+    problem: Problem
+    N: int
+    T: int
+    move: str = "rwmh"
+    leapfrog: int = 5
+    eps0: float = 0.1
+    eps_adapt: bool = False
+    eps_kappa: float = 0.0
+    accept_target: float = 0.574
+    seed: int = 0
+    problem_id: int = 0
+
+
+def run_batch(items, rounds: int, use_graph: bool = True) -> dict:
+    """Alg. 2 for many independent problems in one enqueue (optionally one hipGraph)."""
+    items = list(items)
+    P = len(items)
+    dev = items[0].problem.device
+    arr = (_BatchProblem * P)()
+    for i, it in enumerate(items):
+        arr[i].problem = it.problem.c()
+        arr[i].kernel = _kernel(it.move, it.leapfrog, False, "ess", 0.5)
+        arr[i].N = int(it.N)
+        arr[i].T = int(it.T)
+        arr[i].eps_adapt = int(bool(it.eps_adapt))
+        arr[i].eps0 = float(it.eps0)
+        arr[i].eps_kappa = float(it.eps_kappa)
+        arr[i].accept_target = float(it.accept_target)
+        arr[i].seed = int(it.seed) & (2 ** 64 - 1)
+        arr[i].problem_id = int(it.problem_id)
+    logZ = np.zeros((P, rounds))
+    lam = np.zeros((P, rounds))
+    status = np.zeros((P, rounds), dtype=np.int32)
+    out = _BatchOut(_np_ptr(logZ), _np_ptr(lam), _np_ptr(status))
+    _check(_load().oasmc_run_batch(_handle(dev.index or 0), arr, P, int(rounds), int(bool(use_graph)),
+                                   C.byref(out), _stream(dev)))
+    return dict(logZ=logZ, Lambda_T=lam, status=status)

@@ -1,0 +1,56 @@
+// adjoint.hip -- dispatch of the reverse pass (see adjoint.hpp) and the
+// fixed-order reduction of the per-wave gradient sums.
+#include "adjoint.hpp"
+
+namespace oasmc {
+
+bool adjoint_shape(int d, int K, ValuShape* s, int* kb)
+{
+    if (d < 1 || d > 32 || K < 1 || K > 8) return false;
+    if (d <= 24) {
+        s->lpp = 1;
+        s->dpl = ((d + 3) / 4) * 4;
+    } else {
+        s->lpp = 2;
+        s->dpl = 16;
+    }
+    *kb = (K <= 2) ? 2 : (K <= 4 ? 4 : 8);
+    return true;
+}
+
+hipError_t launch_adjoint(const AdjointArgs& A, const ValuShape& s, int kb, hipStream_t st)
+{
+#define OASMC_ADJ(L, D, KB_) \
+    if (s.lpp == L && s.dpl == D && kb == KB_) return launch_adjoint_t<L, D, KB_>(A, st);
+#define OASMC_ADJ_K(L, D) OASMC_ADJ(L, D, 2) OASMC_ADJ(L, D, 4) OASMC_ADJ(L, D, 8)
+    OASMC_ADJ_K(1, 4)
+    OASMC_ADJ_K(1, 8)
+    OASMC_ADJ_K(1, 12)
+    OASMC_ADJ_K(1, 16)
+    OASMC_ADJ_K(1, 20)
+    OASMC_ADJ_K(1, 24)
+    OASMC_ADJ_K(2, 16)
+#undef OASMC_ADJ_K
+#undef OASMC_ADJ
+    return hipErrorInvalidValue;
+}
+
+__global__ void k_adjoint_reduce(const double* __restrict__ partial, int64_t nwaves, int np,
+                                 double* grad)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= np) return;
+    double s = 0.0;
+    for (int64_t w = 0; w < nwaves; ++w) s += partial[(size_t)w * np + c];
+    grad[c] = s;
+}
+
+hipError_t launch_adjoint_reduce(const double* partial, int64_t nwaves, int np, double* grad,
+                                 hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adjoint_reduce, dim3((np + 127) / 128), dim3(128), 0, st, partial, nwaves,
+                       np, grad);
+    return hipGetLastError();
+}
+
+}  // namespace oasmc

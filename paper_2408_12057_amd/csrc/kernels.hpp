@@ -29,6 +29,16 @@ struct TargetDev {
     double ref_sigma2;
 };
 
+// Pointers to a problem's target parameters as the particle code reads them:
+// reference mean [d], Gaussian mean [d] or mixture means [K*d], and the
+// mixture's 1/(2 v_k), 1/v_k.
+struct ParView {
+    const float* m;
+    const float* mu;
+    const double* hiv;
+    const double* iv;
+};
+
 // Arguments of one annealing pass.
 struct SweepArgs {
     TargetDev tg;
@@ -46,6 +56,8 @@ struct SweepArgs {
     float* x_out;          // device [N*d] or null
     uint32_t* acc_bits;    // device [N*acc_words] or null
     int acc_words;
+    float* ckpt;           // device [N][ceil(T/ckpt_every)][d] states before steps 1, 1+every, ... or null
+    int ckpt_every;
 };
 
 // State of the particle system between steps of the resampling variant.
@@ -76,6 +88,20 @@ struct ValuShape {
 };
 
 bool valu_shape(int d, ValuShape* s);
+
+// A batch of problems of one (family, move, shape) class.
+struct ValuBatch {
+    const SweepArgs* args;   // device [nprob]
+    const ParView* views;    // device [nprob]
+    const int2* items;       // device [nitems]: (problem, slot)
+    int64_t nitems;
+};
+hipError_t launch_oais_valu_batch(int family, int move, const ValuShape& s, const ValuBatch& b,
+                                  int grid_waves, hipStream_t st);
+// Fills per-problem parameter buffers (reference mean, 1/(2 v_k), 1/v_k) for
+// batched launches: m[d], hiv[K], iv[K] at the given device addresses.
+hipError_t launch_batch_params(const TargetDev* tgs, float* const* m, double* const* hiv,
+                               double* const* iv, int nprob, hipStream_t st);
 int64_t valu_tiles(int64_t N, const ValuShape& s);
 
 hipError_t launch_oais_valu(const SweepArgs& a, const ValuShape& s, int grid_waves,
@@ -89,6 +115,41 @@ hipError_t launch_merge_slots(const double* part, int64_t S, int T, int64_t N, d
                               double* acc, double* logZ, hipStream_t st);
 hipError_t launch_resample_plain(int64_t N, const double* lw, uint32_t u, int32_t* anc,
                                  uint64_t* C, uint64_t* btot, double* scal, hipStream_t st);
+// Reverse pass of the pathwise gradient of log Z_hat (mixture target, MALA).
+struct AdjointArgs {
+    SweepArgs a;          // same target, schedule, keys; ckpt and acc_bits filled by the forward pass
+    const double* lw;     // [N] final log-weights of the forward pass
+    const double* scal;   // [0] = log Z_hat of the forward pass
+    float* seg;           // [N][ckpt_every][d] scratch for one recomputed segment
+    double* partial;      // [waves][np] per-wave weighted gradient sums
+    int64_t nwaves;
+};
+bool adjoint_shape(int d, int K, ValuShape* s, int* kb);
+hipError_t launch_adjoint(const AdjointArgs& A, const ValuShape& s, int kb, hipStream_t st);
+hipError_t launch_adjoint_reduce(const double* partial, int64_t nwaves, int np, double* grad,
+                                 hipStream_t st);
+
+// One problem's between-rounds work on the device (Alg. 2 round step).
+struct RoundDev {
+    int T, Tn;              // this round's and the next round's number of steps
+    int64_t N, S;           // particles, slots of the sweep
+    const double* part;     // [S][T+1][4] slot partials of the sweep
+    const double* beta;     // [T+1] this round's schedule
+    const double* eps;      // [T] this round's step sizes
+    double* log_g;          // [3T] out
+    double* acc;            // [T] out
+    double* logZ;           // [1] out
+    double* Lambda;         // [T+1] out
+    double* beta_next;      // [Tn+1] out
+    double* eps_next;       // [Tn] out
+    int* status;            // [1] out: 1 when the moments were not finite
+    double* scratch;        // [3(T+1)]
+    int interp, eps_adapt;
+    double eps0, accept_target;
+};
+hipError_t launch_round_merge(const RoundDev* rd, int nprob, hipStream_t st);
+hipError_t launch_round_schedule(const RoundDev* rd, int nprob, hipStream_t st);
+
 hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t count,
                          hipStream_t st);
 
@@ -96,6 +157,18 @@ int64_t resample_blocks(int64_t N);
 
 hipError_t launch_oais_logreg(const SweepArgs& a, int cus, void* ws, size_t ws_bytes,
                               hipStream_t st);
+// One logistic-regression problem as its sweep kernel sees it.
+struct LogregArgs {
+    SweepArgs a;
+    const float* Xp;   // packed [n_pad][64]
+    const float* yp;   // [n_pad], -1 on padding rows
+    int n_pad;
+};
+int logreg_kh(int d);      // column half-width class of d (-1 if unsupported)
+int logreg_npad(int n);    // padded row count
+hipError_t logreg_pack_into(const TargetDev& tg, float* Xp, float* yp, hipStream_t st);
+hipError_t launch_oais_logreg_batch(int kh, const LogregArgs* args, const int2* items,
+                                   int64_t nitems, int grid, hipStream_t st);
 hipError_t launch_logreg_eval(const TargetDev& tg, const float* theta, int64_t N, double* ell,
                               float* grad, void* ws, hipStream_t st);
 size_t logreg_workspace_bytes(const TargetDev& tg, int64_t N);

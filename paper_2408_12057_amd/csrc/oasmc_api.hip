@@ -53,6 +53,11 @@ struct oasmc_handle_s {
     int cus = 256;
     size_t lds_per_block = 0;
     std::vector<Buf> bufs;
+    // a captured multi-round graph and the descriptor bytes it was built from;
+    // capture runs on a stream of the handle (the null stream cannot capture)
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::vector<char> graph_key;
     // live kernel timing
     bool prof = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -85,7 +90,8 @@ namespace {
 
 enum BufId {
     B_BETA, B_EPS, B_PART, B_LOGG, B_ACC, B_SCAL, B_X, B_X2, B_ELL, B_ELL2, B_LW, B_ACCW,
-    B_TPART, B_NRES, B_ESS, B_RES, B_C, B_BTOT, B_LWO, B_XO, B_LOGREG, B_COUNT
+    B_TPART, B_NRES, B_ESS, B_RES, B_C, B_BTOT, B_LWO, B_XO, B_LOGREG, B_CKPT, B_SEG, B_ABITS,
+    B_GPART, B_GRAD, B_DEVRUN, B_DEVDESC, B_COUNT
 };
 
 template <typename T>
@@ -282,6 +288,368 @@ int adapt_schedule_impl(int T, const double* beta, const double* log_g, int Tn, 
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Device-resident round loop (Alg. 2 with N fixed): every round's sweep,
+// merge, OptimiseSchedule and step-size update stay on the GPU; one batch of
+// problems (or a single one) is enqueued, optionally as one hipGraph.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct DevProblem {
+    oasmc_problem prob;
+    oasmc_kernel kern;
+    int64_t N;
+    std::vector<int> Ts;  // T of each round, plus the T of the schedule after the last
+    int eps_adapt, interp;
+    double eps0, eps_kappa, accept_target;
+    uint64_t seed;
+    uint32_t problem_id;
+    // derived
+    bool logreg;
+    ValuShape shape;
+    int kh;
+    int64_t ntiles, S;
+    int Tcap;
+    size_t off_sched, off_out, off_part, off_scratch, off_par, off_data;
+};
+
+struct DevOut {  // byte offsets inside a problem's output block
+    size_t logZ, log_g, acc, Lambda, status, beta, eps;
+};
+
+template <typename T>
+T* at(char* base, size_t off) { return reinterpret_cast<T*>(base + off); }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+DevOut out_layout(const DevProblem& q, int R, size_t* bytes)
+{
+    DevOut o{};
+    size_t b = 0;
+    const size_t Tc = (size_t)q.Tcap;
+    o.logZ = b; b += sizeof(double) * R;
+    o.log_g = b; b += sizeof(double) * R * 3 * Tc;
+    o.acc = b; b += sizeof(double) * R * Tc;
+    o.Lambda = b; b += sizeof(double) * R * (Tc + 1);
+    o.status = b; b += sizeof(int) * R;
+    b = align256(b);
+    *bytes = b;
+    return o;
+}
+
+// schedule block: beta [(R+1)][Tcap+1] then eps [(R+1)][Tcap]
+size_t sched_bytes(const DevProblem& q, int R)
+{
+    return align256(sizeof(double) * (size_t)(R + 1) * ((q.Tcap + 1) + q.Tcap));
+}
+
+int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_graph,
+               std::vector<char>& host_sched, std::vector<char>& host_out, hipStream_t st)
+{
+    const int P = (int)ps.size();
+    // layout of the device workspace
+    size_t off = 0;
+    size_t sched_total = 0, out_total = 0;
+    for (auto& q : ps) { q.off_sched = sched_total; sched_total += sched_bytes(q, R); }
+    off = sched_total;
+    const size_t out_base = off;
+    for (auto& q : ps) {
+        size_t ob;
+        out_layout(q, R, &ob);
+        q.off_out = out_base + out_total;
+        out_total += ob;
+    }
+    off += out_total;
+    for (auto& q : ps) {
+        q.off_part = off;
+        off += align256(sizeof(double) * (size_t)q.S * (q.Tcap + 1) * 4);
+        q.off_scratch = off;
+        off += align256(sizeof(double) * 3 * (size_t)(q.Tcap + 1));
+        q.off_par = off;
+        if (!q.logreg)
+            off += align256(sizeof(float) * q.prob.d + 2 * sizeof(double) * kMaxK);
+        q.off_data = off;
+        if (q.logreg) {
+            const int np = logreg_npad(q.prob.n);
+            off += align256(sizeof(float) * (size_t)np * 65);
+        }
+    }
+    char* ws;
+    {
+        void* v;
+        HIP_TRY(h->get(B_DEVRUN, off, &v));
+        ws = static_cast<char*>(v);
+    }
+    // descriptors: SweepArgs [R][P], LogregArgs [R][P], ParView [P], RoundDev [R][P],
+    // TargetDev [P], param pointers [3][P], items per class
+    struct ClassKey {
+        bool logreg; int fam, move, lpp, dpl, kh;
+        bool operator==(const ClassKey& o) const
+        {
+            return logreg == o.logreg && fam == o.fam && move == o.move && lpp == o.lpp &&
+                   dpl == o.dpl && kh == o.kh;
+        }
+    };
+    std::vector<ClassKey> classes;
+    std::vector<std::vector<int2>> items;
+    std::vector<std::vector<double>> item_cost;
+    for (int p = 0; p < P; ++p) {
+        const DevProblem& q = ps[p];
+        ClassKey k{q.logreg, q.prob.family, q.kern.move, q.shape.lpp, q.shape.dpl, q.kh};
+        size_t c = 0;
+        while (c < classes.size() && !(classes[c] == k)) ++c;
+        if (c == classes.size()) { classes.push_back(k); items.emplace_back(); item_cost.emplace_back(); }
+        for (int64_t sl = 0; sl < q.S; ++sl) {
+            const int64_t tiles = (q.ntiles - sl + q.S - 1) / q.S;
+            items[c].push_back(make_int2(p, (int)sl));
+            item_cost[c].push_back((double)tiles * q.Ts[R - 1] * (q.logreg ? q.prob.n : q.prob.d));
+        }
+    }
+    // longest items first, so the static round-robin assignment balances
+    for (size_t c = 0; c < classes.size(); ++c) {
+        std::vector<size_t> idx(items[c].size());
+        for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+        std::stable_sort(idx.begin(), idx.end(),
+                         [&](size_t a, size_t b) { return item_cost[c][a] > item_cost[c][b]; });
+        std::vector<int2> sorted(idx.size());
+        for (size_t i = 0; i < idx.size(); ++i) sorted[i] = items[c][idx[i]];
+        items[c].swap(sorted);
+    }
+    size_t dsz = 0;
+    const size_t d_sweep = dsz; dsz += align256(sizeof(SweepArgs) * R * P);
+    const size_t d_lr = dsz; dsz += align256(sizeof(LogregArgs) * R * P);
+    const size_t d_view = dsz; dsz += align256(sizeof(ParView) * P);
+    const size_t d_round = dsz; dsz += align256(sizeof(RoundDev) * R * P);
+    const size_t d_tg = dsz; dsz += align256(sizeof(TargetDev) * P);
+    const size_t d_pp = dsz; dsz += align256(sizeof(void*) * 3 * P);
+    std::vector<size_t> d_items(classes.size());
+    for (size_t c = 0; c < classes.size(); ++c) { d_items[c] = dsz; dsz += align256(sizeof(int2) * items[c].size()); }
+    char* dd;
+    {
+        void* v;
+        HIP_TRY(h->get(B_DEVDESC, dsz, &v));
+        dd = static_cast<char*>(v);
+    }
+    std::vector<char> blob(dsz, 0);
+    for (int p = 0; p < P; ++p) {
+        DevProblem& q = ps[p];
+        size_t ob;
+        const DevOut o = out_layout(q, R, &ob);
+        char* outp = ws + q.off_out;
+        double* beta0 = at<double>(ws, q.off_sched);
+        double* eps0 = beta0 + (size_t)(R + 1) * (q.Tcap + 1);
+        // parameter view (closed-form families): m [d] floats, then 1/(2 v_k) and
+        // 1/v_k (kMaxK doubles each); none for logistic regression
+        ParView v{};
+        if (!q.logreg) {
+            v.m = at<float>(ws, q.off_par);
+            v.hiv = reinterpret_cast<const double*>(ws + q.off_par + align256(sizeof(float) * q.prob.d));
+            v.iv = v.hiv + kMaxK;
+            v.mu = (q.prob.family == OASMC_GMM) ? q.prob.means : q.prob.mu;
+        }
+        reinterpret_cast<ParView*>(blob.data() + d_view)[p] = v;
+        reinterpret_cast<TargetDev*>(blob.data() + d_tg)[p] = target_dev(&q.prob);
+        void** pp = reinterpret_cast<void**>(blob.data() + d_pp);
+        pp[p] = (void*)v.m;
+        pp[P + p] = (void*)v.hiv;
+        pp[2 * P + p] = (void*)v.iv;
+        for (int k = 0; k < R; ++k) {
+            const int T = q.Ts[k];
+            SweepArgs a{};
+            a.tg = target_dev(&q.prob);
+            a.move = q.kern.move;
+            a.leapfrog = q.kern.leapfrog;
+            a.N = q.N;
+            a.T = T;
+            a.beta = beta0 + (size_t)k * (q.Tcap + 1);
+            a.eps = eps0 + (size_t)k * q.Tcap;
+            a.key.k0 = (uint32_t)(q.seed & 0xFFFFFFFFu);
+            a.key.k1 = (uint32_t)(q.seed >> 32);
+            a.key.c2 = ((uint32_t)(k + 1) & 0xFFFFu) | (q.problem_id << 16);
+            a.part = at<double>(ws, q.off_part);
+            a.S = q.S;
+            a.ntiles = q.ntiles;
+            a.acc_words = (T + 31) / 32;
+            reinterpret_cast<SweepArgs*>(blob.data() + d_sweep)[(size_t)k * P + p] = a;
+            LogregArgs la{};
+            la.a = a;
+            if (q.logreg) {
+                const int np = logreg_npad(q.prob.n);
+                la.Xp = at<float>(ws, q.off_data);
+                la.yp = la.Xp + (size_t)np * 64;
+                la.n_pad = np;
+            }
+            reinterpret_cast<LogregArgs*>(blob.data() + d_lr)[(size_t)k * P + p] = la;
+            RoundDev rd{};
+            rd.T = T;
+            rd.Tn = q.Ts[k + 1];
+            rd.N = q.N;
+            rd.S = q.S;
+            rd.part = a.part;
+            rd.beta = a.beta;
+            rd.eps = a.eps;
+            rd.log_g = at<double>(outp, o.log_g) + (size_t)k * 3 * q.Tcap;
+            rd.acc = at<double>(outp, o.acc) + (size_t)k * q.Tcap;
+            rd.logZ = at<double>(outp, o.logZ) + k;
+            rd.Lambda = at<double>(outp, o.Lambda) + (size_t)k * (q.Tcap + 1);
+            rd.beta_next = beta0 + (size_t)(k + 1) * (q.Tcap + 1);
+            rd.eps_next = eps0 + (size_t)(k + 1) * q.Tcap;
+            rd.status = at<int>(outp, o.status) + k;
+            rd.scratch = at<double>(ws, q.off_scratch);
+            rd.interp = q.interp;
+            rd.eps_adapt = q.eps_adapt;
+            rd.eps0 = q.eps0;
+            rd.accept_target = q.accept_target;
+            reinterpret_cast<RoundDev*>(blob.data() + d_round)[(size_t)k * P + p] = rd;
+        }
+    }
+    for (size_t c = 0; c < classes.size(); ++c)
+        std::copy(items[c].begin(), items[c].end(), reinterpret_cast<int2*>(blob.data() + d_items[c]));
+
+    // the round-1 schedules and step sizes
+    host_sched.assign(sched_total, 0);
+    for (const auto& q : ps) {
+        double* b = reinterpret_cast<double*>(host_sched.data() + q.off_sched);
+        double* e = b + (size_t)(R + 1) * (q.Tcap + 1);
+        const int T = q.Ts[0];
+        uniform_schedule(T, b);
+        for (int t = 1; t <= T; ++t)
+            e[t - 1] = q.eps_adapt ? q.eps0 / std::sqrt(1.0 + b[t] * q.eps_kappa) : q.eps0;
+    }
+    HIP_TRY(hipMemcpyAsync(dd, blob.data(), dsz, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ws, host_sched.data(), sched_total, hipMemcpyHostToDevice, st));
+    // per-problem constant data: parameter views and packed regression data
+    {
+        std::vector<int> vp;
+        for (int p = 0; p < P; ++p)
+            if (!ps[p].logreg) vp.push_back(p);
+        if (!vp.empty()) {
+            const TargetDev* tgs = reinterpret_cast<const TargetDev*>(dd + d_tg);
+            float* const* pm = reinterpret_cast<float* const*>(dd + d_pp);
+            double* const* ph = reinterpret_cast<double* const*>(dd + d_pp + sizeof(void*) * P);
+            double* const* pi = reinterpret_cast<double* const*>(dd + d_pp + 2 * sizeof(void*) * P);
+            // logistic-regression entries have null pointers and are skipped by family
+            HIP_TRY(launch_batch_params(tgs, pm, ph, pi, P, st));
+        }
+        for (int p = 0; p < P; ++p)
+            if (ps[p].logreg) {
+                const int np = logreg_npad(ps[p].prob.n);
+                float* Xp = at<float>(ws, ps[p].off_data);
+                const TargetDev tg = target_dev(&ps[p].prob);
+                HIP_TRY(logreg_pack_into(tg, Xp, Xp + (size_t)np * 64, st));
+            }
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+
+    auto enqueue = [&](hipStream_t s) -> int {
+        for (int k = 0; k < R; ++k) {
+            for (size_t c = 0; c < classes.size(); ++c) {
+                const int64_t n = (int64_t)items[c].size();
+                const int2* it = reinterpret_cast<const int2*>(dd + d_items[c]);
+                if (classes[c].logreg) {
+                    const LogregArgs* la = reinterpret_cast<const LogregArgs*>(dd + d_lr) + (size_t)k * P;
+                    const int grid = (int)std::min<int64_t>(n, h->cus);
+                    HIP_TRY(launch_oais_logreg_batch(classes[c].kh, la, it, n, grid, s));
+                } else {
+                    ValuBatch b{};
+                    b.args = reinterpret_cast<const SweepArgs*>(dd + d_sweep) + (size_t)k * P;
+                    b.views = reinterpret_cast<const ParView*>(dd + d_view);
+                    b.items = it;
+                    b.nitems = n;
+                    ValuShape sh{classes[c].lpp, classes[c].dpl};
+                    const int gw = (int)std::min<int64_t>(n, (int64_t)h->cus * 8);
+                    HIP_TRY(launch_oais_valu_batch(classes[c].fam, classes[c].move, sh, b, gw, s));
+                }
+            }
+            const RoundDev* rd = reinterpret_cast<const RoundDev*>(dd + d_round) + (size_t)k * P;
+            HIP_TRY(launch_round_merge(rd, P, s));
+            HIP_TRY(launch_round_schedule(rd, P, s));
+        }
+        return OASMC_OK;
+    };
+
+    if (h->prof) HIP_TRY(hipEventRecord(h->ev0, st));
+    if (use_graph) {
+        // reuse the instantiated graph when the descriptors are unchanged
+        std::vector<char> key(blob);
+        key.insert(key.end(), host_sched.begin(), host_sched.end());
+        const char* wsc = reinterpret_cast<const char*>(&ws);
+        key.insert(key.end(), wsc, wsc + sizeof(ws));
+        if (!h->graph_exec || key != h->graph_key) {
+            if (h->graph_exec) {
+                HIP_TRY(hipGraphExecDestroy(h->graph_exec));
+                h->graph_exec = nullptr;
+            }
+            hipGraph_t g;
+            if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+            HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+            const int e = enqueue(h->cap_stream);
+            hipGraph_t gg = nullptr;
+            const hipError_t ce = hipStreamEndCapture(h->cap_stream, &gg);
+            if (e != OASMC_OK) {
+                if (gg) hipGraphDestroy(gg);
+                return e;
+            }
+            if (ce != hipSuccess) return fail(OASMC_EHIP, "graph capture failed: %s", hipGetErrorString(ce));
+            g = gg;
+            HIP_TRY(hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0));
+            HIP_TRY(hipGraphDestroy(g));
+            h->graph_key.swap(key);
+        }
+        HIP_TRY(hipGraphLaunch(h->graph_exec, st));
+    } else {
+        const int e = enqueue(st);
+        if (e != OASMC_OK) return e;
+    }
+    if (h->prof) HIP_TRY(hipEventRecord(h->ev1, st));
+    host_out.resize(out_total + sched_total);
+    HIP_TRY(hipMemcpyAsync(host_out.data(), ws + out_base, out_total, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(host_out.data() + out_total, ws, sched_total, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h->prof) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+        h->prof_ms += ms;
+        h->prof_launches += 1;
+        for (const auto& q : ps)
+            for (int k = 0; k < R; ++k) {
+                h->prof_steps += (double)q.N * q.Ts[k];
+                if (q.logreg) h->prof_flops += 4.0 * q.prob.d * (double)q.prob.n * (double)q.N * (q.Ts[k] + 1);
+            }
+    }
+    return OASMC_OK;
+}
+
+// Fills the derived fields of a problem; returns a status.
+int prepare_dev_problem(oasmc_handle* h, DevProblem& q)
+{
+    int s = check_problem(&q.prob, &q.kern);
+    if (s) return s;
+    if (q.kern.resample) return fail(OASMC_EUNSUPPORTED, "the device round loop runs AIS passes");
+    if (q.N < 1 || q.N > ((int64_t)1 << 30)) return fail(OASMC_EINVAL, "N must lie in [1, 2^30]");
+    if (!(q.eps0 > 0.0)) return fail(OASMC_EINVAL, "eps0 must be positive");
+    q.logreg = (q.prob.family == OASMC_LOGREG);
+    if (q.logreg) {
+        if (h->lds_per_block < logreg_shared_bytes())
+            return fail(OASMC_EUNSUPPORTED, "device offers %zu bytes of LDS per workgroup, need %zu",
+                        h->lds_per_block, logreg_shared_bytes());
+        q.kh = logreg_kh(q.prob.d);
+        if (q.kh < 0) return fail(OASMC_EUNSUPPORTED, "no kernel for d=%d", q.prob.d);
+        q.shape = ValuShape{0, 0};
+        q.ntiles = logreg_tiles(q.N);
+    } else {
+        if (!valu_shape(q.prob.d, &q.shape)) return fail(OASMC_EUNSUPPORTED, "no kernel for d=%d", q.prob.d);
+        q.kh = 0;
+        q.ntiles = valu_tiles(q.N, q.shape);
+    }
+    q.S = std::min<int64_t>(q.ntiles, 2048);
+    q.Tcap = 1;
+    for (int T : q.Ts) q.Tcap = std::max(q.Tcap, T);
+    return OASMC_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* oasmc_last_error(void) { return g_err.c_str(); }
@@ -311,6 +679,8 @@ int oasmc_handle_destroy(oasmc_handle* h)
     hipSetDevice(h->device);
     if (h->ev0) hipEventDestroy(h->ev0);
     if (h->ev1) hipEventDestroy(h->ev1);
+    if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
+    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     for (auto& b : h->bufs)
         if (b.p) hipFree(b.p);
     delete h;
@@ -502,6 +872,93 @@ int oasmc_logreg_eval(oasmc_handle* h, const oasmc_problem* problem, int64_t N,
     return OASMC_OK;
 }
 
+int oasmc_logZ_backward(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel* kernel,
+                        int64_t N, int32_t T, const double* beta, const double* eps, uint64_t seed,
+                        uint32_t round_k, uint32_t problem_id, double* logZ, double* grad,
+                        void* stream)
+{
+    if (!h || !logZ || !grad) return fail(OASMC_EINVAL, "NULL argument");
+    int s = check_problem(problem, kernel);
+    if (s) return s;
+    if (problem->family != OASMC_GMM || kernel->move != OASMC_MALA || kernel->resample)
+        return fail(OASMC_EUNSUPPORTED, "the gradient is built for the mixture target with MALA and no resampling");
+    ValuShape shape{}, ashape{};
+    int kb = 0;
+    if (!valu_shape(problem->d, &shape) || !adjoint_shape(problem->d, problem->K, &ashape, &kb) ||
+        shape.lpp != ashape.lpp || shape.dpl != ashape.dpl)
+        return fail(OASMC_EUNSUPPORTED, "the gradient supports d <= 32 and K <= 8");
+    s = check_schedule(T, beta);
+    if (s) return s;
+    if (N < 1 || N > ((int64_t)1 << 30)) return fail(OASMC_EINVAL, "N must lie in [1, 2^30]");
+    if (!eps) return fail(OASMC_EINVAL, "eps is NULL");
+    for (int t = 0; t < T; ++t)
+        if (!(eps[t] > 0.0) || !std::isfinite(eps[t]))
+            return fail(OASMC_EINVAL, "eps[%d] must be positive and finite", t);
+    HIP_TRY(hipSetDevice(h->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int d = problem->d;
+    const int every = 16;
+    const int nseg = (T + every - 1) / every;
+    const int np = problem->K * d + problem->K;
+
+    SweepArgs a{};
+    a.tg = target_dev(problem);
+    a.move = kernel->move;
+    a.leapfrog = 1;
+    a.N = N;
+    a.T = T;
+    a.key.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    a.key.k1 = (uint32_t)(seed >> 32);
+    a.key.c2 = (round_k & 0xFFFFu) | (problem_id << 16);
+    a.acc_words = (T + 31) / 32;
+    a.ckpt_every = every;
+    double *dbeta, *deps, *dlogg, *dacc, *dscal, *dlw, *gpart, *dgrad;
+    HIP_TRY(wget(h, B_BETA, T + 1, &dbeta));
+    HIP_TRY(wget(h, B_EPS, T, &deps));
+    HIP_TRY(wget(h, B_LOGG, 3 * (size_t)T, &dlogg));
+    HIP_TRY(wget(h, B_ACC, T, &dacc));
+    HIP_TRY(wget(h, B_SCAL, 8, &dscal));
+    HIP_TRY(wget(h, B_LWO, N, &dlw));
+    HIP_TRY(wget(h, B_CKPT, (size_t)N * nseg * d, &a.ckpt));
+    HIP_TRY(wget(h, B_ABITS, (size_t)N * a.acc_words, &a.acc_bits));
+    HIP_TRY(hipMemcpyAsync(dbeta, beta, sizeof(double) * (T + 1), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(deps, eps, sizeof(double) * T, hipMemcpyHostToDevice, st));
+    a.beta = dbeta;
+    a.eps = deps;
+    a.lw_out = dlw;
+    const int64_t ntiles = valu_tiles(N, shape);
+    const int64_t S = std::min<int64_t>(ntiles, 2048);
+    double* part;
+    HIP_TRY(wget(h, B_PART, (size_t)S * (T + 1) * 4, &part));
+    a.part = part;
+    a.S = S;
+    a.ntiles = ntiles;
+    // forward: the AIS pass with checkpoints and decisions recorded
+    const int grid_waves = (int)std::min<int64_t>(S, (int64_t)h->cus * 8);
+    HIP_TRY(launch_oais_valu(a, shape, grid_waves, st));
+    HIP_TRY(launch_merge_slots(part, S, T, N, dlogg, dacc, dscal, st));
+    // reverse
+    AdjointArgs A{};
+    A.a = a;
+    A.lw = dlw;
+    A.scal = dscal;
+    HIP_TRY(wget(h, B_SEG, (size_t)N * every * d, &A.seg));
+    HIP_TRY(wget(h, B_GPART, (size_t)ntiles * np, &gpart));
+    HIP_TRY(wget(h, B_GRAD, np, &dgrad));
+    A.partial = gpart;
+    A.nwaves = ntiles;
+    HIP_TRY(launch_adjoint(A, ashape, kb, st));
+    HIP_TRY(launch_adjoint_reduce(gpart, ntiles, np, dgrad, st));
+    double lz = 0.0;
+    HIP_TRY(hipMemcpyAsync(&lz, dscal, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(grad, dgrad, sizeof(double) * np, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *logZ = lz;
+    if (!std::isfinite(lz)) return fail(OASMC_ENONFINITE, "log Z_hat is not finite");
+    g_err.clear();
+    return OASMC_OK;
+}
+
 int oasmc_profile(oasmc_handle* h, int32_t enable, double* kernel_ms, int64_t* launches,
                   double* particle_steps, double* flops)
 {
@@ -616,6 +1073,67 @@ extern "C" int oasmc_run(oasmc_handle* h, const oasmc_problem* problem, const oa
         return fail(OASMC_EINVAL, "every oasmc_run_out array is required");
     const int Tcap = out->Tcap;
     out->rounds_done = 0;
+    if (!kernel->resample &&
+        (opts->budget == OASMC_BUDGET_FIXED || opts->budget == OASMC_BUDGET_DOUBLE_T)) {
+        DevProblem q{};
+        q.prob = *problem;
+        q.kern = *kernel;
+        q.N = N1;
+        int T = opts->T1;
+        for (int k = 0; k <= out->rounds; ++k) {
+            q.Ts.push_back(T);
+            if (opts->budget == OASMC_BUDGET_DOUBLE_T) T *= 2;
+            if (opts->T_max > 0) T = std::min(T, opts->T_max);
+            T = std::min(T, Tcap);
+        }
+        q.eps_adapt = opts->eps_adapt;
+        q.interp = opts->interp;
+        q.eps0 = opts->eps0;
+        q.eps_kappa = opts->eps_kappa;
+        q.accept_target = opts->accept_target;
+        q.seed = seed;
+        q.problem_id = problem_id;
+        int st = prepare_dev_problem(h, q);
+        if (st) return st;
+        HIP_TRY(hipSetDevice(h->device));
+        std::vector<DevProblem> ps{q};
+        std::vector<char> hs, ho;
+        st = run_device(h, ps, out->rounds, false, hs, ho, (hipStream_t)stream);
+        if (st) return st;
+        const DevProblem& r = ps[0];
+        size_t ob;
+        const DevOut o = out_layout(r, out->rounds, &ob);
+        const char* base = ho.data();
+        const char* sched = ho.data() + ob;
+        const double* beta_all = reinterpret_cast<const double*>(sched);
+        const double* eps_all = beta_all + (size_t)(out->rounds + 1) * (r.Tcap + 1);
+        int status = OASMC_OK;
+        for (int k = 0; k < out->rounds; ++k) {
+            const int T = r.Ts[k];
+            out->logZ[k] = reinterpret_cast<const double*>(base + o.logZ)[k];
+            out->N[k] = N1;
+            out->T[k] = T;
+            out->n_resample[k] = 0;
+            std::copy(beta_all + (size_t)k * (r.Tcap + 1), beta_all + (size_t)k * (r.Tcap + 1) + T + 1,
+                      out->beta + (size_t)k * (Tcap + 1));
+            std::copy(eps_all + (size_t)k * r.Tcap, eps_all + (size_t)k * r.Tcap + T,
+                      out->eps + (size_t)k * Tcap);
+            const double* lg = reinterpret_cast<const double*>(base + o.log_g) + (size_t)k * 3 * r.Tcap;
+            std::copy(lg, lg + 3 * T, out->log_g + (size_t)k * 3 * Tcap);
+            const double* ac = reinterpret_cast<const double*>(base + o.acc) + (size_t)k * r.Tcap;
+            std::copy(ac, ac + T, out->accept + (size_t)k * Tcap);
+            const double* la = reinterpret_cast<const double*>(base + o.Lambda) + (size_t)k * (r.Tcap + 1);
+            std::copy(la, la + T + 1, out->Lambda_hat + (size_t)k * (Tcap + 1));
+            if (reinterpret_cast<const int*>(base + o.status)[k] && status == OASMC_OK)
+                status = fail(OASMC_ENONFINITE, "non-finite moments in round %d", k + 1);
+            if (!std::isfinite(out->logZ[k]) && status == OASMC_OK)
+                status = fail(OASMC_ENONFINITE, "log Z_hat is not finite in round %d", k + 1);
+            out->rounds_done = k + 1;
+            if (status != OASMC_OK) break;
+        }
+        if (status == OASMC_OK) g_err.clear();
+        return status;
+    }
     int64_t N = N1;
     int T = opts->T1;
     std::vector<double> beta(T + 1), eps(T);
@@ -671,3 +1189,61 @@ extern "C" int oasmc_run(oasmc_handle* h, const oasmc_problem* problem, const oa
 }
 
 }  // extern "C"
+
+extern "C" int oasmc_run_batch(oasmc_handle* h, const oasmc_batch_problem* probs, int32_t P,
+                               int32_t rounds, int32_t use_graph, oasmc_batch_out* out,
+                               void* stream)
+{
+    if (!h || !probs || !out || !out->logZ) return fail(OASMC_EINVAL, "NULL argument");
+    if (P < 1) return fail(OASMC_EINVAL, "need at least one problem");
+    if (rounds < 1) return fail(OASMC_EINVAL, "rounds must be >= 1");
+    HIP_TRY(hipSetDevice(h->device));
+    std::vector<DevProblem> ps(P);
+    for (int p = 0; p < P; ++p) {
+        const oasmc_batch_problem& b = probs[p];
+        DevProblem& q = ps[p];
+        q.prob = b.problem;
+        q.kern = b.kernel;
+        q.N = b.N;
+        if (b.T < 1) return fail(OASMC_EINVAL, "problem %d: T must be >= 1", p);
+        int T = std::max(1, b.T >> (rounds - 1));
+        for (int k = 0; k <= rounds; ++k) {
+            q.Ts.push_back(T);
+            T = std::min(2 * T, b.T);
+        }
+        q.eps_adapt = b.eps_adapt;
+        q.interp = 0;
+        q.eps0 = b.eps0;
+        q.eps_kappa = b.eps_kappa;
+        q.accept_target = b.accept_target;
+        q.seed = b.seed;
+        q.problem_id = b.problem_id;
+        const int st = prepare_dev_problem(h, q);
+        if (st) {
+            std::string m = g_err;
+            return fail(st, "problem %d: %s", p, m.c_str());
+        }
+    }
+    std::vector<char> hs, ho;
+    const int st = run_device(h, ps, rounds, use_graph != 0, hs, ho, (hipStream_t)stream);
+    if (st) return st;
+    int status = OASMC_OK;
+    for (int p = 0; p < P; ++p) {
+        const DevProblem& q = ps[p];
+        size_t ob;
+        const DevOut o = out_layout(q, rounds, &ob);
+        const char* base = ho.data() + (q.off_out - ps[0].off_out);
+        for (int k = 0; k < rounds; ++k) {
+            out->logZ[(size_t)p * rounds + k] = reinterpret_cast<const double*>(base + o.logZ)[k];
+            if (out->Lambda_T)
+                out->Lambda_T[(size_t)p * rounds + k] =
+                    reinterpret_cast<const double*>(base + o.Lambda)[(size_t)k * (q.Tcap + 1) + q.Ts[k]];
+            const int bad = reinterpret_cast<const int*>(base + o.status)[k];
+            if (out->status) out->status[(size_t)p * rounds + k] = bad;
+            if (bad && status == OASMC_OK)
+                status = fail(OASMC_ENONFINITE, "problem %d round %d: non-finite moments", p, k + 1);
+        }
+    }
+    if (status == OASMC_OK) g_err.clear();
+    return status;
+}

@@ -309,18 +309,51 @@ int64_t valu_tiles(int64_t N, const ValuShape& s)
 
 template <int FAM, int MOVE>
 hipError_t valu_dispatch(int what, const SweepArgs& a, const ValuShape& s, int gw,
-                         const AsmcState* z, int t, hipStream_t st);
+                         const AsmcState* z, int t, hipStream_t st, const ValuBatch* b);
 static hipError_t dispatch_all(int what, const SweepArgs& a, const ValuShape& s, int gw,
-                               const AsmcState* z, int t, hipStream_t st)
+                               const AsmcState* z, int t, hipStream_t st,
+                               const ValuBatch* b = nullptr)
 {
     const int fam = a.tg.family, mv = a.move;
-    if (fam == kGauss && mv == kRwmh) return valu_dispatch<kGauss, kRwmh>(what, a, s, gw, z, t, st);
-    if (fam == kGauss && mv == kMala) return valu_dispatch<kGauss, kMala>(what, a, s, gw, z, t, st);
-    if (fam == kGauss && mv == kHmc) return valu_dispatch<kGauss, kHmc>(what, a, s, gw, z, t, st);
-    if (fam == kGmm && mv == kRwmh) return valu_dispatch<kGmm, kRwmh>(what, a, s, gw, z, t, st);
-    if (fam == kGmm && mv == kMala) return valu_dispatch<kGmm, kMala>(what, a, s, gw, z, t, st);
-    if (fam == kGmm && mv == kHmc) return valu_dispatch<kGmm, kHmc>(what, a, s, gw, z, t, st);
+    if (fam == kGauss && mv == kRwmh) return valu_dispatch<kGauss, kRwmh>(what, a, s, gw, z, t, st, b);
+    if (fam == kGauss && mv == kMala) return valu_dispatch<kGauss, kMala>(what, a, s, gw, z, t, st, b);
+    if (fam == kGauss && mv == kHmc) return valu_dispatch<kGauss, kHmc>(what, a, s, gw, z, t, st, b);
+    if (fam == kGmm && mv == kRwmh) return valu_dispatch<kGmm, kRwmh>(what, a, s, gw, z, t, st, b);
+    if (fam == kGmm && mv == kMala) return valu_dispatch<kGmm, kMala>(what, a, s, gw, z, t, st, b);
+    if (fam == kGmm && mv == kHmc) return valu_dispatch<kGmm, kHmc>(what, a, s, gw, z, t, st, b);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_oais_valu_batch(int family, int move, const ValuShape& s, const ValuBatch& b,
+                                  int grid_waves, hipStream_t st)
+{
+    SweepArgs a{};
+    a.tg.family = family;
+    a.move = move;
+    return dispatch_all(3, a, s, grid_waves, nullptr, 0, st, &b);
+}
+
+__global__ void k_batch_params(const TargetDev* __restrict__ tgs, float* const* m,
+                               double* const* hiv, double* const* iv)
+{
+    const TargetDev& tg = tgs[blockIdx.x];
+    // problems without a parameter view (logistic regression) are skipped
+    if (tg.family == kLogreg || m[blockIdx.x] == nullptr) return;
+    for (int i = threadIdx.x; i < tg.d; i += blockDim.x)
+        m[blockIdx.x][i] = tg.ref_mean ? tg.ref_mean[i] : 0.f;
+    if (tg.family == kGmm && hiv[blockIdx.x] != nullptr && iv[blockIdx.x] != nullptr)
+        for (int k = threadIdx.x; k < tg.K; k += blockDim.x) {
+            const double v = exp(2.0 * (double)tg.log_scales[k]);
+            hiv[blockIdx.x][k] = 0.5 / v;
+            iv[blockIdx.x][k] = 1.0 / v;
+        }
+}
+
+hipError_t launch_batch_params(const TargetDev* tgs, float* const* m, double* const* hiv,
+                               double* const* iv, int nprob, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_batch_params, dim3(nprob), dim3(64), 0, st, tgs, m, hiv, iv);
+    return hipGetLastError();
 }
 
 hipError_t launch_oais_valu(const SweepArgs& a, const ValuShape& s, int grid_waves, hipStream_t st)

@@ -326,36 +326,20 @@ __device__ __forceinline__ void contraction(LogregShared<PIPE>& sh, const float*
     lsync();
 }
 
-struct LogregArgs {
-    SweepArgs a;
-    const float* Xp;
-    const float* yp;
-    int n_pad;
-};
 
 // Particle p's thread r (of tpp) handles the normal blocks r, r + tpp,
 // r + 2 tpp, ... i.e. the features 4b..4b+3 of those blocks (below d).
 template <int TPP>
 __device__ __forceinline__ int feat_of(int r, int u) { return 4 * (r + TPP * (u / 4)) + (u % 4); }
 
+// The parameters shared by every tile of a problem: zero the particle arrays
+// (columns beyond d stay zero) and stage the reference mean in packed columns.
 template <int KH, bool PIPE>
-__global__ void __launch_bounds__(LCfg<PIPE>::threads) k_oais_logreg(LogregArgs A)
+__device__ __forceinline__ void logreg_setup(LogregShared<PIPE>& sh, const SweepArgs& a)
 {
-    using Cf = LCfg<PIPE>;
-    constexpr int kLThreads = Cf::threads;
-    constexpr int kTPP = Cf::tpp;
-    constexpr int kBlocksPerThread = Cf::blocks_per_thread;
-    constexpr int kFeatPerThread = Cf::feats_per_thread;
-    extern __shared__ __align__(16) char sh_raw[];
-    LogregShared<PIPE>& sh = *reinterpret_cast<LogregShared<PIPE>*>(sh_raw);
-    const SweepArgs& a = A.a;
+    constexpr int kLThreads = LCfg<PIPE>::threads;
     const int tid = threadIdx.x;
-    const int p = tid / kTPP, r = tid % kTPP;
     const int d = a.tg.d;
-    const int T = a.T;
-    const double s2r = a.tg.ref_sigma2;
-    const double inv_s2r = 1.0 / s2r, half_inv_s2r = 0.5 / s2r, sref = sqrt(s2r);
-
     for (int e = tid; e < kLP * kPs; e += kLThreads) {
         (&sh.theta[0][0])[e] = 0.f;
         (&sh.prop[0][0])[e] = 0.f;
@@ -369,8 +353,24 @@ __global__ void __launch_bounds__(LCfg<PIPE>::threads) k_oais_logreg(LogregArgs 
         sh.m[c] = (f >= 0 && f < d && a.tg.ref_mean) ? a.tg.ref_mean[f] : 0.f;
     }
     lsync();
+}
 
-    for (int64_t slot = blockIdx.x; slot < a.S; slot += gridDim.x) {
+// All tiles of one slot of one problem, in tile order (whole workgroup).
+template <int KH, bool PIPE>
+__device__ __forceinline__ void logreg_slot(LogregShared<PIPE>& sh, const LogregArgs& A,
+                                            int64_t slot)
+{
+    using Cf = LCfg<PIPE>;
+    constexpr int kTPP = Cf::tpp;
+    constexpr int kBlocksPerThread = Cf::blocks_per_thread;
+    constexpr int kFeatPerThread = Cf::feats_per_thread;
+    const SweepArgs& a = A.a;
+    const int tid = threadIdx.x;
+    const int p = tid / kTPP, r = tid % kTPP;
+    const int d = a.tg.d;
+    const int T = a.T;
+    const double s2r = a.tg.ref_sigma2;
+    const double inv_s2r = 1.0 / s2r, half_inv_s2r = 0.5 / s2r, sref = sqrt(s2r);
         for (int64_t tile = slot; tile < a.ntiles; tile += a.S) {
             const bool first = (tile == slot);
             const int64_t n64 = tile * kLP + p;
@@ -540,6 +540,32 @@ __global__ void __launch_bounds__(LCfg<PIPE>::threads) k_oais_logreg(LogregArgs 
             }
             lsync();
         }
+}
+
+template <int KH, bool PIPE>
+__global__ void __launch_bounds__(LCfg<PIPE>::threads) k_oais_logreg(LogregArgs A)
+{
+    extern __shared__ __align__(16) char sh_raw[];
+    LogregShared<PIPE>& sh = *reinterpret_cast<LogregShared<PIPE>*>(sh_raw);
+    logreg_setup<KH, PIPE>(sh, A.a);
+    for (int64_t slot = blockIdx.x; slot < A.a.S; slot += gridDim.x) logreg_slot<KH, PIPE>(sh, A, slot);
+}
+
+// Many logistic-regression problems with the same column half-width in one
+// launch: each workgroup walks the work list of (problem, slot) items.
+template <int KH, bool PIPE>
+__global__ void __launch_bounds__(LCfg<PIPE>::threads)
+    k_oais_logreg_batch(const LogregArgs* __restrict__ args, const int2* __restrict__ items,
+                        int64_t nitems)
+{
+    extern __shared__ __align__(16) char sh_raw[];
+    LogregShared<PIPE>& sh = *reinterpret_cast<LogregShared<PIPE>*>(sh_raw);
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int2 item = items[it];
+        const LogregArgs A = args[item.x];
+        logreg_setup<KH, PIPE>(sh, A.a);
+        logreg_slot<KH, PIPE>(sh, A, (int64_t)item.y);
+        lsync();
     }
 }
 
@@ -653,6 +679,34 @@ static void layout(const TargetDev& tg, void* ws, float** Xp, float** yp, int* n
 // Exact half-widths with a dedicated instantiation; other widths round up.
 static int kh_for(int d);
 
+int logreg_kh(int d) { return kh_for(d); }
+int logreg_npad(int n) { return n_pad_of(n); }
+
+hipError_t logreg_pack_into(const TargetDev& tg, float* Xp, float* yp, hipStream_t st)
+{
+    const int kh = kh_for(tg.d);
+    if (kh < 0) return hipErrorInvalidValue;
+    const int np = n_pad_of(tg.n);
+    const int64_t total = (int64_t)np * 64;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_logreg_pack, dim3(blocks), dim3(256), 0, st, tg.X, tg.y, tg.n, tg.d, kh,
+                       np, Xp, yp);
+    return hipGetLastError();
+}
+
+template <int KH, bool PIPE>
+static hipError_t launch_batch_kh2(const LogregArgs* args, const int2* items, int64_t nitems,
+                                   int grid, hipStream_t st)
+{
+    const size_t shb = sizeof(LogregShared<PIPE>);
+    hipError_t e = hipFuncSetAttribute((const void*)k_oais_logreg_batch<KH, PIPE>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_oais_logreg_batch<KH, PIPE>), dim3(grid), dim3(LCfg<PIPE>::threads), shb,
+                       st, args, items, nitems);
+    return hipGetLastError();
+}
+
 hipError_t logreg_prepare(const TargetDev& tg, void* ws, hipStream_t st)
 {
     float *Xp, *yp;
@@ -695,6 +749,21 @@ hipError_t launch_oais_logreg(const SweepArgs& a, int cus, void* ws, size_t, hip
     const int grid = (int)std::min<int64_t>(a.S, (int64_t)cus);
     switch (kh) {
 #define OASMC_KH_CASE(K) case K: return launch_kh<K>(A, grid, st);
+        OASMC_KH_LIST(OASMC_KH_CASE)
+#undef OASMC_KH_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_oais_logreg_batch(int kh, const LogregArgs* args, const int2* items,
+                                   int64_t nitems, int grid, hipStream_t st)
+{
+    const bool pipe = use_pipe();
+    switch (kh) {
+#define OASMC_KH_CASE(K) \
+    case K: return pipe ? launch_batch_kh2<K, true>(args, items, nitems, grid, st) \
+                        : launch_batch_kh2<K, false>(args, items, nitems, grid, st);
         OASMC_KH_LIST(OASMC_KH_CASE)
 #undef OASMC_KH_CASE
     default:

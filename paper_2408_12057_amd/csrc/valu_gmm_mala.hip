@@ -4,5 +4,6 @@
 
 namespace oasmc {
 template hipError_t valu_dispatch<kGmm, kMala>(int, const SweepArgs&, const ValuShape&, int,
-                                                  const AsmcState*, int, hipStream_t);
+                                                  const AsmcState*, int, hipStream_t,
+                                                  const ValuBatch*);
 }  // namespace oasmc

@@ -55,13 +55,8 @@ __device__ __forceinline__ Consts make_consts(const TargetDev& tg)
 }
 
 // Target parameters staged in LDS: reference mean [d], then the Gaussian mean
-// [d] or the mixture means [K*d], then the mixture 1/(2 v_k), 1/v_k.
-struct ParView {
-    const float* m;      // ref mean
-    const float* mu;     // gaussian mean or mixture means
-    const double* hiv;   // mixture 1/(2 v_k)
-    const double* iv;    // mixture 1/v_k
-};
+// [d] or the mixture means [K*d], then the mixture 1/(2 v_k), 1/v_k (the view
+// type ParView is declared in kernels.hpp).
 
 __device__ __forceinline__ ParView stage_params(const TargetDev& tg, char* sh)
 {
@@ -239,7 +234,8 @@ struct Particle {
     static __device__ __forceinline__ bool move(const TargetDev& tg, const Consts& c,
                                                 const ParView& pv, const RngKey& key, uint32_t n,
                                                 uint32_t t, int r, int L, double beta, double eps,
-                                                float (&x)[DPL], double& ell, double (&g)[DPL])
+                                                float (&x)[DPL], double& ell, double (&g)[DPL],
+                                                int forced = -1)
     {
         const int d = tg.d;
         const int i0 = r * DPL;
@@ -338,7 +334,7 @@ struct Particle {
                         group_sum<LPP>(kin1) + group_sum<LPP>(kin0);
         }
         const uint4 w = draw_block(key, n, t, kStreamAccept, 0u, 0u);
-        const bool acc = log(word_uniform(w.x)) < log_alpha;
+        const bool acc = (forced >= 0) ? (forced != 0) : (log(word_uniform(w.x)) < log_alpha);
         if (acc) {
 #pragma unroll
             for (int j = 0; j < DPL; ++j) {
@@ -357,23 +353,19 @@ struct Particle {
 constexpr int kTC = 8;      // steps buffered before a transposed reduction
 constexpr int kWavesPerBlock = 4;
 
+// All tiles of one slot of one problem, in tile order (one wave).  The
+// moments of a slot therefore accumulate in the same order whichever wave,
+// kernel or launch processes the slot.
 template <int FAM, int MOVE, int LPP, int DPL>
-__global__ void __launch_bounds__(256) k_oais_valu(SweepArgs a)
+__device__ __forceinline__ void oais_slot(const SweepArgs& a, const ParView& pv, const Consts& c,
+                                          int64_t slot, double2 (&rec)[kTC][kWave / LPP],
+                                          uint32_t (&cntb)[kTC])
 {
     constexpr int P = kWave / LPP;
     constexpr int PP = (P + 7) / 8;  // particles per reduction lane
-    __shared__ double2 sh_rec[kWavesPerBlock][kTC][P];
-    __shared__ uint32_t sh_cnt[kWavesPerBlock][kTC];
-    extern __shared__ __align__(16) char sh_dyn[];
-    const ParView pv = stage_params(a.tg, sh_dyn);
-    const Consts c = make_consts(a.tg);
-
     const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
     const int r = lane % LPP;
     const int pl = lane / LPP;
-    const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + wv;
-    const int64_t W = (int64_t)gridDim.x * kWavesPerBlock;
     const int T = a.T;
     const int d = a.tg.d;
     const bool grad = (MOVE != kRwmh);
@@ -390,7 +382,7 @@ __global__ void __launch_bounds__(256) k_oais_valu(SweepArgs a)
             for (int q = 0; q < PP; ++q) {
                 const int p = part * PP + q;
                 if (p < P) {
-                    const double2 v = sh_rec[wv][tcl][p];
+                    const double2 v = rec[tcl][p];
 #pragma unroll
                     for (int i = 0; i < 3; ++i) m[i] = fmax(m[i], v.x + (double)i * v.y);
                 }
@@ -399,7 +391,7 @@ __global__ void __launch_bounds__(256) k_oais_valu(SweepArgs a)
             for (int q = 0; q < PP; ++q) {
                 const int p = part * PP + q;
                 if (p < P) {
-                    const double2 v = sh_rec[wv][tcl][p];
+                    const double2 v = rec[tcl][p];
 #pragma unroll
                     for (int i = 0; i < 3; ++i)
                         if (m[i] > -INFINITY) s[i] += exp(v.x + (double)i * v.y - m[i]);
@@ -422,12 +414,12 @@ __global__ void __launch_bounds__(256) k_oais_valu(SweepArgs a)
                 const double L = lse_value(m[i], s[i]);
                 e[i] = first ? L : log_add(e[i], L);
             }
-            e[3] = (first ? 0.0 : e[3]) + (double)sh_cnt[wv][tcl];
+            e[3] = (first ? 0.0 : e[3]) + (double)cntb[tcl];
         }
         wave_sync();
     };
 
-    for (int64_t slot = gw; slot < a.S; slot += W) {
+    {
         for (int64_t tile = slot; tile < a.ntiles; tile += a.S) {
             const bool first = (tile == slot);
             const int64_t n64 = tile * P + pl;
@@ -439,16 +431,25 @@ __global__ void __launch_bounds__(256) k_oais_valu(SweepArgs a)
             double lw = 0.0;
             uint32_t accw = 0;
             for (int t = 1; t <= T; ++t) {
+                if (a.ckpt && ((t - 1) % a.ckpt_every) == 0 && valid) {
+                    const int nseg = (T + a.ckpt_every - 1) / a.ckpt_every;
+                    float* cp = a.ckpt + ((size_t)n64 * nseg + (t - 1) / a.ckpt_every) * d;
+#pragma unroll
+                    for (int j = 0; j < DPL; ++j) {
+                        const int i = r * DPL + j;
+                        if (i < d) cp[i] = x[j];
+                    }
+                }
                 const double lg = (a.beta[t] - a.beta[t - 1]) * ell;
                 const int tc = (t - 1) % kTC;
                 if (r == 0)
-                    sh_rec[wv][tc][pl] = valid ? make_double2(lw, lg) : make_double2(-INFINITY, 0.0);
+                    rec[tc][pl] = valid ? make_double2(lw, lg) : make_double2(-INFINITY, 0.0);
                 lw += lg;
                 const bool acc = Particle<FAM, LPP, DPL>::template move<MOVE>(
                     a.tg, c, pv, a.key, n, (uint32_t)t, r, a.leapfrog, a.beta[t], a.eps[t - 1], x,
                     ell, g);
                 const uint64_t bal = __ballot(valid && acc && r == 0);
-                if (lane == 0) sh_cnt[wv][tc] = (uint32_t)__popcll(bal);
+                if (lane == 0) cntb[tc] = (uint32_t)__popcll(bal);
                 accw |= (acc ? 1u : 0u) << ((t - 1) & 31);
                 if (((t - 1) & 31) == 31 || t == T) {
                     if (a.acc_bits && valid && r == 0)
@@ -458,8 +459,8 @@ __global__ void __launch_bounds__(256) k_oais_valu(SweepArgs a)
                 if (tc == kTC - 1 || t == T) flush(slot, first, t - 1 - tc, tc + 1);
             }
             // final weights -> entry T (log-sum-exp of log w_T over the tile)
-            if (r == 0) sh_rec[wv][0][pl] = valid ? make_double2(lw, 0.0) : make_double2(-INFINITY, 0.0);
-            if (lane == 0) sh_cnt[wv][0] = 0u;
+            if (r == 0) rec[0][pl] = valid ? make_double2(lw, 0.0) : make_double2(-INFINITY, 0.0);
+            if (lane == 0) cntb[0] = 0u;
             flush(slot, first, T, 1);
             if (valid) {
                 if (a.lw_out && r == 0) a.lw_out[n64] = lw;
@@ -472,6 +473,44 @@ __global__ void __launch_bounds__(256) k_oais_valu(SweepArgs a)
                 }
             }
         }
+    }
+}
+
+template <int FAM, int MOVE, int LPP, int DPL>
+__global__ void __launch_bounds__(256) k_oais_valu(SweepArgs a)
+{
+    __shared__ double2 sh_rec[kWavesPerBlock][kTC][kWave / LPP];
+    __shared__ uint32_t sh_cnt[kWavesPerBlock][kTC];
+    extern __shared__ __align__(16) char sh_dyn[];
+    const ParView pv = stage_params(a.tg, sh_dyn);
+    const Consts c = make_consts(a.tg);
+    const int wv = threadIdx.x / kWave;
+    const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+    const int64_t W = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t slot = gw; slot < a.S; slot += W)
+        oais_slot<FAM, MOVE, LPP, DPL>(a, pv, c, slot, sh_rec[wv], sh_cnt[wv]);
+}
+
+// Many problems of one (family, move, shape) class in one launch: each wave
+// walks the work list of (problem, slot) items; target parameters are read
+// from global memory through per-problem views.
+template <int FAM, int MOVE, int LPP, int DPL>
+__global__ void __launch_bounds__(256) k_oais_valu_batch(const SweepArgs* __restrict__ args,
+                                                         const ParView* __restrict__ views,
+                                                         const int2* __restrict__ items,
+                                                         int64_t nitems)
+{
+    __shared__ double2 sh_rec[kWavesPerBlock][kTC][kWave / LPP];
+    __shared__ uint32_t sh_cnt[kWavesPerBlock][kTC];
+    const int wv = threadIdx.x / kWave;
+    const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+    const int64_t W = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t it = gw; it < nitems; it += W) {
+        const int2 item = items[it];
+        const SweepArgs a = args[item.x];
+        const ParView pv = views[item.x];
+        const Consts c = make_consts(a.tg);
+        oais_slot<FAM, MOVE, LPP, DPL>(a, pv, c, (int64_t)item.y, sh_rec[wv], sh_cnt[wv]);
     }
 }
 
@@ -595,6 +634,14 @@ struct Launch {
                            params_bytes(a.tg), st, a);
         return hipGetLastError();
     }
+    static hipError_t batch(const SweepArgs* args, const ParView* views, const int2* items,
+                            int64_t nitems, int grid_waves, hipStream_t st)
+    {
+        const int blocks = (grid_waves + kWavesPerBlock - 1) / kWavesPerBlock;
+        hipLaunchKernelGGL((k_oais_valu_batch<FAM, MOVE, LPP, DPL>), dim3(blocks), dim3(256), 0, st,
+                           args, views, items, nitems);
+        return hipGetLastError();
+    }
     static hipError_t init(const SweepArgs& a, const AsmcState& z, hipStream_t st)
     {
         const int64_t blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -613,12 +660,15 @@ struct Launch {
 
 template <int FAM, int MOVE>
 hipError_t valu_dispatch(int what, const SweepArgs& a, const ValuShape& s, int gw,
-                           const AsmcState* z, int t, hipStream_t st)
+                           const AsmcState* z, int t, hipStream_t st, const ValuBatch* b)
 {
 #define OASMC_CASE(L, D)                                                     \
     if (s.lpp == L && s.dpl == D) {                                          \
         if (what == 0) return Launch<FAM, MOVE, L, D>::oais(a, gw, st);      \
         if (what == 1) return Launch<FAM, MOVE, L, D>::init(a, *z, st);      \
+        if (what == 3)                                                       \
+            return Launch<FAM, MOVE, L, D>::batch(b->args, b->views, b->items, \
+                                                  b->nitems, gw, st);        \
         return Launch<FAM, MOVE, L, D>::step(a, *z, t, st);                  \
     }
     OASMC_CASE(1, 4)

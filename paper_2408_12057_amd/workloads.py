@@ -89,3 +89,29 @@ def random_gmm(rng: np.random.Generator, d: int, K: int) -> dict:
 
 def synthetic_logw(rng: np.random.Generator, N: int, scale: float = 3.0) -> np.ndarray:
     return rng.normal(scale=scale, size=N)
+
+
+def batch_problems(n_problems: int = 256, seed_offset: int = 5, d_max_logreg: int = 64):
+    """Independent problems of uneven size: family by a fair coin (the d-dimensional
+    Gaussian target exp(-|x - 2 1|^2 / 0.5) with RWMH, or the logistic-regression
+    generator with MALA), d uniform in [5, 200] (logistic regression: [5, d_max_logreg]),
+    n uniform in [100, 5000], N in {2^8, ..., 2^16}, T in {2^5, ..., 2^10}.
+    Returns a list of dicts (family, d, N, T, params, eps0, eps_kappa)."""
+    rng = np.random.default_rng(DATA_SEED + seed_offset)
+    out = []
+    for p in range(n_problems):
+        fam = "gauss" if rng.random() < 0.5 else "logreg"
+        N = int(2 ** rng.integers(8, 17))
+        T = int(2 ** rng.integers(5, 11))
+        if fam == "gauss":
+            d = int(rng.integers(5, 201))
+            out.append(dict(family="gauss", d=d, N=N, T=T, move="rwmh",
+                            params=dict(mu=np.full(d, 2.0, dtype=np.float32), sigma2=0.25),
+                            eps0=0.5 / np.sqrt(d), eps_adapt=False, eps_kappa=0.0))
+        else:
+            d = int(rng.integers(5, d_max_logreg + 1))
+            n = int(rng.integers(100, 5001))
+            X, y, _ = logreg_data(n, d, DATA_SEED + 1000 + p)
+            out.append(dict(family="logreg", d=d, N=N, T=T, move="mala", params=dict(X=X, y=y),
+                            eps0=0.5 * d ** (-1.0 / 6.0), eps_adapt=True, eps_kappa=n / 4.0))
+    return out

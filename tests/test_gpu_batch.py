@@ -1,0 +1,98 @@
+"""Batched runs: many independent problems (mixed families, dimensions and
+kernel shapes) in one device-resident enqueue, optionally one hipGraph.  Each
+problem's per-round log Z_hat and Lambda_hat_T must equal, bit for bit, a
+plain oasmc_run of that problem alone: the same kernels walk the same slots in
+the same order, and Alg. 3 runs on the device in both."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2408_12057_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def oa():
+    import paper_2408_12057_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def _problem(oa, spec):
+    if spec["family"] == "gauss":
+        return oa.Problem.gauss(spec["params"]["mu"], spec["params"]["sigma2"], 1.0)
+    if spec["family"] == "gmm":
+        return oa.Problem.gmm(spec["params"]["means"], spec["params"]["log_scales"], 4.0)
+    return oa.Problem.logreg(spec["params"]["X"], spec["params"]["y"], 1.0)
+
+
+def _plain(oa, prob, spec, rounds, seed, pid):
+    T = spec["T"]
+    return oa.run(prob, spec["N"], rounds, seed=seed, problem_id=pid, move=spec["move"],
+                  leapfrog=3, budget="double_t", T1=max(1, T >> (rounds - 1)), T_max=T,
+                  eps0=spec["eps0"], eps_adapt=spec["eps_adapt"], eps_kappa=spec["eps_kappa"],
+                  accept_target=0.574, Tcap=T)
+
+
+def _mixed_specs():
+    rng = np.random.default_rng(8)
+    specs = []
+    for d, N, T in [(5, 100, 8), (10, 256, 16), (33, 300, 12), (70, 130, 8), (150, 65, 4)]:
+        specs.append(dict(family="gauss", d=d, N=N, T=T, move="rwmh",
+                          params=wl.random_gauss(rng, d), eps0=0.5 / np.sqrt(d), eps_adapt=False,
+                          eps_kappa=0.0))
+    specs.append(dict(family="gmm", d=20, N=500, T=16, move="mala",
+                      params=wl.random_gmm(rng, 20, 4), eps0=0.4, eps_adapt=True, eps_kappa=2.0))
+    specs.append(dict(family="gmm", d=6, N=70, T=9, move="hmc",
+                      params=wl.random_gmm(rng, 6, 3), eps0=0.3, eps_adapt=True, eps_kappa=1.0))
+    for d, n, N, T in [(7, 300, 64, 8), (50, 1000, 200, 16), (33, 777, 65, 4)]:
+        X, y, _ = wl.logreg_data(n, d, n + d)
+        specs.append(dict(family="logreg", d=d, N=N, T=T, move="mala", params=dict(X=X, y=y),
+                          eps0=0.5 * d ** (-1 / 6), eps_adapt=True, eps_kappa=n / 4))
+    return specs
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_equals_plain_runs(oa, use_graph):
+    rounds = 3
+    specs = _mixed_specs()
+    probs = [_problem(oa, s) for s in specs]
+    items = [oa.BatchItem(problem=p, N=s["N"], T=s["T"], move=s["move"], leapfrog=3,
+                          eps0=s["eps0"], eps_adapt=s["eps_adapt"], eps_kappa=s["eps_kappa"],
+                          seed=1000 + i, problem_id=i) for i, (p, s) in enumerate(zip(probs, specs))]
+    b = oa.run_batch(items, rounds, use_graph=use_graph)
+    assert np.all(b["status"] == 0)
+    for i, (p, s) in enumerate(zip(probs, specs)):
+        r = _plain(oa, p, s, rounds, 1000 + i, i)
+        np.testing.assert_array_equal(b["logZ"][i], r["logZ"], err_msg=f"problem {i}")
+        lam_T = np.array([r["Lambda"][k][r["T"][k]] for k in range(rounds)])
+        np.testing.assert_array_equal(b["Lambda_T"][i], lam_T, err_msg=f"problem {i}")
+
+
+def test_graph_replay_is_identical(oa):
+    specs = _mixed_specs()[:4]
+    probs = [_problem(oa, s) for s in specs]
+    items = [oa.BatchItem(problem=p, N=s["N"], T=s["T"], move=s["move"], eps0=s["eps0"],
+                          seed=7, problem_id=i) for i, (p, s) in enumerate(zip(probs, specs))]
+    a = oa.run_batch(items, 2, use_graph=True)
+    b = oa.run_batch(items, 2, use_graph=True)  # replays the cached graph
+    np.testing.assert_array_equal(a["logZ"], b["logZ"])
+    np.testing.assert_array_equal(a["Lambda_T"], b["Lambda_T"])
+
+
+def test_full_batch_sampled_against_plain(oa):
+    """The 256-problem workload (uneven d, n, N, T; 4 rounds) in one graph;
+    sampled problems equal their plain runs and every result is finite."""
+    specs = wl.batch_problems()
+    probs = [_problem(oa, s) for s in specs]
+    items = [oa.BatchItem(problem=p, N=s["N"], T=s["T"], move=s["move"], eps0=s["eps0"],
+                          eps_adapt=s["eps_adapt"], eps_kappa=s["eps_kappa"], seed=99,
+                          problem_id=i) for i, (p, s) in enumerate(zip(probs, specs))]
+    b = oa.run_batch(items, 4, use_graph=True)
+    assert np.all(np.isfinite(b["logZ"]))
+    rng = np.random.default_rng(0)
+    for i in rng.choice(len(specs), size=4, replace=False):
+        s = specs[i]
+        r = _plain(oa, probs[i], s, 4, 99, int(i))
+        np.testing.assert_array_equal(b["logZ"][i], r["logZ"], err_msg=f"problem {i}")
