@@ -28,6 +28,10 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 # plain-ALU peak: 256 CUs x 64 lanes x 2.4 GHz lane-operations per second
 PEAK_VALU_LANE_OPS = 256 * 64 * 2.4e9
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (scaled by the copy-kernel calibration); None until measured for
+# the current kernel.
+TRAFFIC = {}
 
 
 def log(msg: str) -> None:
@@ -42,14 +46,35 @@ def logreg_setup(oa, wl):
     return w, prob, kw, 11
 
 
-def gauss_setup(oa, wl):
-    w = wl.gaussian_d10(N=1 << 22)
+def gauss_setup(oa, wl, N=1024):
+    """The d = 10 Gaussian workload: N = 1024, 2048, 4096, 8192 over 4 rounds, T = 64."""
+    w = wl.gaussian_d10(N=N)
     prob = oa.Problem.gauss(w.params["mu"], w.params["sigma2"], w.ref_sigma2)
-    kw = dict(move="rwmh", budget="fixed", T1=64, eps0=w.eps0)
+    kw = dict(move="rwmh", budget="double_n", T1=64, eps0=w.eps0)
     return w, prob, kw, 4
 
 
-WORKLOADS = {"logreg": logreg_setup, "gauss": gauss_setup}
+def gauss_sat_setup(oa, wl):
+    """The same target at a saturating particle count (2^22, fixed), T = 64."""
+    w = wl.gaussian_d10(N=1 << 22)
+    prob = oa.Problem.gauss(w.params["mu"], w.params["sigma2"], w.ref_sigma2)
+    kw = dict(move="rwmh", budget="fixed", T1=64, eps0=w.eps0)
+    return w, prob, kw, 2
+
+
+def asmc_setup(oa, wl):
+    """8-component mixture in d = 100, HMC (5 leapfrogs), resampling when the
+    relative ESS drops below 0.5, N = 65536, T = 1, 2, ..., 1024, 2000."""
+    w = wl.gmm8_d100()
+    prob = oa.Problem.gmm(w.params["means"], w.params["log_scales"], w.ref_sigma2)
+    kw = dict(move="hmc", leapfrog=5, resample_=True, trigger="ess", nu=0.5, budget="double_t",
+              T1=1, T_max=2000, eps0=w.eps0, eps_adapt=True, eps_kappa=25.0 / 0.1 - 1.0,
+              accept_target=0.65)
+    return w, prob, kw, 12
+
+
+WORKLOADS = {"logreg": logreg_setup, "gauss": gauss_setup, "gauss_sat": gauss_sat_setup,
+             "asmc": asmc_setup}
 
 
 def cpu_baseline(w, res, budget_s: float = 15.0) -> dict:
@@ -88,12 +113,58 @@ def cpu_baseline(w, res, budget_s: float = 15.0) -> dict:
                       f"{dt:.1f} s"}
 
 
+def extra_workload(args, oa, wl, torch) -> int:
+    """The gradient (mixture d = 20, K = 4, N = 8192, T = 256 MALA, checkpoints
+    every 16) and the 256-problem batch (4 rounds, one hipGraph)."""
+    if args.workload == "grad":
+        w = wl.gmm4_d20()
+        T = 256
+        beta = np.linspace(0, 1, T + 1) ** 2
+        eps = w.eps0 / np.sqrt(1 + 8 * beta[1:])
+        prob = oa.Problem.gmm(w.params["means"], w.params["log_scales"], w.ref_sigma2)
+        run = lambda i: oa.logZ_backward(prob, w.N, beta, eps, args.seed + i)
+        steps_per = float(w.N * T)
+        name, cfg = w.name + "_gradient", {"N": w.N, "T": T, "d": w.d, "K": 4}
+    else:
+        specs = wl.batch_problems()
+        probs = []
+        for s in specs:
+            if s["family"] == "gauss":
+                probs.append(oa.Problem.gauss(s["params"]["mu"], s["params"]["sigma2"], 1.0))
+            else:
+                probs.append(oa.Problem.logreg(s["params"]["X"], s["params"]["y"], 1.0))
+        items = [oa.BatchItem(problem=p, N=s["N"], T=s["T"], move=s["move"], eps0=s["eps0"],
+                              eps_adapt=s["eps_adapt"], eps_kappa=s["eps_kappa"], seed=args.seed,
+                              problem_id=i) for i, (p, s) in enumerate(zip(probs, specs))]
+        rounds = 4
+        run = lambda i: oa.run_batch(items, rounds, use_graph=True)
+        steps_per = float(sum(s["N"] * sum(min(max(1, s["T"] >> (rounds - 1)) << k, s["T"])
+                                           for k in range(rounds)) for s in specs))
+        name, cfg = "batch_256_problems", {"problems": len(specs), "rounds": rounds}
+    for i in range(args.warmup):
+        run(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        run(i)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    line = {"metric": "particle-steps/sec and fraction of roofline at matched log Z error",
+            "value": steps_per * args.steps / el, "unit": "particle-steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32 state / f64 arithmetic and weights", "data": "synthetic",
+            "config": dict(workload=name, **cfg), "roofline": None, "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="logreg", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="logreg", choices=sorted(WORKLOADS) + ["grad", "batch"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=20240812)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -122,6 +193,8 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": nbytes, "repeats": 3}), flush=True)
         return 0
+    if args.workload in ("grad", "batch"):
+        return extra_workload(args, oa, wl, torch)
     w, prob, kw, rounds = WORKLOADS[args.workload](oa, wl)
     log(f"workload {w.name}: N={w.N} d={w.d} rounds={rounds}")
     res = None
@@ -143,16 +216,17 @@ def main() -> int:
     if w.family == "logreg":
         achieved = prof["flops"] / (prof["kernel_ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
-                "kernel": "k_oais_logreg", "avg_launch_ms": avg_ms,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
+                "traffic": TRAFFIC.get(args.workload),
+                "kernel": "k_oais_logreg_batch<25, false>", "avg_launch_ms": avg_ms,
                 "launches": prof["launches"]}
     else:
-        rate = prof["particle_steps"] / (prof["kernel_ms"] * 1e-3)
+        rate = prof["particle_steps"] / (prof["kernel_ms"] * 1e-3) if prof["kernel_ms"] else None
         roof = {"bound": "alu", "achieved": rate, "peak": None, "unit": "particle-steps/s",
-                "frac": None, "traffic": None, "kernel": "k_oais_valu",
+                "frac": None, "traffic": None, "kernel": "sweep kernels",
                 "avg_launch_ms": avg_ms, "launches": prof["launches"]}
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and w.family in ("logreg", "gauss"):
         log("timing the CPU oracle on a sample ...")
         cpu = cpu_baseline(w, res)
     line = {
@@ -171,6 +245,7 @@ def main() -> int:
         "config": {"workload": w.name, "N": w.N, "d": w.d, "rounds": rounds,
                    "T_per_round": res["T"].tolist(),
                    "n": int(w.params["X"].shape[0]) if w.family == "logreg" else None,
+                   "n_resample_last_round": int(res["n_resample"][-1]),
                    "logZ_last_round": float(res["logZ"][-1]),
                    "Lambda_hat_last_round": float(res["Lambda"][-1][res["T"][-1]]),
                    "parallelism": "single GPU"},

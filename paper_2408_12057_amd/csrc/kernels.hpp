@@ -147,7 +147,7 @@ struct RoundDev {
     int interp, eps_adapt;
     double eps0, accept_target;
 };
-hipError_t launch_round_merge(const RoundDev* rd, int nprob, hipStream_t st);
+hipError_t launch_round_merge(const RoundDev* rd, int nprob, int Tmax, hipStream_t st);
 hipError_t launch_round_schedule(const RoundDev* rd, int nprob, hipStream_t st);
 
 hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t count,

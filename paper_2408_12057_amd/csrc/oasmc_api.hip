@@ -61,6 +61,7 @@ struct oasmc_handle_s {
     // live kernel timing
     bool prof = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> evpool;  // event pairs around the sweeps of each round
     double prof_ms = 0.0, prof_steps = 0.0, prof_flops = 0.0;
     int64_t prof_launches = 0;
 
@@ -541,8 +542,20 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
     }
     HIP_TRY(hipStreamSynchronize(st));
 
+    int Tmax = 1;
+    for (const auto& q : ps)
+        for (int k = 0; k < R; ++k) Tmax = std::max(Tmax, q.Ts[k]);
+    // per-round event pairs around the sweep kernels (timed runs, not graphs)
+    const bool time_sweeps = h->prof && !use_graph;
+    if (time_sweeps)
+        while ((int)h->evpool.size() < 2 * R) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            h->evpool.push_back(e);
+        }
     auto enqueue = [&](hipStream_t s) -> int {
         for (int k = 0; k < R; ++k) {
+            if (time_sweeps) HIP_TRY(hipEventRecord(h->evpool[2 * k], s));
             for (size_t c = 0; c < classes.size(); ++c) {
                 const int64_t n = (int64_t)items[c].size();
                 const int2* it = reinterpret_cast<const int2*>(dd + d_items[c]);
@@ -561,14 +574,15 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
                     HIP_TRY(launch_oais_valu_batch(classes[c].fam, classes[c].move, sh, b, gw, s));
                 }
             }
+            if (time_sweeps) HIP_TRY(hipEventRecord(h->evpool[2 * k + 1], s));
             const RoundDev* rd = reinterpret_cast<const RoundDev*>(dd + d_round) + (size_t)k * P;
-            HIP_TRY(launch_round_merge(rd, P, s));
+            HIP_TRY(launch_round_merge(rd, P, Tmax, s));
             HIP_TRY(launch_round_schedule(rd, P, s));
         }
         return OASMC_OK;
     };
 
-    if (h->prof) HIP_TRY(hipEventRecord(h->ev0, st));
+    if (h->prof && use_graph) HIP_TRY(hipEventRecord(h->ev0, st));
     if (use_graph) {
         // reuse the instantiated graph when the descriptors are unchanged
         std::vector<char> key(blob);
@@ -601,16 +615,26 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
         const int e = enqueue(st);
         if (e != OASMC_OK) return e;
     }
-    if (h->prof) HIP_TRY(hipEventRecord(h->ev1, st));
+    if (h->prof && use_graph) HIP_TRY(hipEventRecord(h->ev1, st));
     host_out.resize(out_total + sched_total);
     HIP_TRY(hipMemcpyAsync(host_out.data(), ws + out_base, out_total, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(host_out.data() + out_total, ws, sched_total, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (h->prof) {
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-        h->prof_ms += ms;
-        h->prof_launches += 1;
+        // graphs: the whole replay; otherwise the sweep kernels of each round
+        if (use_graph) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+            h->prof_ms += ms;
+            h->prof_launches += 1;
+        } else {
+            for (int k = 0; k < R; ++k) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, h->evpool[2 * k], h->evpool[2 * k + 1]));
+                h->prof_ms += ms;
+                h->prof_launches += (int64_t)classes.size();
+            }
+        }
         for (const auto& q : ps)
             for (int k = 0; k < R; ++k) {
                 h->prof_steps += (double)q.N * q.Ts[k];
@@ -680,6 +704,7 @@ int oasmc_handle_destroy(oasmc_handle* h)
     if (h->ev0) hipEventDestroy(h->ev0);
     if (h->ev1) hipEventDestroy(h->ev1);
     if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
+    for (auto e : h->evpool) hipEventDestroy(e);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     for (auto& b : h->bufs)
         if (b.p) hipFree(b.p);

@@ -23,12 +23,14 @@ __device__ __forceinline__ double d_log_add(double a, double b)
     return m + log1p(exp(-fabs(a - b)));
 }
 
-// Merge the slot partials of one problem (blockIdx.x selects the problem).
+// Merge the slot partials of one problem (blockIdx.x selects the problem,
+// blockIdx.y a range of 256 entries).
 __global__ void k_round_merge(const RoundDev* __restrict__ rd)
 {
     const RoundDev& R = rd[blockIdx.x];
     const int T = R.T;
-    for (int e = threadIdx.x; e <= T; e += blockDim.x) {
+    const int e = blockIdx.y * blockDim.x + threadIdx.x;
+    if (e <= T) {
         double L[3] = {-INFINITY, -INFINITY, -INFINITY};
         double cnt = 0.0;
         for (int64_t s = 0; s < R.S; ++s) {
@@ -49,7 +51,7 @@ __global__ void k_round_merge(const RoundDev* __restrict__ rd)
 
 // Alg. 3 + step sizes + Budget for one problem per workgroup.  Reads
 // beta[T+1], eps[T], log_g[3T], acc[T]; writes beta_next[Tn+1],
-// eps_next[Tn], Lambda[T+1] and *T_next.
+// eps_next[Tn] and Lambda[T+1].
 __global__ void __launch_bounds__(256) k_round_schedule(const RoundDev* __restrict__ rd)
 {
     const RoundDev& R = rd[blockIdx.x];
@@ -190,9 +192,9 @@ __global__ void __launch_bounds__(256) k_round_schedule(const RoundDev* __restri
     }
 }
 
-hipError_t launch_round_merge(const RoundDev* rd, int nprob, hipStream_t st)
+hipError_t launch_round_merge(const RoundDev* rd, int nprob, int Tmax, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_round_merge, dim3(nprob), dim3(256), 0, st, rd);
+    hipLaunchKernelGGL(k_round_merge, dim3(nprob, (Tmax + 1 + 255) / 256), dim3(256), 0, st, rd);
     return hipGetLastError();
 }
 

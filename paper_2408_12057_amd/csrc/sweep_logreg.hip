@@ -615,12 +615,14 @@ size_t logreg_workspace_bytes(const TargetDev& tg, int64_t)
     return (size_t)np * 64 * sizeof(float) + (size_t)np * sizeof(float) + 256;
 }
 
-// The shape used for a launch: OASMC_LOGREG_SHAPE=8 selects the 8-wave
-// workgroup, anything else the pipelined 4-wave one.
+// The shape used for a launch.  FP32 MFMA needs two waves per SIMD to reach
+// its peak (measured: 156 TFLOP/s with two, 145 with one), so the 8-wave
+// workgroup is the default; OASMC_LOGREG_SHAPE=4 selects the pipelined
+// 4-wave one.
 static bool use_pipe()
 {
     const char* v = getenv("OASMC_LOGREG_SHAPE");
-    return !(v && v[0] == '8');
+    return v && v[0] == '4';
 }
 
 size_t logreg_shared_bytes()
