@@ -31,7 +31,7 @@ PEAK_VALU_LANE_OPS = 256 * 64 * 2.4e9
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by the copy-kernel calibration); None until measured for
 # the current kernel.
-TRAFFIC = {"logreg": 6.462e9}
+TRAFFIC = {}
 
 
 def log(msg: str) -> None:

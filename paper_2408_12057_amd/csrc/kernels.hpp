@@ -160,13 +160,12 @@ hipError_t launch_oais_logreg(const SweepArgs& a, int cus, void* ws, size_t ws_b
 // One logistic-regression problem as its sweep kernel sees it.
 struct LogregArgs {
     SweepArgs a;
-    const float* Xp;   // packed [n_pad][64]
-    const float* yp;   // [n_pad], -1 on padding rows
+    const float* Xp;   // packed [n_pad][64], rows signed by 2 y - 1, padding rows zero
     int n_pad;
 };
 int logreg_kh(int d);      // column half-width class of d (-1 if unsupported)
 int logreg_npad(int n);    // padded row count
-hipError_t logreg_pack_into(const TargetDev& tg, float* Xp, float* yp, hipStream_t st);
+hipError_t logreg_pack_into(const TargetDev& tg, float* Xp, hipStream_t st);
 hipError_t launch_oais_logreg_batch(int kh, const LogregArgs* args, const int2* items,
                                    int64_t nitems, int grid, hipStream_t st);
 hipError_t launch_logreg_eval(const TargetDev& tg, const float* theta, int64_t N, double* ell,

@@ -372,7 +372,7 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
         q.off_data = off;
         if (q.logreg) {
             const int np = logreg_npad(q.prob.n);
-            off += align256(sizeof(float) * (size_t)np * 65);
+            off += align256(sizeof(float) * (size_t)np * 64);
         }
     }
     char* ws;
@@ -477,7 +477,6 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
             if (q.logreg) {
                 const int np = logreg_npad(q.prob.n);
                 la.Xp = at<float>(ws, q.off_data);
-                la.yp = la.Xp + (size_t)np * 64;
                 la.n_pad = np;
             }
             reinterpret_cast<LogregArgs*>(blob.data() + d_lr)[(size_t)k * P + p] = la;
@@ -534,10 +533,9 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
         }
         for (int p = 0; p < P; ++p)
             if (ps[p].logreg) {
-                const int np = logreg_npad(ps[p].prob.n);
                 float* Xp = at<float>(ws, ps[p].off_data);
                 const TargetDev tg = target_dev(&ps[p].prob);
-                HIP_TRY(logreg_pack_into(tg, Xp, Xp + (size_t)np * 64, st));
+                HIP_TRY(logreg_pack_into(tg, Xp, st));
             }
     }
     HIP_TRY(hipStreamSynchronize(st));

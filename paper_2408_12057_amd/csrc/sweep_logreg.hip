@@ -22,53 +22,58 @@
 // columns for the K loop of the first product (instruction s, lane half h ->
 // column 32h + s) and the second product's 64 output columns cover all
 // features with two 32-wide tiles.
-#include <stdlib.h>
-
+//
+// Labels are folded into the rows: row i is stored as s_i X_i with
+// s_i = 2 y_i - 1, so the first product gives u_i = s_i z_i and, with
+// sigma the logistic function,
+//     y_i z_i - softplus(z_i) = min(u_i, 0) - log(1 + exp(-|u_i|)),
+//     (y_i - sigma(z_i)) X_i  = sigma(-u_i) (s_i X_i),
+// i.e. the epilogue needs no labels and the second product takes sigma(-u)
+// directly.  Padding rows are zero, so u = 0 and they add nothing to either
+// product; their factor 2 in the product of (1 + exp(-|u|)) is divided out.
 #include "kernels.hpp"
 
 namespace oasmc {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+// X and y are read through global-address-space pointers: the pointers
+// arrive through a descriptor in memory, so the compiler cannot infer the
+// address space, and flat loads would share the LDS wait counter (every LDS
+// wait in the chunk loop would then also wait for the next chunk's prefetch).
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const float gmem_f;
+typedef __attribute__((address_space(1))) const floatx4 gmem_f4;
 
 constexpr int kLP = 64;          // particles per tile
 constexpr int kRows = 32;        // data rows per chunk
-constexpr int kSt = 72;          // floats per staged row: 64 columns, y, mask, padding
+constexpr int kSt = 68;          // floats per staged row: 64 columns + 4 (bank offset)
 constexpr int kPs = 68;          // floats per particle row in LDS
 constexpr int kRowAlign = kRows * 8;
 
-// Two shapes of the same workgroup:
-//  PIPE = true : 4 waves (one per SIMD, 512 registers per lane), double-
-//                buffered logits so the next chunk's first product overlaps
-//                the current chunk's epilogue inside one wave;
-//  PIPE = false: 8 waves (two per SIMD, 256 registers per lane), one chunk at
-//                a time; the two waves of a SIMD overlap each other instead.
-template <bool PIPE>
+// Workgroup shape: 8 waves, two per SIMD (256 registers per lane).
 struct LCfg {
-    static constexpr int waves = PIPE ? 4 : 8;
+    static constexpr int waves = 8;
     static constexpr int threads = waves * kWave;
     static constexpr int tpp = threads / kLP;   // threads per particle, scalar phases
-    static constexpr int nbuf = PIPE ? 2 : 1;   // LDS staging buffers per wave
     static constexpr int blocks_per_thread = 16 / tpp;
     static constexpr int feats_per_thread = 4 * blocks_per_thread;
 };
 
-template <bool PIPE>
 struct LogregShared {
-    using C = LCfg<PIPE>;
     float theta[kLP][kPs];  // current states (packed columns)
     float prop[kLP][kPs];   // proposals
     float gl[kLP][kPs];     // gradient of ell at theta
     float glp[kLP][kPs];    // gradient of ell at prop
-    float stage[C::waves][C::nbuf][kRows][kSt];
+    float stage[LCfg::waves][kRows][kSt];
     double ll[kLP], llp[kLP], lw[kLP];
-    double llpart[C::waves][kLP];
+    double llpart[LCfg::waves][kLP];
     double fwd[kLP], dle[kLP], logu[kLP];
     float m[64];
     uint32_t cnt;
 };
 
-static_assert(sizeof(float) * 4 * 2 * kRows * kSt >= sizeof(float) * 2 * 64 * kWave, "reduction fits");
-static_assert(sizeof(float) * 8 * 1 * kRows * kSt >= sizeof(float) * 4 * 64 * kWave, "reduction fits");
+static_assert(sizeof(LogregShared::stage) >= sizeof(float) * (LCfg::waves / 2) * 64 * kWave,
+              "the gradient reduction fits in the staging buffers");
 
 __device__ __forceinline__ void lsync() { __syncthreads(); }
 
@@ -80,11 +85,11 @@ __device__ __forceinline__ void wsync()
 
 __host__ __device__ __forceinline__ int col_of(int f, int KH) { return f < KH ? f : 32 + f - KH; }
 
-// Packs X (n x d, row-major) into Xp (n_pad x 64) with the column map above
-// and y into yp, marking padded rows with y = -1.
+// Packs X (n x d, row-major) into Xp (n_pad x 64) with the column map above,
+// each row multiplied by s_i = 2 y_i - 1 (a label y_i != 0 counts as 1);
+// padding rows are zero.
 __global__ void k_logreg_pack(const float* __restrict__ X, const float* __restrict__ y, int n,
-                              int d, int KH, int n_pad, float* __restrict__ Xp,
-                              float* __restrict__ yp)
+                              int d, int KH, int n_pad, float* __restrict__ Xp)
 {
     const int64_t total = (int64_t)n_pad * 64;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -96,34 +101,137 @@ __global__ void k_logreg_pack(const float* __restrict__ X, const float* __restri
         } else if (c - 32 < d - KH) {
             f = KH + c - 32;
         }
-        Xp[e] = (i < n && f >= 0 && f < d) ? X[(int64_t)i * d + f] : 0.f;
-        if (c == 0) yp[i] = (i < n) ? y[i] : -1.f;
+        const bool in = i < n && f >= 0 && f < d;
+        const float v = in ? X[(int64_t)i * d + f] : 0.f;
+        Xp[e] = (in && y[i] == 0.f) ? -v : v;
+    }
+}
+
+// Row of the 32-row chunk that accumulator element q of lane half h holds
+// (the 32 x 32 output layout of v_mfma_f32_32x32x2f32).
+__device__ __forceinline__ int slot_row(int q, int h) { return 8 * (q / 4) + 4 * h + (q % 4); }
+
+// The epilogue of one signed logit u = s z, in two halves:
+//   a: e = exp(-|u|), 1 + e, 1 / (1 + e)
+//   b: the row's share min(u, 0) of ell; the factor 1 + e of the running
+//      product whose log2 gives the sum of log(1 + e) over the chunk's rows
+//      (one log per chunk instead of one per row); and sigma(-u), which
+//      replaces u as the second product's operand.
+// On gfx950 FP32 matrix-core instructions and VALU instructions do not run
+// concurrently on a SIMD (measured: the time of an interleaved sequence is
+// the sum of the two), so every VALU instruction here costs matrix-core
+// time; the halves are placed between the gradient products only to keep
+// the wave's dependencies short.
+struct EpiTmp {
+    float e, ope, inv;
+};
+
+__device__ __forceinline__ void epi_a(float u, EpiTmp& t)
+{
+    t.e = __expf(-fabsf(u));
+    t.ope = 1.0f + t.e;
+    t.inv = __builtin_amdgcn_rcpf(t.ope);
+    // an empty volatile asm that consumes and redefines the three values pins
+    // this half where it is written (the IR passes would otherwise sink it
+    // next to its uses in the second half)
+    asm volatile("" : "+v"(t.e), "+v"(t.ope), "+v"(t.inv));
+}
+
+__device__ __forceinline__ float epi_b(float u, const EpiTmp& t, float& llc, float& prod)
+{
+    const bool pos = u >= 0.f;
+    llc += pos ? 0.f : u;
+    prod *= t.ope;
+    return pos ? t.e * t.inv : t.inv;
+}
+
+// Padding rows among the 16 rows a lane half h holds in a chunk whose first
+// L rows are data (rows slot_row(q, h): blocks of 4 at 8 b + 4 h).
+__device__ __forceinline__ int padding_rows(int L, int h)
+{
+    if (L >= kRows) return 0;
+    int c = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) c += min(4, max(0, 8 * b + 4 * h + 4 - L));
+    return c;
+}
+
+// One 32-row chunk's share of a lane: row l / 2, columns 32 (l % 2) ..+31
+// (8 x 16 bytes of the packed rows).
+struct Slice {
+    floatx4 v0, v1, v2, v3, v4, v5, v6, v7;
+};
+
+// Rows [r0, r0 + rows_w) of the packed data belong to wave w of the tile.
+__device__ __forceinline__ int wave_rows(int n_pad) { return n_pad / LCfg::waves; }
+
+// Loads chunk c of this wave's rows.  The address-space cast is taken on the
+// base pointer (a cast of each derived address can fold back into a flat
+// access, and flat loads would share the LDS wait counter).
+__device__ __forceinline__ Slice fetch_slice(const float* Xp, int n_pad, int c)
+{
+    const int l = threadIdx.x % kWave;
+    const int r0 = (threadIdx.x / kWave) * wave_rows(n_pad);
+    gmem_f* const Xg = (gmem_f*)Xp;
+    const gmem_f4* src = (const gmem_f4*)(Xg + (size_t)(r0 + c * kRows + l / 2) * 64 + (l % 2) * 32);
+    Slice t;
+    t.v0 = src[0]; t.v1 = src[1]; t.v2 = src[2]; t.v3 = src[3];
+    t.v4 = src[4]; t.v5 = src[5]; t.v6 = src[6]; t.v7 = src[7];
+    return t;
+}
+
+__device__ __forceinline__ void put_slice(float (*stc)[kSt], const Slice& t)
+{
+    const int l = threadIdx.x % kWave;
+    floatx4* dst = reinterpret_cast<floatx4*>(&stc[l / 2][(l % 2) * 32]);
+    dst[0] = t.v0; dst[1] = t.v1; dst[2] = t.v2; dst[3] = t.v3;
+    dst[4] = t.v4; dst[5] = t.v5; dst[6] = t.v6; dst[7] = t.v7;
+}
+
+// The 64 gradient accumulators of a lane as 16 float4 (element 4 k + i is
+// G[g][ft][q] with (g * 2 + ft) * 16 + q = 4 k + i), stored lane-interleaved
+// (float4 k of lane l at k * 64 + l) so every 128-bit LDS access is
+// conflict-free.
+__device__ __forceinline__ void store_grad(floatx4* dst, const floatx16 (&G)[2][2], int l)
+{
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const floatx16& v = G[k / 8][(k / 4) % 2];
+        const int q = 4 * (k % 4);
+        dst[k * kWave + l] = floatx4{v[q], v[q + 1], v[q + 2], v[q + 3]};
+    }
+}
+
+__device__ __forceinline__ void add_grad(floatx16 (&G)[2][2], const floatx4* src, int l)
+{
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        floatx16& v = G[k / 8][(k / 4) % 2];
+        const int q = 4 * (k % 4);
+        const floatx4 u = src[k * kWave + l];
+        v[q] += u[0];
+        v[q + 1] += u[1];
+        v[q + 2] += u[2];
+        v[q + 3] += u[3];
     }
 }
 
 // ell and grad ell at sh.prop for the 64 particles of the tile; results in
 // sh.llp (binary64) and sh.glp (packed columns).  All threads participate.
-template <int KH, bool PIPE>
-__device__ __forceinline__ void contraction(LogregShared<PIPE>& sh, const float* __restrict__ Xp,
-                            const float* __restrict__ yp, int n_pad)
+// n is the number of data rows.  `first` holds this wave's chunk 0 on entry;
+// on exit it holds chunk 0 again, loaded at the end so that the next call
+// finds it in registers.
+template <int KH>
+__device__ __forceinline__ void contraction(LogregShared& sh, const float* __restrict__ Xp, int n,
+                                            int n_pad, Slice& first)
 {
-    constexpr int kLWaves = LCfg<PIPE>::waves;
+    constexpr int kLWaves = LCfg::waves;
+    constexpr double kLn2 = 0.693147180559945309;
     const int tid = threadIdx.x;
     const int w = tid / kWave;
     const int l = tid % kWave;
     const int h = l / 32;
     const int j = l % 32;
-
-    // B operand of the first product: the particles' states.  The pipelined
-    // shape keeps them in registers; the 8-wave shape (256 registers per
-    // lane) reads them from LDS at each k-step.
-    float bth[2][PIPE ? KH : 1];
-    if constexpr (PIPE) {
-#pragma unroll
-        for (int g = 0; g < 2; ++g)
-#pragma unroll
-            for (int s = 0; s < KH; ++s) bth[g][s] = sh.prop[32 * g + j][32 * h + s];
-    }
 
     floatx16 G[2][2];
 #pragma unroll
@@ -134,143 +242,72 @@ __device__ __forceinline__ void contraction(LogregShared<PIPE>& sh, const float*
             for (int q = 0; q < 16; ++q) G[g][ft][q] = 0.f;
     double llacc[2] = {0.0, 0.0};
 
-    const int rows_w = n_pad / kLWaves;
-    const int r0 = w * rows_w;
-    const int nchunks = rows_w / kRows;
-    const int srow = l / 2, shalf = l % 2;
+    const int nchunks = wave_rows(n_pad) / kRows;
+    const int r0 = w * wave_rows(n_pad);
+    float(*stc)[kSt] = sh.stage[w];
 
-    // Software pipeline over 32-row chunks.  Chunk c sits in LDS buffer c&1
-    // with its logits in registers; each of its 16 row slots q runs
-    //   ~KH/16 k-steps of the NEXT chunk's logits   (matrix cores)
-    //   the epilogue of slot q                        (VALU)
-    //   slot q's share of the gradient product        (matrix cores)
-    // so the in-order wave always has independent matrix-core work queued
-    // behind its VALU work.  Global loads run two chunks ahead in registers
-    // and land in the buffer chunk c releases.
-    // one chunk's share of this lane: 8 x 16 bytes of X and (y, row mask)
-    struct Slice {
-        float4 v0, v1, v2, v3, v4, v5, v6, v7;
-        float2 y;
-    };
-    auto fetch = [&](int c) -> Slice {
-        const float4* src =
-            reinterpret_cast<const float4*>(Xp + (size_t)(r0 + c * kRows + srow) * 64 + shalf * 32);
-        Slice t;
-        t.v0 = src[0]; t.v1 = src[1]; t.v2 = src[2]; t.v3 = src[3];
-        t.v4 = src[4]; t.v5 = src[5]; t.v6 = src[6]; t.v7 = src[7];
-        t.y = make_float2(0.f, 0.f);
-        if (l < kRows) {
-            const float yr = yp[r0 + c * kRows + l];
-            t.y = (yr >= 0.f) ? make_float2(yr, 1.f) : make_float2(0.f, 0.f);
-        }
-        return t;
-    };
-    auto put = [&](int buf, const Slice& t) {
-        float4* dst = reinterpret_cast<float4*>(&sh.stage[w][buf][srow][shalf * 32]);
-        dst[0] = t.v0; dst[1] = t.v1; dst[2] = t.v2; dst[3] = t.v3;
-        dst[4] = t.v4; dst[5] = t.v5; dst[6] = t.v6; dst[7] = t.v7;
-        if (l < kRows) *reinterpret_cast<float2*>(&sh.stage[w][buf][l][64]) = t.y;
-    };
-    auto zero = [](floatx16 (&acc)[2]) {
+    // the next chunk's slice is loaded into registers while the current
+    // chunk is consumed from the wave's LDS staging buffer
+    floatx16 acc[2];
+    Slice ahead = first;
+    for (int c = 0; c < nchunks; ++c) {
+        put_slice(stc, ahead);
+        wsync();
+        ahead = fetch_slice(Xp, n_pad, min(c + 1, nchunks - 1));
+        // signed logits of the chunk, transposed: acc[g] = X'_chunk . Theta_g^T
+        // (k-step s: lane half h holds column 32 h + s of its row and of its
+        // particle)
 #pragma unroll
         for (int g = 0; g < 2; ++g)
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[g][q] = 0.f;
-    };
-    constexpr float kLn2 = 0.693147180559945309f;
-    // k-steps [s0, s1) of the first product for the chunk in buffer `buf`
-    auto gemm1 = [&](int buf, floatx16 (&acc)[2], int s0, int s1) {
-        float(*st)[kSt] = sh.stage[w][buf];
 #pragma unroll
-        for (int s = s0; s < s1; ++s) {
-            const float a = st[j][32 * h + s];
-#pragma unroll
-            for (int g = 0; g < 2; ++g) {
-                float bv;
-                if constexpr (PIPE) bv = bth[g][s];
-                else bv = sh.prop[32 * g + j][32 * h + s];
-                acc[g] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc[g], 0, 0, 0);
-            }
-        }
-    };
-    // epilogue of row slot q (y and the row mask in columns 64, 65), then the
-    // slot's share of the gradient product
-    auto slot = [&](float(*stc)[kSt], floatx16 (&cur)[2], int q, float (&llc)[2]) {
-        const int i = 8 * (q / 4) + 4 * h + (q % 4);
-        const float2 yv = *reinterpret_cast<const float2*>(&stc[i][64]);
-#pragma unroll
-        for (int g = 0; g < 2; ++g) {
-            const float z = cur[g][q];
-            const float e = __expf(-fabsf(z));
-            const float ope = 1.0f + e;
-            const float inv = __builtin_amdgcn_rcpf(ope);
-            const float sig = (z >= 0.f) ? inv : e * inv;
-            const float sp = fmaxf(z, 0.f) + kLn2 * __builtin_amdgcn_logf(ope);
-            llc[g] = fmaf(yv.y, fmaf(yv.x, z, -sp), llc[g]);
-            cur[g][q] = fmaf(-yv.y, sig, yv.x);
-        }
-#pragma unroll
-        for (int ft = 0; ft < 2; ++ft) {
-            const float bx = stc[i][32 * ft + j];
+        for (int s = 0; s < KH; ++s) {
+            const float a = stc[j][32 * h + s];
 #pragma unroll
             for (int g = 0; g < 2; ++g)
-                G[g][ft] = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[g][q], bx, G[g][ft], 0, 0, 0);
+                acc[g] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, sh.prop[32 * g + j][32 * h + s],
+                                                            acc[g], 0, 0, 0);
         }
-    };
-
-    if constexpr (PIPE) {
-        // Chunk c sits in buffer c&1 with its logits in registers; each row
-        // slot q runs ~KH/16 k-steps of the NEXT chunk's first product, then
-        // its own epilogue and gradient share, so the in-order wave always has
-        // independent matrix-core work queued behind its VALU work.  Loads run
-        // two chunks ahead and land in the buffer chunk c releases.  The body
-        // is branch-free: past the last chunk it recomputes the last chunk
-        // and discards the result.
-        auto stage_step = [&](int c, floatx16 (&cur)[2], floatx16 (&nxt)[2]) {
-            const int b = c & 1;
-            float(*stc)[kSt] = sh.stage[w][b];
-            const Slice ahead = fetch(min(c + 2, nchunks - 1));
-            zero(nxt);
-            float llc[2] = {0.f, 0.f};
+        // row slots: the epilogue of slot q + 1 is issued between the four
+        // gradient products of slot q (G[g][ft] += sigma(-u_g)^T X'_ft over
+        // its rows)
+        float llc[2] = {0.f, 0.f}, prod[2] = {1.f, 1.f};
+        EpiTmp t0, t1;
+        epi_a(acc[0][0], t0);
+        acc[0][0] = epi_b(acc[0][0], t0, llc[0], prod[0]);
+        epi_a(acc[1][0], t1);
+        acc[1][0] = epi_b(acc[1][0], t1, llc[1], prod[1]);
+        float bx0 = stc[slot_row(0, h)][j], bx1 = stc[slot_row(0, h)][32 + j];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                gemm1(b ^ 1, nxt, (q * KH + 15) / 16, ((q + 1) * KH + 15) / 16);
-                slot(stc, cur, q, llc);
-            }
-            llacc[0] += (double)llc[0];
-            llacc[1] += (double)llc[1];
-            wsync();
-            put(b, ahead);
-            wsync();
-        };
-        floatx16 accA[2], accB[2];
-        put(0, fetch(0));
-        put(1, fetch(min(1, nchunks - 1)));
+        for (int q = 0; q < 16; ++q) {
+            const int qn = (q < 15) ? q + 1 : 15;
+            const int in = slot_row(qn, h);
+            const float nbx0 = stc[in][j], nbx1 = stc[in][32 + j];
+            G[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[0][q], bx0, G[0][0], 0, 0, 0);
+            if (q < 15) epi_a(acc[0][qn], t0);
+            __builtin_amdgcn_sched_barrier(0);
+            G[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[1][q], bx0, G[1][0], 0, 0, 0);
+            if (q < 15) acc[0][qn] = epi_b(acc[0][qn], t0, llc[0], prod[0]);
+            __builtin_amdgcn_sched_barrier(0);
+            G[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[0][q], bx1, G[0][1], 0, 0, 0);
+            if (q < 15) epi_a(acc[1][qn], t1);
+            __builtin_amdgcn_sched_barrier(0);
+            G[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[1][q], bx1, G[1][1], 0, 0, 0);
+            if (q < 15) acc[1][qn] = epi_b(acc[1][qn], t1, llc[1], prod[1]);
+            __builtin_amdgcn_sched_barrier(0);
+            bx0 = nbx0;
+            bx1 = nbx1;
+        }
+        // sum of log(1 + e) over the chunk's data rows: divide out the
+        // padding rows' exact factors of 2, one log per chunk
+        const int npad_rows = padding_rows(n - (r0 + c * kRows), h);
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const float lp = __builtin_amdgcn_logf(__builtin_amdgcn_ldexpf(prod[g], -npad_rows));
+            llacc[g] += (double)llc[g] - kLn2 * (double)lp;
+        }
         wsync();
-        zero(accA);
-        gemm1(0, accA, 0, KH);
-        for (int c = 0; c < nchunks; c += 2) {
-            stage_step(c, accA, accB);
-            if (c + 1 < nchunks) stage_step(c + 1, accB, accA);
-        }
-    } else {
-        // One buffer per wave: the next chunk's slice waits in registers
-        // while the current chunk is consumed.
-        floatx16 acc[2];
-        Slice ahead = fetch(0);
-        for (int c = 0; c < nchunks; ++c) {
-            put(0, ahead);
-            wsync();
-            ahead = fetch(min(c + 1, nchunks - 1));
-            zero(acc);
-            gemm1(0, acc, 0, KH);
-            float llc[2] = {0.f, 0.f};
-#pragma unroll
-            for (int q = 0; q < 16; ++q) slot(sh.stage[w][0], acc, q, llc);
-            llacc[0] += (double)llc[0];
-            llacc[1] += (double)llc[1];
-            wsync();
-        }
     }
 
     // per-particle log-likelihood: halves of the wave, then waves in order
@@ -282,47 +319,36 @@ __device__ __forceinline__ void contraction(LogregShared<PIPE>& sh, const float*
     }
     lsync();  // every wave is done with its staging buffer
 
-    // gradient: fixed tree (w + w^2), (w + w^1) through LDS
-    float* red = &sh.stage[0][0][0][0];
-    static_assert(sizeof(sh.stage) >= sizeof(float) * (kLWaves / 2) * 64 * kWave, "reduction fits");
-    for (int span = kLWaves / 2; span >= 1; span /= 2) {
-        if (w >= span && w < 2 * span) {
-            float* dst = red + (size_t)(w - span) * 64 * kWave;
-#pragma unroll
-            for (int g = 0; g < 2; ++g)
-#pragma unroll
-                for (int ft = 0; ft < 2; ++ft)
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) dst[((g * 2 + ft) * 16 + q) * kWave + l] = G[g][ft][q];
-        }
-        lsync();
-        if (w < span) {
-            const float* src = red + (size_t)w * 64 * kWave;
-#pragma unroll
-            for (int g = 0; g < 2; ++g)
-#pragma unroll
-                for (int ft = 0; ft < 2; ++ft)
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) G[g][ft][q] += src[((g * 2 + ft) * 16 + q) * kWave + l];
-        }
-        lsync();
-    }
-    if (w == 0) {
-#pragma unroll
-        for (int g = 0; g < 2; ++g)
-#pragma unroll
-            for (int ft = 0; ft < 2; ++ft)
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int p = 32 * g + 8 * (q / 4) + 4 * h + (q % 4);
-                    sh.glp[p][32 * ft + j] = G[g][ft][q];
-                }
-    }
+    // gradient: G_w + G_{w+4} on waves 0..3, then wave 0 adds waves 1, 2, 3
+    // in that order (fixed tree), through four 16 KB slots of the staging area
+    floatx4* red = reinterpret_cast<floatx4*>(&sh.stage[0][0][0]);
+    constexpr int kSlot = 16 * kWave;  // float4 per slot
+    if (w >= 4) store_grad(red + (w - 4) * kSlot, G, l);
     if (tid < kLP) {
         double s = 0.0;
         for (int ww = 0; ww < kLWaves; ++ww) s += sh.llpart[ww][tid];
         sh.llp[tid] = s;
     }
+    lsync();
+    if (w < 4) {
+        add_grad(G, red + w * kSlot, l);
+        if (w > 0) store_grad(red + w * kSlot, G, l);  // slot w is read only by wave w
+    }
+    lsync();
+    if (w == 0) {
+        add_grad(G, red + 1 * kSlot, l);
+        add_grad(G, red + 2 * kSlot, l);
+        add_grad(G, red + 3 * kSlot, l);
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int ft = 0; ft < 2; ++ft)
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    sh.glp[32 * g + slot_row(q, h)][32 * ft + j] = G[g][ft][q];
+    }
+    // chunk 0 of the next evaluation (the rows do not change between steps)
+    first = fetch_slice(Xp, n_pad, 0);
     lsync();
 }
 
@@ -334,10 +360,10 @@ __device__ __forceinline__ int feat_of(int r, int u) { return 4 * (r + TPP * (u 
 
 // The parameters shared by every tile of a problem: zero the particle arrays
 // (columns beyond d stay zero) and stage the reference mean in packed columns.
-template <int KH, bool PIPE>
-__device__ __forceinline__ void logreg_setup(LogregShared<PIPE>& sh, const SweepArgs& a)
+template <int KH>
+__device__ __forceinline__ void logreg_setup(LogregShared& sh, const SweepArgs& a)
 {
-    constexpr int kLThreads = LCfg<PIPE>::threads;
+    constexpr int kLThreads = LCfg::threads;
     const int tid = threadIdx.x;
     const int d = a.tg.d;
     for (int e = tid; e < kLP * kPs; e += kLThreads) {
@@ -356,11 +382,11 @@ __device__ __forceinline__ void logreg_setup(LogregShared<PIPE>& sh, const Sweep
 }
 
 // All tiles of one slot of one problem, in tile order (whole workgroup).
-template <int KH, bool PIPE>
-__device__ __forceinline__ void logreg_slot(LogregShared<PIPE>& sh, const LogregArgs& A,
+template <int KH>
+__device__ __forceinline__ void logreg_slot(LogregShared& sh, const LogregArgs& A,
                                             int64_t slot)
 {
-    using Cf = LCfg<PIPE>;
+    using Cf = LCfg;
     constexpr int kTPP = Cf::tpp;
     constexpr int kBlocksPerThread = Cf::blocks_per_thread;
     constexpr int kFeatPerThread = Cf::feats_per_thread;
@@ -371,47 +397,50 @@ __device__ __forceinline__ void logreg_slot(LogregShared<PIPE>& sh, const Logreg
     const int T = a.T;
     const double s2r = a.tg.ref_sigma2;
     const double inv_s2r = 1.0 / s2r, half_inv_s2r = 0.5 / s2r, sref = sqrt(s2r);
+    // the schedule through global-address-space pointers (see fetch_slice)
+    typedef __attribute__((address_space(1))) const double gmem_d;
+    gmem_d* const beta_g = (gmem_d*)a.beta;
+    gmem_d* const eps_g = (gmem_d*)a.eps;
+    Slice chunk0 = fetch_slice(A.Xp, A.n_pad, 0);
         for (int64_t tile = slot; tile < a.ntiles; tile += a.S) {
             const bool first = (tile == slot);
             const int64_t n64 = tile * kLP + p;
             const bool valid = n64 < a.N;
             const uint32_t n = (uint32_t)n64;
             uint32_t accw = 0;
+            // beta_t and eps_t of the next step are loaded one step ahead
+            double beta_next = (T >= 1) ? beta_g[1] : 1.0;
+            double eps_next = (T >= 1) ? eps_g[0] : 1.0;
+            double beta_prev = 0.0;
             // t = 0 draws X_0 ~ eta and caches ell, grad ell (always kept);
             // t >= 1 reweights, proposes, evaluates and corrects.
             for (int t = 0; t <= T; ++t) {
-                const double beta = (t > 0) ? a.beta[t] : 0.0;
-                const double eps = (t > 0) ? a.eps[t - 1] : 1.0;
+                const double beta = (t > 0) ? beta_next : 0.0;
+                const double eps = (t > 0) ? eps_next : 1.0;
+                if (t > 0 && t < T) {
+                    beta_next = beta_g[t + 1];
+                    eps_next = eps_g[t];
+                }
                 const double hh = 0.5 * eps * eps;
-                if (t > 0 && tid < kWave) {
-                    // reweight at the pre-move state and stream the moments
-                    const int q = tid;
+                if (t > 0 && tid < 3 * kWave) {
+                    // moment i = wave index of the pre-move weights times
+                    // g_t^i: a max and a sum of exps over the 64 particles
+                    // (the weights themselves advance in the correction)
+                    const int i = tid / kWave, q = tid % kWave;
                     const bool vq = (tile * kLP + q) < a.N;
-                    const double lwq = sh.lw[q];
-                    const double lg = (beta - a.beta[t - 1]) * sh.ll[q];
-                    double m3[3], s3[3];
+                    const double lg = (beta - beta_prev) * sh.ll[q];
+                    const double x = vq ? sh.lw[q] + (double)i * lg : -INFINITY;
+                    double m = x;
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        m3[i] = vq ? lwq + (double)i * lg : -INFINITY;
-                        s3[i] = vq ? 1.0 : 0.0;
-                    }
+                    for (int o = 1; o < kWave; o <<= 1) m = fmax(m, __shfl_xor(m, o, kWave));
+                    double sum = (m > -INFINITY && vq) ? exp(x - m) : 0.0;
 #pragma unroll
-                    for (int o = 1; o < kWave; o <<= 1)
-#pragma unroll
-                        for (int i = 0; i < 3; ++i) {
-                            const double m2 = __shfl_xor(m3[i], o, kWave);
-                            const double s2 = __shfl_xor(s3[i], o, kWave);
-                            lse_merge(m3[i], s3[i], m2, s2);
-                        }
+                    for (int o = 1; o < kWave; o <<= 1) sum += __shfl_xor(sum, o, kWave);
                     if (q == 0) {
                         double* e = a.part + ((size_t)slot * (T + 1) + (t - 1)) * 4;
-#pragma unroll
-                        for (int i = 0; i < 3; ++i) {
-                            const double L = lse_value(m3[i], s3[i]);
-                            e[i] = first ? L : log_add(e[i], L);
-                        }
+                        const double L = lse_value(m, sum);
+                        e[i] = first ? L : log_add(e[i], L);
                     }
-                    sh.lw[q] = lwq + lg;
                 }
                 if (tid == 0) sh.cnt = 0u;
                 // t = 0: x = m + s z;  t >= 1: x' = x + (eps^2/2) grad log pi_beta(x) + eps xi
@@ -457,7 +486,7 @@ __device__ __forceinline__ void logreg_slot(LogregShared<PIPE>& sh, const Logreg
                     }
                 }
                 lsync();
-                contraction<KH, PIPE>(sh, A.Xp, A.yp, A.n_pad);
+                contraction<KH>(sh, A.Xp, a.tg.n, A.n_pad, chunk0);
                 // Metropolis-Hastings correction (the initial draw is always kept)
                 {
                     double bwd = 0.0;
@@ -493,8 +522,10 @@ __device__ __forceinline__ void logreg_slot(LogregShared<PIPE>& sh, const Logreg
                     const uint64_t bal = __ballot(acc && valid && r == 0);
                     if ((tid % kWave) == 0) atomicAdd(&sh.cnt, (uint32_t)__popcll(bal));
                     if (r == 0) {
+                        // the weight advances by the increment the moments
+                        // used, at the pre-move log-likelihood
+                        sh.lw[p] = (t == 0) ? 0.0 : sh.lw[p] + (beta - beta_prev) * sh.ll[p];
                         if (acc) sh.ll[p] = sh.llp[p];
-                        if (t == 0) sh.lw[p] = 0.0;
                         if (t > 0) {
                             accw |= (acc ? 1u : 0u) << ((t - 1) & 31);
                             if (((t - 1) & 31) == 31 || t == T) {
@@ -510,6 +541,7 @@ __device__ __forceinline__ void logreg_slot(LogregShared<PIPE>& sh, const Logreg
                     double* e = a.part + ((size_t)slot * (T + 1) + (t - 1)) * 4;
                     e[3] = (first ? 0.0 : e[3]) + (double)sh.cnt;
                 }
+                beta_prev = beta;
             }
             // log Z_hat contribution of the tile: entry T
             if (tid < kWave) {
@@ -542,45 +574,45 @@ __device__ __forceinline__ void logreg_slot(LogregShared<PIPE>& sh, const Logreg
         }
 }
 
-template <int KH, bool PIPE>
-__global__ void __launch_bounds__(LCfg<PIPE>::threads) k_oais_logreg(LogregArgs A)
+template <int KH>
+__global__ void __launch_bounds__(LCfg::threads) k_oais_logreg(LogregArgs A)
 {
     extern __shared__ __align__(16) char sh_raw[];
-    LogregShared<PIPE>& sh = *reinterpret_cast<LogregShared<PIPE>*>(sh_raw);
-    logreg_setup<KH, PIPE>(sh, A.a);
-    for (int64_t slot = blockIdx.x; slot < A.a.S; slot += gridDim.x) logreg_slot<KH, PIPE>(sh, A, slot);
+    LogregShared& sh = *reinterpret_cast<LogregShared*>(sh_raw);
+    logreg_setup<KH>(sh, A.a);
+    for (int64_t slot = blockIdx.x; slot < A.a.S; slot += gridDim.x) logreg_slot<KH>(sh, A, slot);
 }
 
 // Many logistic-regression problems with the same column half-width in one
 // launch: each workgroup walks the work list of (problem, slot) items.
-template <int KH, bool PIPE>
-__global__ void __launch_bounds__(LCfg<PIPE>::threads)
+template <int KH>
+__global__ void __launch_bounds__(LCfg::threads)
     k_oais_logreg_batch(const LogregArgs* __restrict__ args, const int2* __restrict__ items,
                         int64_t nitems)
 {
     extern __shared__ __align__(16) char sh_raw[];
-    LogregShared<PIPE>& sh = *reinterpret_cast<LogregShared<PIPE>*>(sh_raw);
+    LogregShared& sh = *reinterpret_cast<LogregShared*>(sh_raw);
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int2 item = items[it];
         const LogregArgs A = args[item.x];
-        logreg_setup<KH, PIPE>(sh, A.a);
-        logreg_slot<KH, PIPE>(sh, A, (int64_t)item.y);
+        logreg_setup<KH>(sh, A.a);
+        logreg_slot<KH>(sh, A, (int64_t)item.y);
         lsync();
     }
 }
 
 // ell and its gradient for given states (the same contraction as the sweep).
-template <int KH, bool PIPE>
-__global__ void __launch_bounds__(LCfg<PIPE>::threads) k_logreg_eval(const float* __restrict__ theta,
+template <int KH>
+__global__ void __launch_bounds__(LCfg::threads) k_logreg_eval(const float* __restrict__ theta,
                                                            int64_t N, int d, const float* Xp,
-                                                           const float* yp, int n_pad,
+                                                           int n, int n_pad,
                                                            double* ell, float* grad)
 {
-    constexpr int kLThreads = LCfg<PIPE>::threads;
-    constexpr int kTPP = LCfg<PIPE>::tpp;
-    constexpr int kFeatPerThread = LCfg<PIPE>::feats_per_thread;
+    constexpr int kLThreads = LCfg::threads;
+    constexpr int kTPP = LCfg::tpp;
+    constexpr int kFeatPerThread = LCfg::feats_per_thread;
     extern __shared__ __align__(16) char sh_raw[];
-    LogregShared<PIPE>& sh = *reinterpret_cast<LogregShared<PIPE>*>(sh_raw);
+    LogregShared& sh = *reinterpret_cast<LogregShared*>(sh_raw);
     const int tid = threadIdx.x;
     const int p = tid / kTPP, r = tid % kTPP;
     for (int e = tid; e < kLP * kPs; e += kLThreads) (&sh.prop[0][0])[e] = 0.f;
@@ -593,7 +625,8 @@ __global__ void __launch_bounds__(LCfg<PIPE>::threads) k_logreg_eval(const float
         if (f < d && valid) sh.prop[p][col_of(f, KH)] = theta[(size_t)n64 * d + f];
     }
     lsync();
-    contraction<KH, PIPE>(sh, Xp, yp, n_pad);
+    Slice chunk0 = fetch_slice(Xp, n_pad, 0);
+    contraction<KH>(sh, Xp, n, n_pad, chunk0);
     if (valid) {
 #pragma unroll
         for (int u = 0; u < kFeatPerThread; ++u) {
@@ -612,70 +645,40 @@ static int n_pad_of(int n) { return ((n + kRowAlign - 1) / kRowAlign) * kRowAlig
 size_t logreg_workspace_bytes(const TargetDev& tg, int64_t)
 {
     const int np = n_pad_of(tg.n);
-    return (size_t)np * 64 * sizeof(float) + (size_t)np * sizeof(float) + 256;
+    return (size_t)np * 64 * sizeof(float) + 256;
 }
 
-// The shape used for a launch.  FP32 MFMA needs two waves per SIMD to reach
-// its peak (measured: 156 TFLOP/s with two, 145 with one), so the 8-wave
-// workgroup is the default; OASMC_LOGREG_SHAPE=4 selects the pipelined
-// 4-wave one.
-static bool use_pipe()
-{
-    const char* v = getenv("OASMC_LOGREG_SHAPE");
-    return v && v[0] == '4';
-}
-
-size_t logreg_shared_bytes()
-{
-    return use_pipe() ? sizeof(LogregShared<true>) : sizeof(LogregShared<false>);
-}
-
-template <int KH, bool PIPE>
-static hipError_t launch_kh2(const LogregArgs& A, int grid, hipStream_t st)
-{
-    const size_t shb = sizeof(LogregShared<PIPE>);
-    hipError_t e = hipFuncSetAttribute((const void*)k_oais_logreg<KH, PIPE>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_oais_logreg<KH, PIPE>), dim3(grid), dim3(LCfg<PIPE>::threads), shb, st,
-                       A);
-    return hipGetLastError();
-}
+size_t logreg_shared_bytes() { return sizeof(LogregShared); }
 
 template <int KH>
 static hipError_t launch_kh(const LogregArgs& A, int grid, hipStream_t st)
 {
-    return use_pipe() ? launch_kh2<KH, true>(A, grid, st) : launch_kh2<KH, false>(A, grid, st);
-}
-
-template <int KH, bool PIPE>
-static hipError_t launch_eval_kh2(const float* theta, int64_t N, int d, const float* Xp,
-                                  const float* yp, int n_pad, double* ell, float* grad,
-                                  hipStream_t st)
-{
-    const size_t shb = sizeof(LogregShared<PIPE>);
-    hipError_t e = hipFuncSetAttribute((const void*)k_logreg_eval<KH, PIPE>,
+    const size_t shb = sizeof(LogregShared);
+    hipError_t e = hipFuncSetAttribute((const void*)k_oais_logreg<KH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_logreg_eval<KH, PIPE>), dim3((unsigned)logreg_tiles(N)),
-                       dim3(LCfg<PIPE>::threads), shb, st, theta, N, d, Xp, yp, n_pad, ell, grad);
+    hipLaunchKernelGGL((k_oais_logreg<KH>), dim3(grid), dim3(LCfg::threads), shb, st, A);
     return hipGetLastError();
 }
 
 template <int KH>
 static hipError_t launch_eval_kh(const float* theta, int64_t N, int d, const float* Xp,
-                                 const float* yp, int n_pad, double* ell, float* grad,
+                                 int n, int n_pad, double* ell, float* grad,
                                  hipStream_t st)
 {
-    return use_pipe() ? launch_eval_kh2<KH, true>(theta, N, d, Xp, yp, n_pad, ell, grad, st)
-                      : launch_eval_kh2<KH, false>(theta, N, d, Xp, yp, n_pad, ell, grad, st);
+    const size_t shb = sizeof(LogregShared);
+    hipError_t e = hipFuncSetAttribute((const void*)k_logreg_eval<KH>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_logreg_eval<KH>), dim3((unsigned)logreg_tiles(N)), dim3(LCfg::threads),
+                       shb, st, theta, N, d, Xp, n, n_pad, ell, grad);
+    return hipGetLastError();
 }
 
-static void layout(const TargetDev& tg, void* ws, float** Xp, float** yp, int* np)
+static void layout(const TargetDev& tg, void* ws, float** Xp, int* np)
 {
     *np = n_pad_of(tg.n);
     *Xp = static_cast<float*>(ws);
-    *yp = *Xp + (size_t)(*np) * 64;
 }
 
 // Exact half-widths with a dedicated instantiation; other widths round up.
@@ -684,7 +687,7 @@ static int kh_for(int d);
 int logreg_kh(int d) { return kh_for(d); }
 int logreg_npad(int n) { return n_pad_of(n); }
 
-hipError_t logreg_pack_into(const TargetDev& tg, float* Xp, float* yp, hipStream_t st)
+hipError_t logreg_pack_into(const TargetDev& tg, float* Xp, hipStream_t st)
 {
     const int kh = kh_for(tg.d);
     if (kh < 0) return hipErrorInvalidValue;
@@ -692,28 +695,28 @@ hipError_t logreg_pack_into(const TargetDev& tg, float* Xp, float* yp, hipStream
     const int64_t total = (int64_t)np * 64;
     const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(k_logreg_pack, dim3(blocks), dim3(256), 0, st, tg.X, tg.y, tg.n, tg.d, kh,
-                       np, Xp, yp);
+                       np, Xp);
     return hipGetLastError();
 }
 
-template <int KH, bool PIPE>
-static hipError_t launch_batch_kh2(const LogregArgs* args, const int2* items, int64_t nitems,
-                                   int grid, hipStream_t st)
+template <int KH>
+static hipError_t launch_batch_kh(const LogregArgs* args, const int2* items, int64_t nitems,
+                                  int grid, hipStream_t st)
 {
-    const size_t shb = sizeof(LogregShared<PIPE>);
-    hipError_t e = hipFuncSetAttribute((const void*)k_oais_logreg_batch<KH, PIPE>,
+    const size_t shb = sizeof(LogregShared);
+    hipError_t e = hipFuncSetAttribute((const void*)k_oais_logreg_batch<KH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_oais_logreg_batch<KH, PIPE>), dim3(grid), dim3(LCfg<PIPE>::threads), shb,
-                       st, args, items, nitems);
+    hipLaunchKernelGGL((k_oais_logreg_batch<KH>), dim3(grid), dim3(LCfg::threads), shb, st, args,
+                       items, nitems);
     return hipGetLastError();
 }
 
 hipError_t logreg_prepare(const TargetDev& tg, void* ws, hipStream_t st)
 {
-    float *Xp, *yp;
+    float* Xp;
     int np;
-    layout(tg, ws, &Xp, &yp, &np);
+    layout(tg, ws, &Xp, &np);
     const int kh = kh_for(tg.d);
     if (kh < 0) return hipErrorInvalidValue;
     // columns are packed with the instantiated half-width, so features
@@ -721,7 +724,7 @@ hipError_t logreg_prepare(const TargetDev& tg, void* ws, hipStream_t st)
     const int64_t total = (int64_t)np * 64;
     const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(k_logreg_pack, dim3(blocks), dim3(256), 0, st, tg.X, tg.y, tg.n, tg.d, kh,
-                       np, Xp, yp);
+                       np, Xp);
     return hipGetLastError();
 }
 
@@ -740,13 +743,12 @@ hipError_t launch_oais_logreg(const SweepArgs& a, int cus, void* ws, size_t, hip
 {
     LogregArgs A{};
     A.a = a;
-    float *Xp, *yp;
+    float* Xp;
     int np;
     const int kh = kh_for(a.tg.d);
     if (kh < 0) return hipErrorInvalidValue;
-    layout(a.tg, ws, &Xp, &yp, &np);
+    layout(a.tg, ws, &Xp, &np);
     A.Xp = Xp;
-    A.yp = yp;
     A.n_pad = np;
     const int grid = (int)std::min<int64_t>(a.S, (int64_t)cus);
     switch (kh) {
@@ -761,11 +763,8 @@ hipError_t launch_oais_logreg(const SweepArgs& a, int cus, void* ws, size_t, hip
 hipError_t launch_oais_logreg_batch(int kh, const LogregArgs* args, const int2* items,
                                    int64_t nitems, int grid, hipStream_t st)
 {
-    const bool pipe = use_pipe();
     switch (kh) {
-#define OASMC_KH_CASE(K) \
-    case K: return pipe ? launch_batch_kh2<K, true>(args, items, nitems, grid, st) \
-                        : launch_batch_kh2<K, false>(args, items, nitems, grid, st);
+#define OASMC_KH_CASE(K) case K: return launch_batch_kh<K>(args, items, nitems, grid, st);
         OASMC_KH_LIST(OASMC_KH_CASE)
 #undef OASMC_KH_CASE
     default:
@@ -776,13 +775,13 @@ hipError_t launch_oais_logreg_batch(int kh, const LogregArgs* args, const int2* 
 hipError_t launch_logreg_eval(const TargetDev& tg, const float* theta, int64_t N, double* ell,
                               float* grad, void* ws, hipStream_t st)
 {
-    float *Xp, *yp;
+    float* Xp;
     int np;
     const int kh = kh_for(tg.d);
     if (kh < 0) return hipErrorInvalidValue;
-    layout(tg, ws, &Xp, &yp, &np);
+    layout(tg, ws, &Xp, &np);
     switch (kh) {
-#define OASMC_KH_CASE(K) case K: return launch_eval_kh<K>(theta, N, tg.d, Xp, yp, np, ell, grad, st);
+#define OASMC_KH_CASE(K) case K: return launch_eval_kh<K>(theta, N, tg.d, Xp, tg.n, np, ell, grad, st);
         OASMC_KH_LIST(OASMC_KH_CASE)
 #undef OASMC_KH_CASE
     default:
