@@ -75,7 +75,12 @@ struct LogregShared {
 static_assert(sizeof(LogregShared::stage) >= sizeof(float) * (LCfg::waves / 2) * 64 * kWave,
               "the gradient reduction fits in the staging buffers");
 
-__device__ __forceinline__ void lsync() { __syncthreads(); }
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS
+// operations, then s_barrier.  Unlike __syncthreads() it does not wait for
+// outstanding global loads, so prefetches (the next step's schedule values,
+// chunk 0 of the next evaluation) stay in flight across it.  Waves of a tile
+// exchange data through LDS only.
+__device__ __forceinline__ void lsync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 __device__ __forceinline__ void wsync()
 {
@@ -332,20 +337,27 @@ __device__ __forceinline__ void contraction(LogregShared& sh, const float* __res
     lsync();
     if (w < 4) {
         add_grad(G, red + w * kSlot, l);
-        if (w > 0) store_grad(red + w * kSlot, G, l);  // slot w is read only by wave w
+        store_grad(red + w * kSlot, G, l);  // slot w is read only by wave w
     }
     lsync();
-    if (w == 0) {
-        add_grad(G, red + 1 * kSlot, l);
-        add_grad(G, red + 2 * kSlot, l);
-        add_grad(G, red + 3 * kSlot, l);
+    // ((slot 0 + slot 1) + slot 2) + slot 3: wave w sums float4 2w, 2w + 1 of
+    // every lane and writes those gradient entries
 #pragma unroll
-        for (int g = 0; g < 2; ++g)
+    for (int kk = 0; kk < 2; ++kk) {
+        const int k = 2 * w + kk;
+        floatx4 v = red[k * kWave + l];
 #pragma unroll
-            for (int ft = 0; ft < 2; ++ft)
+        for (int sl = 1; sl < 4; ++sl) {
+            const floatx4 u = red[sl * kSlot + k * kWave + l];
+            v[0] += u[0];
+            v[1] += u[1];
+            v[2] += u[2];
+            v[3] += u[3];
+        }
+        // float4 k holds G[g][ft][q .. q + 3], (g * 2 + ft) * 16 + q = 4 k
+        const int g = k / 8, ft = (k / 4) % 2, q0 = 4 * (k % 4);
 #pragma unroll
-                for (int q = 0; q < 16; ++q)
-                    sh.glp[32 * g + slot_row(q, h)][32 * ft + j] = G[g][ft][q];
+        for (int i = 0; i < 4; ++i) sh.glp[32 * g + slot_row(q0 + i, h)][32 * ft + j] = v[i];
     }
     // chunk 0 of the next evaluation (the rows do not change between steps)
     first = fetch_slice(Xp, n_pad, 0);
