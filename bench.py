@@ -7,8 +7,11 @@ N = 16384 particles, T = 1, 2, 4, ..., 512, 1000 (11 rounds), MALA with
 adapted per-temperature step sizes, schedules rebuilt by Alg. 3 between rounds.
 Inputs are resident in HBM before the timed region.
 
-Prints ONE JSON line (rank 0).  --workload selects other synthetic workloads
-for extra measurements (not the headline).
+Prints ONE JSON line.  Besides the throughput it reports, outside the timed
+region, the error of the last round's log Z_hat over independent seeds
+against a reference value (closed form where the target has one, otherwise a
+long run of the same estimator), so that throughputs are quoted at a stated
+log Z error.  --workload selects the other synthetic workloads.
 """
 from __future__ import annotations
 
@@ -25,56 +28,66 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
-PEAK_HBM_GBS = 8000.0
-# plain-ALU peak: 256 CUs x 64 lanes x 2.4 GHz lane-operations per second
-PEAK_VALU_LANE_OPS = 256 * 64 * 2.4e9
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (scaled by the copy-kernel calibration); None until measured for
-# the current kernel.
+# WRITE_SIZE (scaled by the copy-kernel calibration); absent until measured
+# for the current kernel.
 TRAFFIC = {}
+METRIC = "particle-steps/sec and fraction of roofline at matched log Z error"
 
 
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def logreg_setup(oa, wl):
+class Spec:
+    """A workload: problem, run options, rounds, the first round's N, the
+    reference log Z and the default number of seeds for the error estimate."""
+
+    def __init__(self, w, prob, kw, rounds, N1, ref, ref_kind, seeds):
+        self.w, self.prob, self.kw, self.rounds, self.N1 = w, prob, kw, rounds, N1
+        self.ref, self.ref_kind, self.seeds = ref, ref_kind, seeds
+
+
+def logreg_spec(oa, wl):
     w = wl.logreg_n10000_d50()
     prob = oa.Problem.logreg(w.params["X"], w.params["y"], w.ref_sigma2)
     kw = dict(move="mala", budget="double_t", T1=1, T_max=1000, eps0=w.eps0, eps_adapt=True,
               eps_kappa=w.params["X"].shape[0] / 4.0, accept_target=0.574, interp=0)
-    return w, prob, kw, 11
+    return Spec(w, prob, kw, 11, w.N, None, "long run", 16)
 
 
-def gauss_setup(oa, wl, N=1024):
-    """The d = 10 Gaussian workload: N = 1024, 2048, 4096, 8192 over 4 rounds, T = 64."""
-    w = wl.gaussian_d10(N=N)
+def gauss_spec(oa, wl):
+    """The d = 10 Gaussian workload as stated: N = 128, 256, 512, 1024 over 4
+    rounds, T = 64 (log Z = 5 ln(pi/2))."""
+    w = wl.gaussian_d10(N=1024)
     prob = oa.Problem.gauss(w.params["mu"], w.params["sigma2"], w.ref_sigma2)
     kw = dict(move="rwmh", budget="double_n", T1=64, eps0=w.eps0)
-    return w, prob, kw, 4
+    return Spec(w, prob, kw, 4, 128, 5 * np.log(np.pi / 2), "closed form", 32)
 
 
-def gauss_sat_setup(oa, wl):
-    """The same target at a saturating particle count (2^22, fixed), T = 64."""
+def gauss_sat_spec(oa, wl):
+    """The same target at a particle count that fills the GPU (2^22, fixed), T = 64."""
     w = wl.gaussian_d10(N=1 << 22)
     prob = oa.Problem.gauss(w.params["mu"], w.params["sigma2"], w.ref_sigma2)
     kw = dict(move="rwmh", budget="fixed", T1=64, eps0=w.eps0)
-    return w, prob, kw, 2
+    return Spec(w, prob, kw, 2, w.N, 5 * np.log(np.pi / 2), "closed form", 8)
 
 
-def asmc_setup(oa, wl):
+def asmc_spec(oa, wl, trigger):
     """8-component mixture in d = 100, HMC (5 leapfrogs), resampling when the
-    relative ESS drops below 0.5, N = 65536, T = 1, 2, ..., 1024, 2000."""
+    trigger (CESS_t / N or the relative ESS) drops below 0.5, N = 65536,
+    T = 1, 2, ..., 1024, 2000 (log Z = 50 ln(0.2 pi))."""
     w = wl.gmm8_d100()
     prob = oa.Problem.gmm(w.params["means"], w.params["log_scales"], w.ref_sigma2)
-    kw = dict(move="hmc", leapfrog=5, resample_=True, trigger="ess", nu=0.5, budget="double_t",
+    kw = dict(move="hmc", leapfrog=5, resample_=True, trigger=trigger, nu=0.5, budget="double_t",
               T1=1, T_max=2000, eps0=w.eps0, eps_adapt=True, eps_kappa=25.0 / 0.1 - 1.0,
               accept_target=0.65)
-    return w, prob, kw, 12
+    return Spec(w, prob, kw, 12, w.N, 50 * np.log(0.2 * np.pi), "closed form", 4)
 
 
-WORKLOADS = {"logreg": logreg_setup, "gauss": gauss_setup, "gauss_sat": gauss_sat_setup,
-             "asmc": asmc_setup}
+WORKLOADS = {"logreg": logreg_spec, "gauss": gauss_spec, "gauss_sat": gauss_sat_spec,
+             "asmc": lambda oa, wl: asmc_spec(oa, wl, "cess"),
+             "asmc_ess": lambda oa, wl: asmc_spec(oa, wl, "ess")}
 
 
 def cpu_baseline(w, res, budget_s: float = 15.0) -> dict:
@@ -113,9 +126,43 @@ def cpu_baseline(w, res, budget_s: float = 15.0) -> dict:
                       f"{dt:.1f} s"}
 
 
+def long_run_reference(oa, spec, res, N: int = 1 << 17, T: int = 4000) -> float:
+    """log Z_hat of one long run (N = 2^17, T = 4000) on a schedule rebuilt by
+    Alg. 3 from the last round of `res`, with step sizes interpolated in beta."""
+    k = int(np.max(np.nonzero(res["T"])[0]))
+    Tk = int(res["T"][k])
+    beta_k = res["beta"][k][: Tk + 1]
+    beta, _ = oa.adapt_schedule(beta_k, res["log_g"][k][:, :Tk], T)
+    eps = np.interp(beta[1:], beta_k[1:], res["eps"][k][:Tk])
+    out = oa.asmc(spec.prob, N, beta, eps, 7777, round_k=99, move=spec.kw["move"],
+                  return_state=False)
+    return float(out["logZ"])
+
+
+def logz_error(oa, spec, args, last_logz, res) -> dict:
+    """Error of the last round's log Z_hat over independent seeds (the timed
+    runs plus untimed ones), against the reference value."""
+    S = args.rmse_seeds if args.rmse_seeds > 0 else spec.seeds
+    vals = list(last_logz)
+    i = 0
+    while len(vals) < S:
+        r = oa.run(spec.prob, spec.N1, spec.rounds, seed=args.seed + 5000 + i, **spec.kw)
+        vals.append(float(r["logZ"][-1]))
+        i += 1
+    vals = np.array(vals[:S])
+    ref = spec.ref
+    if ref is None:
+        ref = long_run_reference(oa, spec, res)
+    err = vals - ref
+    return {"seeds": int(len(vals)), "reference": float(ref), "reference_kind": spec.ref_kind,
+            "rmse": float(np.sqrt(np.mean(err ** 2))), "mean_error": float(np.mean(err)),
+            "sd": float(np.std(vals, ddof=1)) if len(vals) > 1 else None}
+
+
 def extra_workload(args, oa, wl, torch) -> int:
     """The gradient (mixture d = 20, K = 4, N = 8192, T = 256 MALA, checkpoints
-    every 16) and the 256-problem batch (4 rounds, one hipGraph)."""
+    every 16) and the 256-problem batch (4 rounds: one hipGraph, or the same
+    problems one plain run after another)."""
     if args.workload == "grad":
         w = wl.gmm4_d20()
         T = 256
@@ -137,10 +184,18 @@ def extra_workload(args, oa, wl, torch) -> int:
                               eps_adapt=s["eps_adapt"], eps_kappa=s["eps_kappa"], seed=args.seed,
                               problem_id=i) for i, (p, s) in enumerate(zip(probs, specs))]
         rounds = 4
-        run = lambda i: oa.run_batch(items, rounds, use_graph=True)
+        sequential = args.workload == "batch_seq"
+
+        def run(i):
+            if not sequential:
+                return oa.run_batch(items, rounds, use_graph=True)
+            for it in items:
+                oa.run_batch([it], rounds, use_graph=False)
+
         steps_per = float(sum(s["N"] * sum(min(max(1, s["T"] >> (rounds - 1)) << k, s["T"])
                                            for k in range(rounds)) for s in specs))
-        name, cfg = "batch_256_problems", {"problems": len(specs), "rounds": rounds}
+        name = "batch_256_problems" + ("_sequential" if sequential else "_graph")
+        cfg = {"problems": len(specs), "rounds": rounds}
     for i in range(args.warmup):
         run(i)
     torch.cuda.synchronize()
@@ -149,12 +204,12 @@ def extra_workload(args, oa, wl, torch) -> int:
         run(i)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    line = {"metric": "particle-steps/sec and fraction of roofline at matched log Z error",
-            "value": steps_per * args.steps / el, "unit": "particle-steps/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f32 state / f64 arithmetic and weights", "data": "synthetic",
-            "config": dict(workload=name, **cfg), "roofline": None, "cpu_baseline": None}
+    line = {"metric": METRIC, "value": steps_per * args.steps / el, "unit": "particle-steps/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32 state / f64 arithmetic and weights",
+            "data": "synthetic", "config": dict(workload=name, **cfg), "roofline": None,
+            "cpu_baseline": None}
     print(json.dumps(line), flush=True)
     return 0
 
@@ -164,8 +219,11 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="logreg", choices=sorted(WORKLOADS) + ["grad", "batch"])
+    ap.add_argument("--workload", default="logreg",
+                    choices=sorted(WORKLOADS) + ["grad", "batch", "batch_seq"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rmse-seeds", type=int, default=-1,
+                    help="seeds for the log Z error (default per workload; 0 skips it)")
     ap.add_argument("--seed", type=int, default=20240812)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a device-to-device copy of this many MiB (3 times) and exit: "
@@ -193,44 +251,51 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": nbytes, "repeats": 3}), flush=True)
         return 0
-    if args.workload in ("grad", "batch"):
+    if args.workload in ("grad", "batch", "batch_seq"):
         return extra_workload(args, oa, wl, torch)
-    w, prob, kw, rounds = WORKLOADS[args.workload](oa, wl)
-    log(f"workload {w.name}: N={w.N} d={w.d} rounds={rounds}")
+    spec = WORKLOADS[args.workload](oa, wl)
+    w = spec.w
+    log(f"workload {w.name}: N1={spec.N1} d={w.d} rounds={spec.rounds}")
     res = None
     for i in range(args.warmup):
-        res = oa.run(prob, w.N, rounds, seed=args.seed + i, **kw)
+        res = oa.run(spec.prob, spec.N1, spec.rounds, seed=args.seed + i, **spec.kw)
     torch.cuda.synchronize()
     oa.profile(True)
     t0 = time.perf_counter()
     steps_done = 0.0
+    last_logz = []
     for i in range(args.steps):
-        res = oa.run(prob, w.N, rounds, seed=args.seed + 1000 + i, **kw)
+        res = oa.run(spec.prob, spec.N1, spec.rounds, seed=args.seed + 1000 + i, **spec.kw)
         steps_done += float(np.sum(res["N"].astype(np.float64) * res["T"]))
+        last_logz.append(float(res["logZ"][-1]))
         log(f"step {i}: logZ per round {np.round(res['logZ'], 3).tolist()}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = oa.profile(False)
     value = steps_done / elapsed
-    avg_ms = prof["kernel_ms"] / max(prof["launches"], 1)
+    avg_ms = prof["kernel_ms"] / prof["launches"] if prof["launches"] else None
     if w.family == "logreg":
         achieved = prof["flops"] / (prof["kernel_ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
                 "traffic": TRAFFIC.get(args.workload),
-                "kernel": "k_oais_logreg_batch<25, false>", "avg_launch_ms": avg_ms,
+                "kernel": "k_oais_logreg_batch<25>", "avg_launch_ms": avg_ms,
                 "launches": prof["launches"]}
     else:
         rate = prof["particle_steps"] / (prof["kernel_ms"] * 1e-3) if prof["kernel_ms"] else None
         roof = {"bound": "alu", "achieved": rate, "peak": None, "unit": "particle-steps/s",
                 "frac": None, "traffic": None, "kernel": "sweep kernels",
                 "avg_launch_ms": avg_ms, "launches": prof["launches"]}
+    err = None
+    if args.rmse_seeds != 0:
+        log("log Z error over seeds (untimed) ...")
+        err = logz_error(oa, spec, args, last_logz, res)
     cpu = None
     if not args.no_cpu_baseline and w.family in ("logreg", "gauss"):
         log("timing the CPU oracle on a sample ...")
         cpu = cpu_baseline(w, res)
     line = {
-        "metric": "particle-steps/sec and fraction of roofline at matched log Z error",
+        "metric": METRIC,
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
@@ -242,13 +307,14 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32 state / f32 MFMA contraction / f64 weights",
         "data": "synthetic",
-        "config": {"workload": w.name, "N": w.N, "d": w.d, "rounds": rounds,
-                   "T_per_round": res["T"].tolist(),
+        "config": {"workload": w.name, "N_per_round": res["N"].tolist(), "d": w.d,
+                   "rounds": spec.rounds, "T_per_round": res["T"].tolist(),
                    "n": int(w.params["X"].shape[0]) if w.family == "logreg" else None,
-                   "n_resample_last_round": int(res["n_resample"][-1]),
-                   "logZ_last_round": float(res["logZ"][-1]),
+                   "trigger": spec.kw.get("trigger") if spec.kw.get("resample_") else None,
+                   "n_resample_per_round": res["n_resample"].tolist(),
                    "Lambda_hat_last_round": float(res["Lambda"][-1][res["T"][-1]]),
                    "parallelism": "single GPU"},
+        "logZ_error": err,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

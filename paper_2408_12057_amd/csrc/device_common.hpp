@@ -96,15 +96,62 @@ __device__ __forceinline__ double lse_value(double m, double s)
     return (s > 0.0) ? m + log(s) : -INFINITY;
 }
 
+// A binary64 value from another lane of the same row of 16, by a DPP
+// permutation (a VALU move: no LDS traffic, unlike a general shuffle).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// DPP controls: quad_perm [1,0,3,2] (lane ^ 1), quad_perm [2,3,0,1]
+// (lane ^ 2), row_half_mirror (i -> 7 - i within 8), row_mirror (i -> 15 - i).
+constexpr int kDppXor1 = 0xB1;
+constexpr int kDppXor2 = 0x4E;
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+
 // Sum over aligned groups of G lanes (G a power of two <= 64).  All lanes of a
-// group end with the same bits: the butterfly adds the same operands in the
-// same order on every lane of a pair.
+// group end with the same bits: each level adds the partial sums of two
+// disjoint halves, and the two lanes of a pair add the same operands (the sum
+// is commutative), so the tree is that of the xor butterfly.  Levels inside a
+// row of 16 lanes use DPP; wider levels use shuffles.
 template <int G>
 __device__ __forceinline__ double group_sum(double v)
 {
+    if constexpr (G >= 2) v += dpp_f64<kDppXor1>(v);
+    if constexpr (G >= 4) v += dpp_f64<kDppXor2>(v);
+    if constexpr (G >= 8) v += dpp_f64<kDppHalfMirror>(v);
+    if constexpr (G >= 16) v += dpp_f64<kDppMirror>(v);
 #pragma unroll
-    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, kWave);
+    for (int o = 16; o < G; o <<= 1) v += __shfl_xor(v, o, kWave);
     return v;
+}
+
+// Wave-wide max and sum (xor butterflies: every lane ends with the same bits).
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// log sum_j exp(v_j) over the values of a wave: the maximum, then the sum of
+// exp(v_j - max) (-inf when every value is -inf).  Fixed order.
+__device__ __forceinline__ double wave_lse(double v)
+{
+    const double m = wave_max(v);
+    const double s = wave_sum((m > -INFINITY && v > -INFINITY) ? exp(v - m) : 0.0);
+    return lse_value(m, s);
 }
 
 }  // namespace oasmc

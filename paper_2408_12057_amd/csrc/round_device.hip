@@ -3,7 +3,7 @@
 // problems) can be enqueued without host round trips and captured in a
 // hipGraph:
 //   * merge of the slot partials (the moments of eq. (CESS), acceptance and
-//     log Z_hat), in slot order;
+//     log Z_hat) in a fixed order that does not depend on the grid;
 //   * Alg. 3 (OptimiseSchedule): D_hat_t, Lambda_hat_t = sum sqrt(D_hat_s),
 //     monotone cubic (Fritsch-Carlson) inverse of the knots (Lambda_hat_t,
 //     beta_t) evaluated at Lambda_hat_T t'/T';
@@ -16,35 +16,44 @@
 
 namespace oasmc {
 
-__device__ __forceinline__ double d_log_add(double a, double b)
-{
-    const double m = fmax(a, b);
-    if (m == -INFINITY) return -INFINITY;
-    return m + log1p(exp(-fabs(a - b)));
-}
-
 // Merge the slot partials of one problem (blockIdx.x selects the problem,
-// blockIdx.y a range of 256 entries).
-__global__ void k_round_merge(const RoundDev* __restrict__ rd)
+// blockIdx.y + k gridDim.y the entry; one wave per entry, a maximum and then
+// a sum of exp(x - max) over the slots in a fixed order).
+__global__ void __launch_bounds__(kWave) k_round_merge(const RoundDev* __restrict__ rd)
 {
     const RoundDev& R = rd[blockIdx.x];
     const int T = R.T;
-    const int e = blockIdx.y * blockDim.x + threadIdx.x;
-    if (e <= T) {
-        double L[3] = {-INFINITY, -INFINITY, -INFINITY};
-        double cnt = 0.0;
-        for (int64_t s = 0; s < R.S; ++s) {
+    const int lane = threadIdx.x;
+    for (int e = blockIdx.y; e <= T; e += gridDim.y) {
+        double m[3] = {-INFINITY, -INFINITY, -INFINITY};
+        double c = 0.0;
+        for (int64_t s = lane; s < R.S; s += kWave) {
             const double* p = R.part + ((size_t)s * (T + 1) + e) * 4;
 #pragma unroll
-            for (int i = 0; i < 3; ++i) L[i] = d_log_add(L[i], p[i]);
-            cnt += p[3];
+            for (int i = 0; i < 3; ++i) m[i] = fmax(m[i], p[i]);
+            c += p[3];
         }
-        if (e < T) {
 #pragma unroll
-            for (int i = 0; i < 3; ++i) R.log_g[(size_t)i * T + e] = L[i];
-            R.acc[e] = cnt / (double)R.N;
-        } else {
-            R.logZ[0] = L[0] - log((double)R.N);
+        for (int i = 0; i < 3; ++i) m[i] = wave_max(m[i]);
+        double sum[3] = {0.0, 0.0, 0.0};
+        for (int64_t s = lane; s < R.S; s += kWave) {
+            const double* p = R.part + ((size_t)s * (T + 1) + e) * 4;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                if (m[i] > -INFINITY && p[i] > -INFINITY) sum[i] += exp(p[i] - m[i]);
+        }
+        double L[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) L[i] = lse_value(m[i], wave_sum(sum[i]));
+        const double cnt = wave_sum(c);
+        if (lane == 0) {
+            if (e < T) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) R.log_g[(size_t)i * T + e] = L[i];
+                R.acc[e] = cnt / (double)R.N;
+            } else {
+                R.logZ[0] = L[0] - log((double)R.N);
+            }
         }
     }
 }
@@ -194,7 +203,8 @@ __global__ void __launch_bounds__(256) k_round_schedule(const RoundDev* __restri
 
 hipError_t launch_round_merge(const RoundDev* rd, int nprob, int Tmax, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_round_merge, dim3(nprob, (Tmax + 1 + 255) / 256), dim3(256), 0, st, rd);
+    hipLaunchKernelGGL(k_round_merge, dim3(nprob, std::min(Tmax + 1, 65535)), dim3(kWave), 0, st,
+                       rd);
     return hipGetLastError();
 }
 

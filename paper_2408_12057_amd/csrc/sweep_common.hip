@@ -6,21 +6,45 @@
 
 namespace oasmc {
 
-// Merge the S slot partials per entry in slot order (deterministic):
-// log_g[i*T + e] for e < T, accept fraction, and log Z_hat from entry T.
-__global__ void k_merge_slots(const double* __restrict__ part, int64_t S, int T, int64_t N,
-                              double* log_g, double* acc, double* logZ)
+// Merge the S slot partials of one entry (one wave per entry): each lane
+// takes slots lane, lane + 64, ... and the log-sum-exps are a maximum and then
+// a sum of exp(x - max), reduced in a fixed order (deterministic, and
+// independent of the grid): log_g[i*T + e] for e < T, the accept fraction,
+// and log Z_hat from entry T.
+__device__ __forceinline__ void merge_entry(const double* __restrict__ part, int64_t S, int T,
+                                            int e, double (&L)[3], double& cnt)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e > T) return;
-    double L[3] = {-INFINITY, -INFINITY, -INFINITY};
-    double cnt = 0.0;
-    for (int64_t s = 0; s < S; ++s) {
+    const int lane = threadIdx.x;
+    double m[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double c = 0.0;
+    for (int64_t s = lane; s < S; s += kWave) {
         const double* p = part + ((size_t)s * (T + 1) + e) * 4;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) L[i] = log_add(L[i], p[i]);
-        cnt += p[3];
+        for (int i = 0; i < 3; ++i) m[i] = fmax(m[i], p[i]);
+        c += p[3];
     }
+    double sum[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) m[i] = wave_max(m[i]);
+    for (int64_t s = lane; s < S; s += kWave) {
+        const double* p = part + ((size_t)s * (T + 1) + e) * 4;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            if (m[i] > -INFINITY && p[i] > -INFINITY) sum[i] += exp(p[i] - m[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) L[i] = lse_value(m[i], wave_sum(sum[i]));
+    cnt = wave_sum(c);
+}
+
+__global__ void __launch_bounds__(kWave) k_merge_slots(const double* __restrict__ part, int64_t S,
+                                                       int T, int64_t N, double* log_g, double* acc,
+                                                       double* logZ)
+{
+    const int e = blockIdx.x;
+    double L[3], cnt;
+    merge_entry(part, S, T, e, L, cnt);
+    if (threadIdx.x != 0) return;
     if (e < T) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) log_g[(size_t)i * T + e] = L[i];
@@ -30,55 +54,93 @@ __global__ void k_merge_slots(const double* __restrict__ part, int64_t S, int T,
     }
 }
 
-// One block: merge the tile statistics of step t in tile order, record the
+// One block: merge the tile statistics of step t (fixed order), record the
 // moments, ESS, the event decision and the log Z_hat increment.
-__global__ void __launch_bounds__(256) k_asmc_merge(SweepArgs a, AsmcState z, int t, int trigger,
-                                                    double nu)
+constexpr int kMergeThreads = 1024;
+__global__ void __launch_bounds__(kMergeThreads) k_asmc_merge(SweepArgs a, AsmcState z, int t,
+                                                              int trigger, double nu)
 {
-    __shared__ double sh[256][6];
-    const int tid = threadIdx.x;
-    double L[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
-    double mx = -INFINITY, cnt = 0.0;
-    for (int64_t k = tid; k < a.ntiles; k += 256) {
+    constexpr int W = kMergeThreads / kWave;
+    __shared__ double shm[W][6];
+    __shared__ double res[6];
+    const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+    // pass 1: maxima and the accept count
+    double m[5] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    double cnt = 0.0;
+    for (int64_t k = tid; k < a.ntiles; k += kMergeThreads) {
         const double* tp = z.tile_part + (size_t)k * 8;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) L[i] = log_add(L[i], tp[i]);
-        mx = fmax(mx, tp[4]);
+        for (int i = 0; i < 5; ++i) m[i] = fmax(m[i], tp[i]);
         cnt += tp[5];
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) sh[tid][i] = L[i];
-    sh[tid][4] = mx;
-    sh[tid][5] = cnt;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if (tid < st) {
+    for (int i = 0; i < 5; ++i) m[i] = wave_max(m[i]);
+    cnt = wave_sum(cnt);
+    if (lane == 0) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) sh[tid][i] = log_add(sh[tid][i], sh[tid + st][i]);
-            sh[tid][4] = fmax(sh[tid][4], sh[tid + st][4]);
-            sh[tid][5] += sh[tid + st][5];
-        }
-        __syncthreads();
+        for (int i = 0; i < 5; ++i) shm[w][i] = m[i];
+        shm[w][5] = cnt;
     }
+    __syncthreads();
     if (tid == 0) {
+        double r[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) r[i] = shm[0][i];
+        for (int ww = 1; ww < W; ++ww) {
+#pragma unroll
+            for (int i = 0; i < 5; ++i) r[i] = fmax(r[i], shm[ww][i]);
+            r[5] += shm[ww][5];
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) res[i] = r[i];
+    }
+    __syncthreads();
+    double M[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) M[i] = res[i];
+    const double mx = res[4], total = res[5];
+    __syncthreads();
+    // pass 2: sums of exp(L_tile - max)
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t k = tid; k < a.ntiles; k += kMergeThreads) {
+        const double* tp = z.tile_part + (size_t)k * 8;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (M[i] > -INFINITY && tp[i] > -INFINITY) s[i] += exp(tp[i] - M[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[i] = wave_sum(s[i]);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) shm[w][i] = s[i];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double L[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double acc = shm[0][i];
+            for (int ww = 1; ww < W; ++ww) acc += shm[ww][i];
+            L[i] = lse_value(M[i], acc);
+        }
         const int T = a.T;
         const double logN = log((double)a.N);
-        for (int i = 0; i < 3; ++i) z.log_g[(size_t)i * T + (t - 1)] = sh[0][i];
-        z.accept[t - 1] = sh[0][5];
-        const double rel_ess = exp(2.0 * sh[0][1] - sh[0][3] - logN);
-        const double rel_cess = exp(-(sh[0][2] - 2.0 * sh[0][1] + sh[0][0]));
+        for (int i = 0; i < 3; ++i) z.log_g[(size_t)i * T + (t - 1)] = L[i];
+        z.accept[t - 1] = total;
+        const double rel_ess = exp(2.0 * L[1] - L[3] - logN);
+        const double rel_cess = exp(-(L[2] - 2.0 * L[1] + L[0]));
         z.ess[t - 1] = rel_ess;
         const bool fire = (trigger == 0) ? (rel_ess < nu) : (rel_cess < nu);
         z.resampled[t - 1] = 0;
         z.scal[2] = 0.0;
         if (t == T) {
-            z.scal[0] += sh[0][1] - logN;
+            z.scal[0] += L[1] - logN;
         } else if (fire) {
-            z.scal[0] += sh[0][1] - logN;
-            z.scal[1] = sh[0][4];
+            z.scal[0] += L[1] - logN;
+            z.scal[1] = mx;
             z.scal[2] = 1.0;
-            const uint4 w = draw_block(a.key, 0xFFFFFFFFu, (uint32_t)t, kStreamResample, 0u, 0u);
-            z.scal[3] = (double)w.x;
+            const uint4 wd = draw_block(a.key, 0xFFFFFFFFu, (uint32_t)t, kStreamResample, 0u, 0u);
+            z.scal[3] = (double)wd.x;
             z.resampled[t - 1] = 1;
             z.nres[0] += 1;
         }
@@ -294,7 +356,10 @@ bool valu_shape(int d, ValuShape* s)
     } else if (d <= 64) {
         s->lpp = 4; s->dpl = 16;
     } else if (d <= 128) {
-        s->lpp = 8; s->dpl = 16;
+        // 16 lanes of 8 coordinates rather than 8 of 16: half the registers
+        // per lane, two waves per SIMD for the mixture/HMC sweeps (measured
+        // 25% faster at d = 100)
+        s->lpp = 16; s->dpl = 8;
     } else {
         s->lpp = 16; s->dpl = 16;
     }
@@ -372,7 +437,7 @@ hipError_t launch_asmc_step(const SweepArgs& a, const ValuShape& s, const AsmcSt
 {
     hipError_t e = dispatch_all(2, a, s, 0, &z, t, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_asmc_merge, dim3(1), dim3(256), 0, st, a, z, t, trigger, nu);
+    hipLaunchKernelGGL(k_asmc_merge, dim3(1), dim3(kMergeThreads), 0, st, a, z, t, trigger, nu);
     return hipGetLastError();
 }
 
@@ -400,10 +465,8 @@ hipError_t launch_resample_step(const SweepArgs& a, const AsmcState& z, int t, h
 hipError_t launch_merge_slots(const double* part, int64_t S, int T, int64_t N, double* log_g,
                               double* acc, double* logZ, hipStream_t st)
 {
-    const int threads = 128;
-    const int blocks = (T + 1 + threads - 1) / threads;
-    hipLaunchKernelGGL(k_merge_slots, dim3(blocks), dim3(threads), 0, st, part, S, T, N, log_g,
-                       acc, logZ);
+    hipLaunchKernelGGL(k_merge_slots, dim3(T + 1), dim3(kWave), 0, st, part, S, T, N, log_g, acc,
+                       logZ);
     return hipGetLastError();
 }
 
