@@ -28,6 +28,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
+# plain-ALU issue budget: 256 CUs x 64 lanes x 2.4 GHz lane-cycles per second
+PEAK_LANE_CYCLES = 256 * 64 * 2.4e9
+# algorithmic ALU work per particle-step in lane-cycles (Philox blocks, binary64
+# Box-Muller, target and gradient arithmetic, moment statistics; the model is
+# derived per workload alongside the kernel descriptions)
+ALU_WORK = {"gauss": 700.0, "gauss_sat": 700.0, "asmc": 1.0e4, "asmc_ess": 1.0e4}
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by the copy-kernel calibration); absent until measured
 # for the current kernel.
@@ -283,8 +289,12 @@ def main() -> int:
                 "launches": prof["launches"]}
     else:
         rate = prof["particle_steps"] / (prof["kernel_ms"] * 1e-3) if prof["kernel_ms"] else None
-        roof = {"bound": "alu", "achieved": rate, "peak": None, "unit": "particle-steps/s",
-                "frac": None, "traffic": None, "kernel": "sweep kernels",
+        peak = PEAK_LANE_CYCLES / ALU_WORK[args.workload]
+        kern = ("k_asmc_step + k_asmc_merge + resampler, per step" if spec.kw.get("resample_")
+                else "k_oais_valu_batch")
+        roof = {"bound": "alu", "achieved": rate, "peak": peak, "unit": "particle-steps/s",
+                "frac": rate / peak if rate else None, "traffic": None, "kernel": kern,
+                "work_lane_cycles_per_particle_step": ALU_WORK[args.workload],
                 "avg_launch_ms": avg_ms, "launches": prof["launches"]}
     err = None
     if args.rmse_seeds != 0:

@@ -292,7 +292,10 @@ int oasmc_logreg_eval(oasmc_handle* h, const oasmc_problem* problem, int64_t N,
  * kernel time in ms, number of launches, and the algorithmic work of those
  * launches (particle-steps, and for the logistic-regression family the
  * contraction flops 4 d n per particle and evaluation, evaluations = T + 1 per
- * particle per pass).
+ * particle per pass).  The resampling variant, which launches several kernels
+ * per step, is timed as a whole and counts one launch per step.  A run
+ * captured in a hipGraph (oasmc_run_batch with use_graph) is timed as one
+ * launch.
  */
 int oasmc_profile(oasmc_handle* h, int32_t enable, double* kernel_ms, int64_t* launches,
                   double* particle_steps, double* flops);

@@ -843,12 +843,14 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
         z.log_g = dlogg;
         z.accept = dacc;
         a.ntiles = ntiles;
+        if (h->prof) HIP_TRY(hipEventRecord(h->ev0, st));
         HIP_TRY(launch_zero(dscal, 8, z.nres, 4, st));
         HIP_TRY(launch_asmc_init(a, shape, z, st));
         for (int t = 1; t <= T; ++t) {
             HIP_TRY(launch_asmc_step(a, shape, z, t, kernel->trigger, kernel->nu, st));
             if (t < T) HIP_TRY(launch_resample_step(a, z, t, st));
         }
+        if (h->prof) HIP_TRY(hipEventRecord(h->ev1, st));
         std::vector<double> cnt(T);
         HIP_TRY(hipMemcpyAsync(out->log_g, dlogg, sizeof(double) * 3 * T, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipMemcpyAsync(cnt.data(), dacc, sizeof(double) * T, hipMemcpyDeviceToHost, st));
@@ -864,6 +866,14 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
             HIP_TRY(hipMemcpyAsync(out->x, z.X, sizeof(float) * N * d, hipMemcpyDeviceToDevice, st));
         HIP_TRY(hipStreamSynchronize(st));
         for (int t = 0; t < T; ++t) out->accept[t] = cnt[t] / (double)N;
+        if (h->prof) {
+            // one "launch" per step: the step's sweep, merge and resampler
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+            h->prof_ms += ms;
+            h->prof_launches += T;
+            h->prof_steps += (double)N * T;
+        }
     }
     out->logZ = scal[0];
     out->n_resample = nres;
