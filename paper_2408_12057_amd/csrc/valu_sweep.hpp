@@ -129,6 +129,9 @@ struct Particle {
                 }
             }
             sse = group_sum<LPP>(sse);
+            if constexpr (LPP > 1) {
+                return mixture_multilane<GRAD>(tg, c, pv, r, x, g, sse);
+            }
             double mx = -INFINITY, s = 0.0;
 #pragma unroll 1
             for (int k = 0; k < tg.K; ++k) {
@@ -177,6 +180,78 @@ struct Particle {
             }
             return lse + sse * c.half_inv_s2r + c.cst_eta;
         }
+    }
+
+    // The mixture term for a particle spread over LPP > 1 lanes, in two
+    // passes: the exponents e_k = -|x - m_k|^2 / (2 v_k) (summed over the
+    // lanes, so every lane holds them all), their maximum M, then one
+    // exponential per component, computed by the lane k mod LPP only, and
+    // log sum_k exp(e_k - M); the gradient gathers the weights from their
+    // lanes.  (Streaming over k on every lane would repeat each exponential
+    // LPP times.)
+    template <bool GRAD>
+    static __device__ __forceinline__ double mixture_multilane(const TargetDev& tg, const Consts& c,
+                                                               const ParView& pv, int r,
+                                                               const float (&x)[DPL],
+                                                               double (&g)[DPL], double sse)
+    {
+        constexpr int KO = (kMaxK + LPP - 1) / LPP;  // components owned by a lane
+        const int d = tg.d;
+        const int K = tg.K;
+        const int i0 = r * DPL;
+        double eo[KO];
+#pragma unroll
+        for (int q = 0; q < KO; ++q) eo[q] = -INFINITY;
+        double M = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < kMaxK; ++k) {
+            if (k < K) {
+                const float* mk = pv.mu + k * d;
+                double sq = 0.0;
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) {
+                    const int i = i0 + j;
+                    if (i < d) {
+                        const double a = (double)x[j] - (double)mk[i];
+                        sq = fma(a, a, sq);
+                    }
+                }
+                const double ek = -group_sum<LPP>(sq) * pv.hiv[k];
+                M = fmax(M, ek);
+                if ((k % LPP) == r) eo[k / LPP] = ek;
+            }
+        }
+        double wo[KO];
+        double so = 0.0;
+#pragma unroll
+        for (int q = 0; q < KO; ++q) {
+            wo[q] = (q * LPP + r < K) ? exp(eo[q] - M) : 0.0;
+            so += wo[q];
+        }
+        const double s = group_sum<LPP>(so);
+        const double lse = M + log(s) - c.logK;
+        if (GRAD) {
+            const int base = (int)(threadIdx.x & (kWave - 1)) & ~(LPP - 1);
+#pragma unroll
+            for (int k = 0; k < kMaxK; ++k) {
+                if (k < K) {
+                    const double f = __shfl(wo[k / LPP], base + k % LPP, kWave) * pv.iv[k];
+                    const float* mk = pv.mu + k * d;
+#pragma unroll
+                    for (int j = 0; j < DPL; ++j) {
+                        const int i = i0 + j;
+                        if (i < d) g[j] = fma(f, (double)mk[i] - (double)x[j], g[j]);
+                    }
+                }
+            }
+            const double inv_s = 1.0 / s;
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) {
+                const int i = i0 + j;
+                if (i < d) g[j] = g[j] * inv_s + ((double)x[j] - (double)pv.m[i]) * c.inv_s2r;
+            }
+        }
+        return lse + sse * c.half_inv_s2r + c.cst_eta;
     }
 
     // d normals of one (particle, step, stream) split over the group's lanes.
