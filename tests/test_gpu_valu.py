@@ -52,8 +52,13 @@ CASES = [
     ("gauss", 33, "rwmh", 70, 12, 0),      # 4 lanes per particle
     ("gmm", 20, "mala", 257, 16, 4),
     ("gmm", 5, "hmc", 100, 11, 3),
-    ("gmm", 100, "hmc", 40, 8, 8),         # 8 lanes per particle
-    ("gmm", 150, "rwmh", 33, 6, 2),        # 16 lanes per particle
+    ("gmm", 100, "hmc", 40, 8, 8),         # 16 lanes of 8 coordinates per particle
+    ("gmm", 150, "rwmh", 33, 6, 2),        # 16 lanes of 16 coordinates
+    # mixture exponentials owned by lane k mod LPP: K below, equal to and above LPP
+    ("gmm", 30, "mala", 90, 10, 5),        # 2 lanes, 3 components per lane
+    ("gmm", 60, "hmc", 50, 7, 16),         # 4 lanes, the largest K
+    ("gmm", 128, "mala", 20, 6, 1),        # 16 lanes, one component
+    ("gmm", 256, "mala", 24, 5, 3),        # the largest d
     ("gauss", 1, "rwmh", 1, 5, 0),         # a single particle in one dimension
 ]
 
