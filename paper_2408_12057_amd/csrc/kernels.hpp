@@ -66,6 +66,8 @@ struct AsmcState {
     float* X2;         // [N*d] gather target
     double* ell;       // [N]
     double* ell2;      // [N]
+    double* G;         // [N*d] grad ell at the current states (MALA, HMC), else null
+    double* G2;        // [N*d] gather target of G
     double* lw;        // [N]
     uint32_t* accw;    // [N] accept bits of the current 32-step word
     double* tile_part; // [ntiles*8]

@@ -92,7 +92,7 @@ namespace {
 enum BufId {
     B_BETA, B_EPS, B_PART, B_LOGG, B_ACC, B_SCAL, B_X, B_X2, B_ELL, B_ELL2, B_LW, B_ACCW,
     B_TPART, B_NRES, B_ESS, B_RES, B_C, B_BTOT, B_LWO, B_XO, B_LOGREG, B_CKPT, B_SEG, B_ABITS,
-    B_GPART, B_GRAD, B_DEVRUN, B_DEVDESC, B_COUNT
+    B_GPART, B_GRAD, B_DEVRUN, B_DEVDESC, B_G, B_G2, B_COUNT
 };
 
 template <typename T>
@@ -831,6 +831,10 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
         HIP_TRY(wget(h, B_X2, (size_t)N * d, &z.X2));
         HIP_TRY(wget(h, B_ELL, N, &z.ell));
         HIP_TRY(wget(h, B_ELL2, N, &z.ell2));
+        if (kernel->move != OASMC_RWMH) {
+            HIP_TRY(wget(h, B_G, (size_t)N * d, &z.G));
+            HIP_TRY(wget(h, B_G2, (size_t)N * d, &z.G2));
+        }
         HIP_TRY(wget(h, B_LW, N, &z.lw));
         HIP_TRY(wget(h, B_ACCW, N, &z.accw));
         HIP_TRY(wget(h, B_TPART, (size_t)ntiles * 8, &z.tile_part));

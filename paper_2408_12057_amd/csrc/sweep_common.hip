@@ -278,7 +278,10 @@ __global__ void k_rs_gather(int64_t N, int d, AsmcState z, int64_t nb)
     if (n >= N) return;
     const uint32_t u = (uint32_t)z.scal[3];
     const int64_t an = find_ancestor(n, N, u, z.C, z.btot, nb);
-    for (int i = threadIdx.x; i < d; i += blockDim.x) z.X2[(size_t)n * d + i] = z.X[(size_t)an * d + i];
+    for (int i = threadIdx.x; i < d; i += blockDim.x) {
+        z.X2[(size_t)n * d + i] = z.X[(size_t)an * d + i];
+        if (z.G) z.G2[(size_t)n * d + i] = z.G[(size_t)an * d + i];
+    }
     if (threadIdx.x == 0) z.ell2[n] = z.ell[an];
 }
 
@@ -289,6 +292,7 @@ __global__ void k_rs_commit(int64_t N, int d, AsmcState z)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         z.X[i] = z.X2[i];
+        if (z.G) z.G[i] = z.G2[i];
         if (i < N) {
             z.ell[i] = z.ell2[i];
             z.lw[i] = 0.0;

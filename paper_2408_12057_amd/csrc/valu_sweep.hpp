@@ -607,11 +607,14 @@ __global__ void __launch_bounds__(256) k_asmc_init(SweepArgs a, AsmcState z)
     float x[DPL];
     double g[DPL];
     const double ell = Particle<FAM, LPP, DPL>::init(a.tg, c, pv, a.key, (uint32_t)n64, r, x, g,
-                                                     false);
+                                                     MOVE != kRwmh);
 #pragma unroll
     for (int j = 0; j < DPL; ++j) {
         const int i = r * DPL + j;
-        if (i < a.tg.d) z.X[(size_t)n64 * a.tg.d + i] = x[j];
+        if (i < a.tg.d) {
+            z.X[(size_t)n64 * a.tg.d + i] = x[j];
+            if (MOVE != kRwmh) z.G[(size_t)n64 * a.tg.d + i] = g[j];
+        }
     }
     if (r == 0) {
         z.ell[n64] = ell;
@@ -635,19 +638,16 @@ __global__ void __launch_bounds__(256) k_asmc_step(SweepArgs a, AsmcState z, int
     const bool valid = n64 < a.N;
     const int d = a.tg.d;
     const int64_t nl = valid ? n64 : a.N - 1;  // invalid lanes work on a copy, write nothing
+    // state, ell and (MALA, HMC) grad ell as the previous step left them
     float x[DPL];
     double g[DPL];
 #pragma unroll
     for (int j = 0; j < DPL; ++j) {
         const int i = r * DPL + j;
         x[j] = (i < d) ? z.X[(size_t)nl * d + i] : 0.f;
-        g[j] = 0.0;
+        g[j] = (MOVE != kRwmh && i < d) ? z.G[(size_t)nl * d + i] : 0.0;
     }
-    double ell;
-    if (MOVE != kRwmh)
-        ell = Particle<FAM, LPP, DPL>::template eval<true>(a.tg, c, pv, r, x, g);
-    else
-        ell = z.ell[nl];
+    double ell = z.ell[nl];
     double lw = z.lw[nl];
     const double lg = (a.beta[t] - a.beta[t - 1]) * ell;
     // tile statistics: lse of lw, lw+lg, lw+2lg, 2(lw+lg)
@@ -685,7 +685,10 @@ __global__ void __launch_bounds__(256) k_asmc_step(SweepArgs a, AsmcState z, int
 #pragma unroll
         for (int j = 0; j < DPL; ++j) {
             const int i = r * DPL + j;
-            if (i < d) z.X[(size_t)n64 * d + i] = x[j];
+            if (i < d) {
+                z.X[(size_t)n64 * d + i] = x[j];
+                if (MOVE != kRwmh) z.G[(size_t)n64 * d + i] = g[j];
+            }
         }
         if (r == 0) {
             z.ell[n64] = ell;
