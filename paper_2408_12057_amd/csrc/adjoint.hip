@@ -4,16 +4,12 @@
 
 namespace oasmc {
 
-bool adjoint_shape(int d, int K, ValuShape* s, int* kb)
+bool adjoint_shape(int d, int K, int64_t N, ValuShape* s, int* kb)
 {
+    // the same particle layout as the forward sweep (valu_shape), so that the
+    // recomputed segments repeat its arithmetic exactly
     if (d < 1 || d > 32 || K < 1 || K > 8) return false;
-    if (d <= 24) {
-        s->lpp = 1;
-        s->dpl = ((d + 3) / 4) * 4;
-    } else {
-        s->lpp = 2;
-        s->dpl = 16;
-    }
+    if (!valu_shape(d, N, s)) return false;
     *kb = (K <= 2) ? 2 : (K <= 4 ? 4 : 8);
     return true;
 }
@@ -30,6 +26,7 @@ hipError_t launch_adjoint(const AdjointArgs& A, const ValuShape& s, int kb, hipS
     OASMC_ADJ_K(1, 20)
     OASMC_ADJ_K(1, 24)
     OASMC_ADJ_K(2, 16)
+    OASMC_ADJ_K(4, 8)
 #undef OASMC_ADJ_K
 #undef OASMC_ADJ
     return hipErrorInvalidValue;

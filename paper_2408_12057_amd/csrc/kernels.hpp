@@ -89,7 +89,9 @@ struct ValuShape {
     int dpl;  // dimensions per lane
 };
 
-bool valu_shape(int d, ValuShape* s);
+// Lanes that fill every SIMD of the GPU twice (256 CUs x 4 SIMDs x 64 x 2).
+constexpr int64_t kFillLanes = 256 * 4 * 64 * 2;
+bool valu_shape(int d, int64_t N, ValuShape* s);
 
 // A batch of problems of one (family, move, shape) class.
 struct ValuBatch {
@@ -126,7 +128,7 @@ struct AdjointArgs {
     double* partial;      // [waves][np] per-wave weighted gradient sums
     int64_t nwaves;
 };
-bool adjoint_shape(int d, int K, ValuShape* s, int* kb);
+bool adjoint_shape(int d, int K, int64_t N, ValuShape* s, int* kb);
 hipError_t launch_adjoint(const AdjointArgs& A, const ValuShape& s, int kb, hipStream_t st);
 hipError_t launch_adjoint_reduce(const double* partial, int64_t nwaves, int np, double* grad,
                                  hipStream_t st);

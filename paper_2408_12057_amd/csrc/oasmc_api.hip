@@ -660,7 +660,7 @@ int prepare_dev_problem(oasmc_handle* h, DevProblem& q)
         q.shape = ValuShape{0, 0};
         q.ntiles = logreg_tiles(q.N);
     } else {
-        if (!valu_shape(q.prob.d, &q.shape)) return fail(OASMC_EUNSUPPORTED, "no kernel for d=%d", q.prob.d);
+        if (!valu_shape(q.prob.d, q.N, &q.shape)) return fail(OASMC_EUNSUPPORTED, "no kernel for d=%d", q.prob.d);
         q.kh = 0;
         q.ntiles = valu_tiles(q.N, q.shape);
     }
@@ -776,7 +776,7 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
                             h->lds_per_block, logreg_shared_bytes());
             ntiles = logreg_tiles(N);
         } else {
-            if (!valu_shape(problem->d, &shape))
+            if (!valu_shape(problem->d, N, &shape))
                 return fail(OASMC_EUNSUPPORTED, "no kernel shape for d=%d", problem->d);
             ntiles = valu_tiles(N, shape);
         }
@@ -822,7 +822,7 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
         }
     } else {
         ValuShape shape{};
-        if (!valu_shape(problem->d, &shape))
+        if (!valu_shape(problem->d, N, &shape))
             return fail(OASMC_EUNSUPPORTED, "no kernel shape for d=%d", problem->d);
         const int64_t ntiles = valu_tiles(N, shape);
         const int d = problem->d;
@@ -921,7 +921,7 @@ int oasmc_logZ_backward(oasmc_handle* h, const oasmc_problem* problem, const oas
         return fail(OASMC_EUNSUPPORTED, "the gradient is built for the mixture target with MALA and no resampling");
     ValuShape shape{}, ashape{};
     int kb = 0;
-    if (!valu_shape(problem->d, &shape) || !adjoint_shape(problem->d, problem->K, &ashape, &kb) ||
+    if (!valu_shape(problem->d, N, &shape) || !adjoint_shape(problem->d, problem->K, N, &ashape, &kb) ||
         shape.lpp != ashape.lpp || shape.dpl != ashape.dpl)
         return fail(OASMC_EUNSUPPORTED, "the gradient supports d <= 32 and K <= 8");
     s = check_schedule(T, beta);

@@ -349,7 +349,7 @@ __global__ void k_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, uint32_t
 // ---------------------------------------------------------------------------
 // Host-side dispatch.
 // ---------------------------------------------------------------------------
-bool valu_shape(int d, ValuShape* s)
+bool valu_shape(int d, int64_t N, ValuShape* s)
 {
     if (d < 1 || d > kMaxDValu) return false;
     if (d <= 24) {
@@ -366,6 +366,12 @@ bool valu_shape(int d, ValuShape* s)
         s->lpp = 16; s->dpl = 8;
     } else {
         s->lpp = 16; s->dpl = 16;
+    }
+    // Few particles: a particle on 4 lanes of 8 coordinates puts more of the
+    // GPU to work (fewer lanes than two waves per SIMD otherwise)
+    if (d > 8 && d <= 32 && N * s->lpp < kFillLanes) {
+        s->lpp = 4;
+        s->dpl = 8;
     }
     return true;
 }

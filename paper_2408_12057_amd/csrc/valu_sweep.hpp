@@ -761,6 +761,7 @@ hipError_t valu_dispatch(int what, const SweepArgs& a, const ValuShape& s, int g
     OASMC_CASE(16, 16)
     OASMC_CASE(8, 8)
     OASMC_CASE(16, 8)
+    OASMC_CASE(4, 8)
 #undef OASMC_CASE
     return hipErrorInvalidValue;
 }
