@@ -53,7 +53,8 @@ typedef enum { OASMC_RWMH = 1, OASMC_MALA = 2, OASMC_HMC = 3 } oasmc_move;
  *   OASMC_GAUSS : gamma(x) = exp(-|x - mu|^2 / (2 sigma2))             mu[d]
  *   OASMC_LOGREG: gamma(x) = eta(x) prod_i s(z_i)^y_i (1 - s(z_i))^(1-y_i),
  *                 z_i = X[i,:] . x, s the logistic function;  X[n][d]
- *                 row-major, y[n] in {0, 1}.  ell is the log-likelihood.
+ *                 row-major, y[n] in {0, 1} (a label other than 0 is read
+ *                 as 1).  ell is the log-likelihood.
  *   OASMC_GMM   : gamma(x) = (1/K) sum_k exp(-|x - means[k]|^2 / (2 exp(2 log_scales[k])))
  *                 means[K][d], log_scales[K].
  *   eta         : N(ref_mean, ref_sigma2 I); ref_mean may be NULL (zero mean).
