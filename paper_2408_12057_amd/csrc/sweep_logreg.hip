@@ -36,11 +36,12 @@
 namespace oasmc {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
-// X and y are read through global-address-space pointers: the pointers
-// arrive through a descriptor in memory, so the compiler cannot infer the
-// address space, and flat loads would share the LDS wait counter (every LDS
-// wait in the chunk loop would then also wait for the next chunk's prefetch).
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+// The packed rows (and the schedule) are read through global-address-space
+// pointers: the pointers arrive through a descriptor in memory, so the
+// compiler cannot infer the address space, and flat loads would share the LDS
+// wait counter (every LDS wait in the chunk loop would then also wait for the
+// next chunk's prefetch).
 typedef __attribute__((address_space(1))) const float gmem_f;
 typedef __attribute__((address_space(1))) const floatx4 gmem_f4;
 
