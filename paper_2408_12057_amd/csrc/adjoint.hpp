@@ -34,7 +34,8 @@ __global__ void __launch_bounds__(256) k_adjoint_gmm(AdjointArgs A)
     const Consts c = make_consts(a.tg);
     const int lane = threadIdx.x & (kWave - 1);
     const int r = lane % LPP, pl = lane / LPP;
-    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t wave =
+        (int64_t)blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     if (wave >= a.ntiles) return;  // the whole wave leaves together
     const int64_t n64 = wave * P + pl;
     const bool valid = n64 < a.N;

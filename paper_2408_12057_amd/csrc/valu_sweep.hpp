@@ -559,7 +559,7 @@ __global__ void __launch_bounds__(256) k_oais_valu(SweepArgs a)
     extern __shared__ __align__(16) char sh_dyn[];
     const ParView pv = stage_params(a.tg, sh_dyn);
     const Consts c = make_consts(a.tg);
-    const int wv = threadIdx.x / kWave;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
     const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + wv;
     const int64_t W = (int64_t)gridDim.x * kWavesPerBlock;
     for (int64_t slot = gw; slot < a.S; slot += W)
@@ -577,7 +577,11 @@ __global__ void __launch_bounds__(256) k_oais_valu_batch(const SweepArgs* __rest
 {
     __shared__ double2 sh_rec[kWavesPerBlock][kTC][kWave / LPP];
     __shared__ uint32_t sh_cnt[kWavesPerBlock][kTC];
-    const int wv = threadIdx.x / kWave;
+    // the wave index through readfirstlane, so that the compiler sees the
+    // work item, its arguments and its parameter view as wave-uniform (scalar
+    // loads into scalar registers instead of per-lane copies in vector
+    // registers)
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + wv;
     const int64_t W = (int64_t)gridDim.x * kWavesPerBlock;
     for (int64_t it = gw; it < nitems; it += W) {
