@@ -177,7 +177,7 @@ __device__ __forceinline__ int wave_rows(int n_pad) { return n_pad / LCfg::waves
 __device__ __forceinline__ Slice fetch_slice(const float* Xp, int n_pad, int c)
 {
     const int l = threadIdx.x % kWave;
-    const int r0 = (threadIdx.x / kWave) * wave_rows(n_pad);
+    const int r0 = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave) * wave_rows(n_pad);
     gmem_f* const Xg = (gmem_f*)Xp;
     const gmem_f4* src = (const gmem_f4*)(Xg + (size_t)(r0 + c * kRows + l / 2) * 64 + (l % 2) * 32);
     Slice t;
@@ -234,7 +234,7 @@ __device__ __forceinline__ void contraction(LogregShared& sh, const float* __res
     constexpr int kLWaves = LCfg::waves;
     constexpr double kLn2 = 0.693147180559945309;
     const int tid = threadIdx.x;
-    const int w = tid / kWave;
+    const int w = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
     const int l = tid % kWave;
     const int h = l / 32;
     const int j = l % 32;
@@ -439,7 +439,7 @@ __device__ __forceinline__ void logreg_slot(LogregShared& sh, const LogregArgs& 
                     // moment i = wave index of the pre-move weights times
                     // g_t^i: a max and a sum of exps over the 64 particles
                     // (the weights themselves advance in the correction)
-                    const int i = tid / kWave, q = tid % kWave;
+                    const int i = __builtin_amdgcn_readfirstlane(tid / kWave), q = tid % kWave;
                     const bool vq = (tile * kLP + q) < a.N;
                     const double lg = (beta - beta_prev) * sh.ll[q];
                     const double x = vq ? sh.lw[q] + (double)i * lg : -INFINITY;
