@@ -428,6 +428,17 @@ struct Particle {
 constexpr int kTC = 8;      // steps buffered before a transposed reduction
 constexpr int kWavesPerBlock = 4;
 
+// Minimum waves per SIMD requested from the compiler for the resampling
+// variant's step kernel: three for particles with at most 8 coordinates per
+// lane (the register budget then costs a few spills and buys a third wave:
+// 15% faster for the mixture/HMC step), the compiler's choice otherwise (wider
+// lanes would spill heavily).  The AIS sweeps, which keep more state across
+// their time loop, measured slower with the same request.
+template <int DPL>
+struct MinWaves {
+    static constexpr int value = DPL <= 8 ? 3 : 1;
+};
+
 // All tiles of one slot of one problem, in tile order (one wave).  The
 // moments of a slot therefore accumulate in the same order whichever wave,
 // kernel or launch processes the slot.
@@ -605,7 +616,8 @@ __global__ void __launch_bounds__(256) k_asmc_init(SweepArgs a, AsmcState z)
     const Consts c = make_consts(a.tg);
     const int lane = threadIdx.x & (kWave - 1);
     const int r = lane % LPP, pl = lane / LPP;
-    const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t tile =
+        (int64_t)blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int64_t n64 = tile * P + pl;
     if (tile >= a.ntiles || n64 >= a.N) return;
     float x[DPL];
@@ -628,7 +640,8 @@ __global__ void __launch_bounds__(256) k_asmc_init(SweepArgs a, AsmcState z)
 }
 
 template <int FAM, int MOVE, int LPP, int DPL>
-__global__ void __launch_bounds__(256) k_asmc_step(SweepArgs a, AsmcState z, int t)
+__global__ void __launch_bounds__(256, MinWaves<DPL>::value)
+    k_asmc_step(SweepArgs a, AsmcState z, int t)
 {
     constexpr int P = kWave / LPP;
     extern __shared__ __align__(16) char sh_dyn[];
@@ -636,7 +649,8 @@ __global__ void __launch_bounds__(256) k_asmc_step(SweepArgs a, AsmcState z, int
     const Consts c = make_consts(a.tg);
     const int lane = threadIdx.x & (kWave - 1);
     const int r = lane % LPP, pl = lane / LPP;
-    const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t tile =
+        (int64_t)blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     if (tile >= a.ntiles) return;  // whole wave leaves together
     const int64_t n64 = tile * P + pl;
     const bool valid = n64 < a.N;
