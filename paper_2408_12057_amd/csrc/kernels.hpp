@@ -60,6 +60,9 @@ struct SweepArgs {
     int ckpt_every;
 };
 
+// Blocks of the first level of the per-step merge in the resampling variant.
+constexpr int kAsmcMergeBlocks = 64;
+
 // State of the particle system between steps of the resampling variant.
 struct AsmcState {
     float* X;          // [N*d] current states
@@ -71,6 +74,7 @@ struct AsmcState {
     double* lw;        // [N]
     uint32_t* accw;    // [N] accept bits of the current 32-step word
     double* tile_part; // [ntiles*8]
+    double* blk_part;  // [kAsmcMergeBlocks*8] per-block merge of tile_part
     // scalars updated on the device
     double* scal;      // [0] log Z_hat, [1] max(lw) at event, [2] flag, [3] u word
     int* nres;         // [1]

@@ -92,7 +92,7 @@ namespace {
 enum BufId {
     B_BETA, B_EPS, B_PART, B_LOGG, B_ACC, B_SCAL, B_X, B_X2, B_ELL, B_ELL2, B_LW, B_ACCW,
     B_TPART, B_NRES, B_ESS, B_RES, B_C, B_BTOT, B_LWO, B_XO, B_LOGREG, B_CKPT, B_SEG, B_ABITS,
-    B_GPART, B_GRAD, B_DEVRUN, B_DEVDESC, B_G, B_G2, B_COUNT
+    B_GPART, B_GRAD, B_DEVRUN, B_DEVDESC, B_G, B_G2, B_BLK, B_COUNT
 };
 
 template <typename T>
@@ -838,6 +838,7 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
         HIP_TRY(wget(h, B_LW, N, &z.lw));
         HIP_TRY(wget(h, B_ACCW, N, &z.accw));
         HIP_TRY(wget(h, B_TPART, (size_t)ntiles * 8, &z.tile_part));
+        HIP_TRY(wget(h, B_BLK, (size_t)kAsmcMergeBlocks * 8, &z.blk_part));
         HIP_TRY(wget(h, B_NRES, 4, &z.nres));
         HIP_TRY(wget(h, B_ESS, T, &z.ess));
         HIP_TRY(wget(h, B_RES, T, &z.resampled));

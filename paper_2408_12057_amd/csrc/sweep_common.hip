@@ -54,20 +54,34 @@ __global__ void __launch_bounds__(kWave) k_merge_slots(const double* __restrict_
     }
 }
 
-// One block: merge the tile statistics of step t (fixed order), record the
-// moments, ESS, the event decision and the log Z_hat increment.
-constexpr int kMergeThreads = 1024;
-__global__ void __launch_bounds__(kMergeThreads) k_asmc_merge(SweepArgs a, AsmcState z, int t,
-                                                              int trigger, double nu)
+// The per-step merge of the resampling variant, in two levels with a fixed
+// order (deterministic, independent of timing): block b of the first level
+// reduces a contiguous range of tile records to one record (log-sum-exps as a
+// maximum and then a sum of exp(x - max)); one wave then merges the block
+// records, records the moments, ESS and CESS, decides the event and adds the
+// log Z_hat increment.
+constexpr int kMergeThreads = 256;
+
+__device__ __forceinline__ int merge_blocks(int64_t ntiles)
+{
+    const int64_t nb = (ntiles + kMergeThreads - 1) / kMergeThreads;
+    return (int)(nb < kAsmcMergeBlocks ? nb : kAsmcMergeBlocks);
+}
+
+__global__ void __launch_bounds__(kMergeThreads) k_asmc_merge_part(SweepArgs a, AsmcState z)
 {
     constexpr int W = kMergeThreads / kWave;
     __shared__ double shm[W][6];
     __shared__ double res[6];
     const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
-    // pass 1: maxima and the accept count
+    const int nb = merge_blocks(a.ntiles);
+    const int64_t per = (a.ntiles + nb - 1) / nb;
+    const int64_t k0 = (int64_t)blockIdx.x * per;
+    const int64_t k1 = (k0 + per < a.ntiles) ? k0 + per : a.ntiles;
+    // pass 1: maxima (the four log-sums and the largest log w) and the count
     double m[5] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY, -INFINITY};
     double cnt = 0.0;
-    for (int64_t k = tid; k < a.ntiles; k += kMergeThreads) {
+    for (int64_t k = k0 + tid; k < k1; k += kMergeThreads) {
         const double* tp = z.tile_part + (size_t)k * 8;
 #pragma unroll
         for (int i = 0; i < 5; ++i) m[i] = fmax(m[i], tp[i]);
@@ -83,67 +97,80 @@ __global__ void __launch_bounds__(kMergeThreads) k_asmc_merge(SweepArgs a, AsmcS
     }
     __syncthreads();
     if (tid == 0) {
-        double r[6];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) r[i] = shm[0][i];
+        for (int i = 0; i < 6; ++i) res[i] = shm[0][i];
         for (int ww = 1; ww < W; ++ww) {
 #pragma unroll
-            for (int i = 0; i < 5; ++i) r[i] = fmax(r[i], shm[ww][i]);
-            r[5] += shm[ww][5];
+            for (int i = 0; i < 5; ++i) res[i] = fmax(res[i], shm[ww][i]);
+            res[5] += shm[ww][5];
         }
-#pragma unroll
-        for (int i = 0; i < 6; ++i) res[i] = r[i];
     }
     __syncthreads();
     double M[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) M[i] = res[i];
-    const double mx = res[4], total = res[5];
-    __syncthreads();
     // pass 2: sums of exp(L_tile - max)
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t k = tid; k < a.ntiles; k += kMergeThreads) {
+    double sm[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t k = k0 + tid; k < k1; k += kMergeThreads) {
         const double* tp = z.tile_part + (size_t)k * 8;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            if (M[i] > -INFINITY && tp[i] > -INFINITY) s[i] += exp(tp[i] - M[i]);
+            if (M[i] > -INFINITY && tp[i] > -INFINITY) sm[i] += exp(tp[i] - M[i]);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) s[i] = wave_sum(s[i]);
+    for (int i = 0; i < 4; ++i) sm[i] = wave_sum(sm[i]);
+    __syncthreads();  // every thread has read res
     if (lane == 0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) shm[w][i] = s[i];
+        for (int i = 0; i < 4; ++i) shm[w][i] = sm[i];
     }
     __syncthreads();
     if (tid == 0) {
-        double L[4];
+        double* out = z.blk_part + (size_t)blockIdx.x * 8;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             double acc = shm[0][i];
             for (int ww = 1; ww < W; ++ww) acc += shm[ww][i];
-            L[i] = lse_value(M[i], acc);
+            out[i] = lse_value(M[i], acc);
         }
-        const int T = a.T;
-        const double logN = log((double)a.N);
-        for (int i = 0; i < 3; ++i) z.log_g[(size_t)i * T + (t - 1)] = L[i];
-        z.accept[t - 1] = total;
-        const double rel_ess = exp(2.0 * L[1] - L[3] - logN);
-        const double rel_cess = exp(-(L[2] - 2.0 * L[1] + L[0]));
-        z.ess[t - 1] = rel_ess;
-        const bool fire = (trigger == 0) ? (rel_ess < nu) : (rel_cess < nu);
-        z.resampled[t - 1] = 0;
-        z.scal[2] = 0.0;
-        if (t == T) {
-            z.scal[0] += L[1] - logN;
-        } else if (fire) {
-            z.scal[0] += L[1] - logN;
-            z.scal[1] = mx;
-            z.scal[2] = 1.0;
-            const uint4 wd = draw_block(a.key, 0xFFFFFFFFu, (uint32_t)t, kStreamResample, 0u, 0u);
-            z.scal[3] = (double)wd.x;
-            z.resampled[t - 1] = 1;
-            z.nres[0] += 1;
-        }
+        out[4] = res[4];
+        out[5] = res[5];
+    }
+}
+
+__global__ void __launch_bounds__(kWave) k_asmc_merge(SweepArgs a, AsmcState z, int t,
+                                                      int trigger, double nu)
+{
+    const int lane = threadIdx.x;
+    const int nb = merge_blocks(a.ntiles);
+    const double* rec = z.blk_part + (size_t)lane * 8;
+    const bool have = lane < nb;
+    double L[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) L[i] = wave_lse(have ? rec[i] : -INFINITY);
+    const double mx = wave_max(have ? rec[4] : -INFINITY);
+    const double total = wave_sum(have ? rec[5] : 0.0);
+    if (lane != 0) return;
+    const int T = a.T;
+    const double logN = log((double)a.N);
+    for (int i = 0; i < 3; ++i) z.log_g[(size_t)i * T + (t - 1)] = L[i];
+    z.accept[t - 1] = total;
+    const double rel_ess = exp(2.0 * L[1] - L[3] - logN);
+    const double rel_cess = exp(-(L[2] - 2.0 * L[1] + L[0]));
+    z.ess[t - 1] = rel_ess;
+    const bool fire = (trigger == 0) ? (rel_ess < nu) : (rel_cess < nu);
+    z.resampled[t - 1] = 0;
+    z.scal[2] = 0.0;
+    if (t == T) {
+        z.scal[0] += L[1] - logN;
+    } else if (fire) {
+        z.scal[0] += L[1] - logN;
+        z.scal[1] = mx;
+        z.scal[2] = 1.0;
+        const uint4 wd = draw_block(a.key, 0xFFFFFFFFu, (uint32_t)t, kStreamResample, 0u, 0u);
+        z.scal[3] = (double)wd.x;
+        z.resampled[t - 1] = 1;
+        z.nres[0] += 1;
     }
 }
 
@@ -447,7 +474,10 @@ hipError_t launch_asmc_step(const SweepArgs& a, const ValuShape& s, const AsmcSt
 {
     hipError_t e = dispatch_all(2, a, s, 0, &z, t, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_asmc_merge, dim3(1), dim3(kMergeThreads), 0, st, a, z, t, trigger, nu);
+    const int64_t nb = std::min<int64_t>((a.ntiles + kMergeThreads - 1) / kMergeThreads,
+                                         kAsmcMergeBlocks);
+    hipLaunchKernelGGL(k_asmc_merge_part, dim3((unsigned)nb), dim3(kMergeThreads), 0, st, a, z);
+    hipLaunchKernelGGL(k_asmc_merge, dim3(1), dim3(kWave), 0, st, a, z, t, trigger, nu);
     return hipGetLastError();
 }
 
