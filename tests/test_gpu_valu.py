@@ -84,7 +84,10 @@ def test_ais_round_matches_oracle(oa, family, d, move, N, T, K):
 
 @pytest.mark.parametrize("trigger", ["ess", "cess"])
 @pytest.mark.parametrize("family,d,move,N,T,K", [("gauss", 4, "hmc", 300, 12, 0),
-                                                 ("gmm", 20, "mala", 2100, 10, 4)])
+                                                 ("gmm", 20, "mala", 2100, 10, 4),
+                                                 # > 64 x 256 tiles: several tile records
+                                                 # per thread in the first merge level
+                                                 ("gauss", 4, "rwmh", 2200000, 3, 0)])
 def test_resampling_round_matches_oracle(oa, family, d, move, N, T, K, trigger):
     """Adaptive resampling: same events, same ancestors (integer CDF), same
     final population and log Z_hat."""
