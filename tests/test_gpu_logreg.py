@@ -52,7 +52,10 @@ def _bounds(X, y, theta):
 
 
 @pytest.mark.parametrize("n,d,N", [(1000, 50, 200), (777, 7, 64), (300, 64, 65), (5000, 33, 130),
-                                   (1, 1, 1)])
+                                   (1, 1, 1),
+                                   (512, 50, 100),    # no padding rows
+                                   (257, 20, 70),     # one data row in the last chunk
+                                   (2048, 64, 64)])   # widest layout, whole chunks only
 def test_contraction_within_fp32_bound(oa, n, d, N):
     X, y, th_star = wl.logreg_data(n, d, 1000 + n + d)
     rng = np.random.default_rng(n)
