@@ -30,7 +30,7 @@ __global__ void __launch_bounds__(256) k_adjoint_gmm(AdjointArgs A)
     constexpr int P = kWave / LPP;
     const SweepArgs& a = A.a;
     extern __shared__ __align__(16) char sh_dyn[];
-    const ParView pv = stage_params(a.tg, sh_dyn);
+    const ParView pv = stage_params_lanes<LPP, DPL>(a.tg, sh_dyn);
     const Consts c = make_consts(a.tg);
     const int lane = threadIdx.x & (kWave - 1);
     const int r = lane % LPP, pl = lane / LPP;
@@ -206,7 +206,7 @@ hipError_t launch_adjoint_t(const AdjointArgs& A, hipStream_t st)
 {
     const int64_t blocks = (A.a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
     hipLaunchKernelGGL((k_adjoint_gmm<LPP, DPL, KB>), dim3((unsigned)blocks), dim3(256),
-                       params_bytes(A.a.tg), st, A);
+                       params_bytes_lanes(A.a.tg, LPP, DPL), st, A);
     return hipGetLastError();
 }
 

@@ -31,13 +31,27 @@ struct TargetDev {
 
 // Pointers to a problem's target parameters as the particle code reads them:
 // reference mean [d], Gaussian mean [d] or mixture means [K*d], and the
-// mixture's 1/(2 v_k), 1/v_k.
+// mixture's 1/(2 v_k), 1/v_k.  lm and lmu hold the same means in binary64 in
+// the lane layout of a sweep shape (LPP lanes of DPL coordinates): element
+// (k, j, r) at (k DPL + j) LPP + r is coordinate r DPL + j of mean k, zero
+// beyond d, so a wave reads them without bank conflicts and padded
+// coordinates need no branch.
 struct ParView {
     const float* m;
     const float* mu;
     const double* hiv;
     const double* iv;
+    const double* lm;   // [DPL][LPP]
+    const double* lmu;  // [K or 1][DPL][LPP]
 };
+
+// Means held by the lane layout: the Gaussian mean, or the K mixture means.
+__host__ __device__ inline int lane_means(const TargetDev& tg) { return tg.family == kGmm ? tg.K : 1; }
+// Doubles of the lane-layout arrays lm and lmu for one sweep shape.
+__host__ __device__ inline size_t lane_param_doubles(const TargetDev& tg, int lpp, int dpl)
+{
+    return (size_t)(1 + lane_means(tg)) * lpp * dpl;
+}
 
 // Arguments of one annealing pass.
 struct SweepArgs {
@@ -59,6 +73,22 @@ struct SweepArgs {
     float* ckpt;           // device [N][ceil(T/ckpt_every)][d] states before steps 1, 1+every, ... or null
     int ckpt_every;
 };
+
+// Element e of the lane layout of (reference mean, target means) for a shape
+// of LPP lanes x DPL coordinates: mean k (0 = reference), coordinate
+// r DPL + j, zero beyond d.
+__device__ __forceinline__ double lane_param(const TargetDev& tg, int lpp, int dpl, int e)
+{
+    const int k = e / (dpl * lpp);
+    const int rem = e - k * dpl * lpp;
+    const int j = rem / lpp;
+    const int r = rem - j * lpp;
+    const int i = r * dpl + j;
+    if (i >= tg.d) return 0.0;
+    if (k == 0) return tg.ref_mean ? (double)tg.ref_mean[i] : 0.0;
+    const float* src = (tg.family == kGmm) ? tg.means : tg.mu;
+    return (double)src[(size_t)(k - 1) * tg.d + i];
+}
 
 // Blocks of the first level of the per-step merge in the resampling variant.
 constexpr int kAsmcMergeBlocks = 64;
@@ -106,10 +136,18 @@ struct ValuBatch {
 };
 hipError_t launch_oais_valu_batch(int family, int move, const ValuShape& s, const ValuBatch& b,
                                   int grid_waves, hipStream_t st);
-// Fills per-problem parameter buffers (reference mean, 1/(2 v_k), 1/v_k) for
-// batched launches: m[d], hiv[K], iv[K] at the given device addresses.
-hipError_t launch_batch_params(const TargetDev* tgs, float* const* m, double* const* hiv,
-                               double* const* iv, int nprob, hipStream_t st);
+// Per-problem parameter buffers of a batched launch (device addresses) and the
+// sweep shape whose lane layout lane[] takes.
+struct BatchParam {
+    float* m;       // [d] reference mean
+    double* hiv;    // [kMaxK] 1/(2 v_k)
+    double* iv;     // [kMaxK] 1/v_k
+    double* lane;   // [lane_param_doubles] lm, then lmu
+    int lpp, dpl;
+};
+// Fills the buffers of every problem with a non-null m (one block each).
+hipError_t launch_batch_params(const TargetDev* tgs, const BatchParam* bp, int nprob,
+                               hipStream_t st);
 int64_t valu_tiles(int64_t N, const ValuShape& s);
 
 hipError_t launch_oais_valu(const SweepArgs& a, const ValuShape& s, int grid_waves,

@@ -367,8 +367,11 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
         q.off_scratch = off;
         off += align256(sizeof(double) * 3 * (size_t)(q.Tcap + 1));
         q.off_par = off;
-        if (!q.logreg)
-            off += align256(sizeof(float) * q.prob.d + 2 * sizeof(double) * kMaxK);
+        if (!q.logreg) {
+            const TargetDev tg = target_dev(&q.prob);
+            off += align256(sizeof(float) * q.prob.d) + align256(2 * sizeof(double) * kMaxK) +
+                   align256(sizeof(double) * lane_param_doubles(tg, q.shape.lpp, q.shape.dpl));
+        }
         q.off_data = off;
         if (q.logreg) {
             const int np = logreg_npad(q.prob.n);
@@ -382,7 +385,7 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
         ws = static_cast<char*>(v);
     }
     // descriptors: SweepArgs [R][P], LogregArgs [R][P], ParView [P], RoundDev [R][P],
-    // TargetDev [P], param pointers [3][P], items per class
+    // TargetDev [P], BatchParam [P], items per class
     struct ClassKey {
         bool logreg; int fam, move, lpp, dpl, kh;
         bool operator==(const ClassKey& o) const
@@ -422,7 +425,7 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
     const size_t d_view = dsz; dsz += align256(sizeof(ParView) * P);
     const size_t d_round = dsz; dsz += align256(sizeof(RoundDev) * R * P);
     const size_t d_tg = dsz; dsz += align256(sizeof(TargetDev) * P);
-    const size_t d_pp = dsz; dsz += align256(sizeof(void*) * 3 * P);
+    const size_t d_pp = dsz; dsz += align256(sizeof(BatchParam) * P);
     std::vector<size_t> d_items(classes.size());
     for (size_t c = 0; c < classes.size(); ++c) { d_items[c] = dsz; dsz += align256(sizeof(int2) * items[c].size()); }
     char* dd;
@@ -440,20 +443,29 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
         double* beta0 = at<double>(ws, q.off_sched);
         double* eps0 = beta0 + (size_t)(R + 1) * (q.Tcap + 1);
         // parameter view (closed-form families): m [d] floats, then 1/(2 v_k) and
-        // 1/v_k (kMaxK doubles each); none for logistic regression
+        // 1/v_k (kMaxK doubles each), then the lane-layout means of the
+        // problem's sweep shape; none for logistic regression
         ParView v{};
+        BatchParam bp{};
         if (!q.logreg) {
-            v.m = at<float>(ws, q.off_par);
-            v.hiv = reinterpret_cast<const double*>(ws + q.off_par + align256(sizeof(float) * q.prob.d));
-            v.iv = v.hiv + kMaxK;
+            char* base = ws + q.off_par;
+            bp.m = reinterpret_cast<float*>(base);
+            bp.hiv = reinterpret_cast<double*>(base + align256(sizeof(float) * q.prob.d));
+            bp.iv = bp.hiv + kMaxK;
+            bp.lane = reinterpret_cast<double*>(base + align256(sizeof(float) * q.prob.d) +
+                                                align256(2 * sizeof(double) * kMaxK));
+            bp.lpp = q.shape.lpp;
+            bp.dpl = q.shape.dpl;
+            v.m = bp.m;
+            v.hiv = bp.hiv;
+            v.iv = bp.iv;
             v.mu = (q.prob.family == OASMC_GMM) ? q.prob.means : q.prob.mu;
+            v.lm = bp.lane;
+            v.lmu = bp.lane + (size_t)bp.lpp * bp.dpl;
         }
         reinterpret_cast<ParView*>(blob.data() + d_view)[p] = v;
         reinterpret_cast<TargetDev*>(blob.data() + d_tg)[p] = target_dev(&q.prob);
-        void** pp = reinterpret_cast<void**>(blob.data() + d_pp);
-        pp[p] = (void*)v.m;
-        pp[P + p] = (void*)v.hiv;
-        pp[2 * P + p] = (void*)v.iv;
+        reinterpret_cast<BatchParam*>(blob.data() + d_pp)[p] = bp;
         for (int k = 0; k < R; ++k) {
             const int T = q.Ts[k];
             SweepArgs a{};
@@ -525,11 +537,9 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
             if (!ps[p].logreg) vp.push_back(p);
         if (!vp.empty()) {
             const TargetDev* tgs = reinterpret_cast<const TargetDev*>(dd + d_tg);
-            float* const* pm = reinterpret_cast<float* const*>(dd + d_pp);
-            double* const* ph = reinterpret_cast<double* const*>(dd + d_pp + sizeof(void*) * P);
-            double* const* pi = reinterpret_cast<double* const*>(dd + d_pp + 2 * sizeof(void*) * P);
+            const BatchParam* bps = reinterpret_cast<const BatchParam*>(dd + d_pp);
             // logistic-regression entries have null pointers and are skipped by family
-            HIP_TRY(launch_batch_params(tgs, pm, ph, pi, P, st));
+            HIP_TRY(launch_batch_params(tgs, bps, P, st));
         }
         for (int p = 0; p < P; ++p)
             if (ps[p].logreg) {

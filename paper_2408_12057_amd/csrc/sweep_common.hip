@@ -435,26 +435,28 @@ hipError_t launch_oais_valu_batch(int family, int move, const ValuShape& s, cons
     return dispatch_all(3, a, s, grid_waves, nullptr, 0, st, &b);
 }
 
-__global__ void k_batch_params(const TargetDev* __restrict__ tgs, float* const* m,
-                               double* const* hiv, double* const* iv)
+__global__ void k_batch_params(const TargetDev* __restrict__ tgs, const BatchParam* __restrict__ bps)
 {
     const TargetDev& tg = tgs[blockIdx.x];
+    const BatchParam& bp = bps[blockIdx.x];
     // problems without a parameter view (logistic regression) are skipped
-    if (tg.family == kLogreg || m[blockIdx.x] == nullptr) return;
+    if (tg.family == kLogreg || bp.m == nullptr) return;
     for (int i = threadIdx.x; i < tg.d; i += blockDim.x)
-        m[blockIdx.x][i] = tg.ref_mean ? tg.ref_mean[i] : 0.f;
-    if (tg.family == kGmm && hiv[blockIdx.x] != nullptr && iv[blockIdx.x] != nullptr)
+        bp.m[i] = tg.ref_mean ? tg.ref_mean[i] : 0.f;
+    if (tg.family == kGmm)
         for (int k = threadIdx.x; k < tg.K; k += blockDim.x) {
             const double v = exp(2.0 * (double)tg.log_scales[k]);
-            hiv[blockIdx.x][k] = 0.5 / v;
-            iv[blockIdx.x][k] = 1.0 / v;
+            bp.hiv[k] = 0.5 / v;
+            bp.iv[k] = 1.0 / v;
         }
+    const int nl = (int)lane_param_doubles(tg, bp.lpp, bp.dpl);
+    for (int e = threadIdx.x; e < nl; e += blockDim.x) bp.lane[e] = lane_param(tg, bp.lpp, bp.dpl, e);
 }
 
-hipError_t launch_batch_params(const TargetDev* tgs, float* const* m, double* const* hiv,
-                               double* const* iv, int nprob, hipStream_t st)
+hipError_t launch_batch_params(const TargetDev* tgs, const BatchParam* bp, int nprob,
+                               hipStream_t st)
 {
-    hipLaunchKernelGGL(k_batch_params, dim3(nprob), dim3(64), 0, st, tgs, m, hiv, iv);
+    hipLaunchKernelGGL(k_batch_params, dim3(nprob), dim3(64), 0, st, tgs, bp);
     return hipGetLastError();
 }
 

@@ -85,33 +85,81 @@ inline size_t params_bytes(const TargetDev& tg)
     return 2 * kMaxK * sizeof(double) + (size_t)(tg.d + nmu) * sizeof(float);
 }
 
+// Offset of the lane-layout arrays behind the staged parameters (8-aligned).
+__host__ __device__ inline size_t lane_params_offset(const TargetDev& tg)
+{
+    const int nmu = (tg.family == kGmm) ? tg.K * tg.d : tg.d;
+    return (2 * kMaxK * sizeof(double) + (size_t)(tg.d + nmu) * sizeof(float) + 7) & ~(size_t)7;
+}
+
+// The same staging followed by the binary64 lane-layout means lm, lmu of the
+// shape (LPP, DPL).
+template <int LPP, int DPL>
+__device__ __forceinline__ ParView stage_params_lanes(const TargetDev& tg, char* sh)
+{
+    const ParView base = stage_params(tg, sh);
+    double* lane = reinterpret_cast<double*>(sh + lane_params_offset(tg));
+    const int nl = (int)lane_param_doubles(tg, LPP, DPL);
+    for (int e = threadIdx.x; e < nl; e += blockDim.x) lane[e] = lane_param(tg, LPP, DPL, e);
+    __syncthreads();
+    return ParView{base.m, base.mu, base.hiv, base.iv, lane, lane + LPP * DPL};
+}
+
+inline size_t params_bytes_lanes(const TargetDev& tg, int lpp, int dpl)
+{
+    return lane_params_offset(tg) + lane_param_doubles(tg, lpp, dpl) * sizeof(double);
+}
+
 // ---------------------------------------------------------------------------
 // Particle arithmetic for one lane group.
 // ---------------------------------------------------------------------------
+// Coordinates of a lane beyond d (the tail of the last lanes' slices) hold
+// exact zeros in x, z, the momentum and the gradient, and the lane-layout
+// means are zero there too, so every coordinate loop runs without a branch:
+// a padded coordinate adds +0 to each sum and stays +0 through every move.
 template <int FAM, int LPP, int DPL>
 struct Particle {
+    // reference mean and target mean k at this lane's coordinate j
+    static __device__ __forceinline__ double ref(const ParView& pv, int r, int j)
+    {
+        return pv.lm[j * LPP + r];
+    }
+    static __device__ __forceinline__ double mean(const ParView& pv, int k, int r, int j)
+    {
+        return pv.lmu[(k * DPL + j) * LPP + r];
+    }
+    // The view with an offset the compiler cannot see through (always zero):
+    // the means are then re-read from LDS at each evaluation instead of being
+    // hoisted out of the time and leapfrog loops into registers, which for
+    // K d / LPP beyond a few dozen would spill.
+    static __device__ __forceinline__ ParView fresh(const ParView& pv)
+    {
+        int z0;
+        asm volatile("s_mov_b32 %0, 0" : "=s"(z0));
+        ParView v = pv;
+        v.lm = pv.lm + z0;
+        v.lmu = pv.lmu + z0;
+        return v;
+    }
+
     // ell(x) = log gamma(x) - log eta(x); with GRAD also its gradient on this
     // lane's coordinates.  r = lane index inside the group.
     template <bool GRAD>
     static __device__ __forceinline__ double eval(const TargetDev& tg, const Consts& c,
-                                                  const ParView& pv, int r, const float (&x)[DPL],
+                                                  const ParView& pv0, int r, const float (&x)[DPL],
                                                   double (&g)[DPL])
     {
-        const int d = tg.d;
-        const int i0 = r * DPL;
+        const ParView pv = fresh(pv0);
         if constexpr (FAM == kGauss) {
             double ssg = 0.0, sse = 0.0;
 #pragma unroll
             for (int j = 0; j < DPL; ++j) {
-                const int i = i0 + j;
-                if (i < d) {
-                    const double xv = (double)x[j];
-                    const double a = xv - (double)pv.mu[i];
-                    const double b = xv - (double)pv.m[i];
-                    ssg = fma(a, a, ssg);
-                    sse = fma(b, b, sse);
-                    if (GRAD) g[j] = -a * c.inv_s2 + b * c.inv_s2r;
-                }
+                const double xv = (double)x[j];
+                const double a = xv - mean(pv, 0, r, j);
+                const double b = xv - ref(pv, r, j);
+                ssg = fma(a, a, ssg);
+                sse = fma(b, b, sse);
+                if (GRAD) g[j] = -a * c.inv_s2 + b * c.inv_s2r;
             }
             const double part = -ssg * c.half_inv_s2 + sse * c.half_inv_s2r;
             return group_sum<LPP>(part) + c.cst_eta;
@@ -121,12 +169,9 @@ struct Particle {
             double sse = 0.0;
 #pragma unroll
             for (int j = 0; j < DPL; ++j) {
-                const int i = i0 + j;
-                if (i < d) {
-                    const double b = (double)x[j] - (double)pv.m[i];
-                    sse = fma(b, b, sse);
-                    if (GRAD) g[j] = 0.0;
-                }
+                const double b = (double)x[j] - ref(pv, r, j);
+                sse = fma(b, b, sse);
+                if (GRAD) g[j] = 0.0;
             }
             sse = group_sum<LPP>(sse);
             if constexpr (LPP > 1) {
@@ -136,14 +181,10 @@ struct Particle {
 #pragma unroll 1
             for (int k = 0; k < tg.K; ++k) {
                 double sq = 0.0;
-                const float* mk = pv.mu + k * d;
 #pragma unroll
                 for (int j = 0; j < DPL; ++j) {
-                    const int i = i0 + j;
-                    if (i < d) {
-                        const double a = (double)x[j] - (double)mk[i];
-                        sq = fma(a, a, sq);
-                    }
+                    const double a = (double)x[j] - mean(pv, k, r, j);
+                    sq = fma(a, a, sq);
                 }
                 const double ek = -group_sum<LPP>(sq) * pv.hiv[k];
                 double wk;
@@ -163,20 +204,16 @@ struct Particle {
                 if (GRAD) {
                     const double f = wk * pv.iv[k];
 #pragma unroll
-                    for (int j = 0; j < DPL; ++j) {
-                        const int i = i0 + j;
-                        if (i < d) g[j] = fma(f, (double)mk[i] - (double)x[j], g[j]);
-                    }
+                    for (int j = 0; j < DPL; ++j)
+                        g[j] = fma(f, mean(pv, k, r, j) - (double)x[j], g[j]);
                 }
             }
             const double lse = mx + log(s) - c.logK;
             if (GRAD) {
                 const double inv_s = 1.0 / s;
 #pragma unroll
-                for (int j = 0; j < DPL; ++j) {
-                    const int i = i0 + j;
-                    if (i < d) g[j] = g[j] * inv_s + ((double)x[j] - (double)pv.m[i]) * c.inv_s2r;
-                }
+                for (int j = 0; j < DPL; ++j)
+                    g[j] = g[j] * inv_s + ((double)x[j] - ref(pv, r, j)) * c.inv_s2r;
             }
             return lse + sse * c.half_inv_s2r + c.cst_eta;
         }
@@ -196,9 +233,7 @@ struct Particle {
                                                                double (&g)[DPL], double sse)
     {
         constexpr int KO = (kMaxK + LPP - 1) / LPP;  // components owned by a lane
-        const int d = tg.d;
         const int K = tg.K;
-        const int i0 = r * DPL;
         double eo[KO];
 #pragma unroll
         for (int q = 0; q < KO; ++q) eo[q] = -INFINITY;
@@ -206,15 +241,11 @@ struct Particle {
 #pragma unroll
         for (int k = 0; k < kMaxK; ++k) {
             if (k < K) {
-                const float* mk = pv.mu + k * d;
                 double sq = 0.0;
 #pragma unroll
                 for (int j = 0; j < DPL; ++j) {
-                    const int i = i0 + j;
-                    if (i < d) {
-                        const double a = (double)x[j] - (double)mk[i];
-                        sq = fma(a, a, sq);
-                    }
+                    const double a = (double)x[j] - mean(pv, k, r, j);
+                    sq = fma(a, a, sq);
                 }
                 const double ek = -group_sum<LPP>(sq) * pv.hiv[k];
                 M = fmax(M, ek);
@@ -236,20 +267,15 @@ struct Particle {
             for (int k = 0; k < kMaxK; ++k) {
                 if (k < K) {
                     const double f = __shfl(wo[k / LPP], base + k % LPP, kWave) * pv.iv[k];
-                    const float* mk = pv.mu + k * d;
 #pragma unroll
-                    for (int j = 0; j < DPL; ++j) {
-                        const int i = i0 + j;
-                        if (i < d) g[j] = fma(f, (double)mk[i] - (double)x[j], g[j]);
-                    }
+                    for (int j = 0; j < DPL; ++j)
+                        g[j] = fma(f, mean(pv, k, r, j) - (double)x[j], g[j]);
                 }
             }
             const double inv_s = 1.0 / s;
 #pragma unroll
-            for (int j = 0; j < DPL; ++j) {
-                const int i = i0 + j;
-                if (i < d) g[j] = g[j] * inv_s + ((double)x[j] - (double)pv.m[i]) * c.inv_s2r;
-            }
+            for (int j = 0; j < DPL; ++j)
+                g[j] = g[j] * inv_s + ((double)x[j] - ref(pv, r, j)) * c.inv_s2r;
         }
         return lse + sse * c.half_inv_s2r + c.cst_eta;
     }
@@ -268,7 +294,7 @@ struct Particle {
                     normals4(key, n, t, stream, (uint32_t)b, q);
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
-                        if (4 * b + u < DPL) z[4 * b + u] = q[u];
+                        if (4 * b + u < DPL) z[4 * b + u] = (4 * b + u < d) ? q[u] : 0.0;
                 }
             }
         } else {
@@ -280,7 +306,7 @@ struct Particle {
                     double q[4];
                     normals4(key, n, t, stream, (uint32_t)b, q);
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) z[4 * bb + u] = q[u];
+                    for (int u = 0; u < 4; ++u) z[4 * bb + u] = (4 * b + u < d) ? q[u] : 0.0;
                 }
             }
         }
@@ -296,8 +322,7 @@ struct Particle {
         normals(key, n, 0u, kStreamInit, r, tg.d, z);
 #pragma unroll
         for (int j = 0; j < DPL; ++j) {
-            const int i = r * DPL + j;
-            x[j] = (i < tg.d) ? (float)((double)pv.m[i] + c.sref * z[j]) : 0.f;
+            x[j] = (float)(ref(pv, r, j) + c.sref * z[j]);
             g[j] = 0.0;
         }
         return grad ? eval<true>(tg, c, pv, r, x, g) : eval<false>(tg, c, pv, r, x, g);
@@ -312,10 +337,8 @@ struct Particle {
                                                 float (&x)[DPL], double& ell, double (&g)[DPL],
                                                 int forced = -1)
     {
-        const int d = tg.d;
-        const int i0 = r * DPL;
         double z[DPL];
-        normals(key, n, t, kStreamMove, r, d, z);
+        normals(key, n, t, kStreamMove, r, tg.d, z);
         float xp[DPL];
         double gp[DPL];
         double ellp;
@@ -324,13 +347,10 @@ struct Particle {
             double dle = 0.0;
 #pragma unroll
             for (int j = 0; j < DPL; ++j) {
-                xp[j] = x[j];
-                if (i0 + j < d) {
-                    xp[j] = (float)((double)x[j] + eps * z[j]);
-                    const double a = (double)x[j] - (double)pv.m[i0 + j];
-                    const double b = (double)xp[j] - (double)pv.m[i0 + j];
-                    dle += a * a - b * b;
-                }
+                xp[j] = (float)((double)x[j] + eps * z[j]);
+                const double a = (double)x[j] - ref(pv, r, j);
+                const double b = (double)xp[j] - ref(pv, r, j);
+                dle += a * a - b * b;
             }
             ellp = eval<false>(tg, c, pv, r, xp, gp);
             log_alpha = group_sum<LPP>(dle) * c.half_inv_s2r + beta * (ellp - ell);
@@ -339,28 +359,23 @@ struct Particle {
             double dle = 0.0, fwd = 0.0, bwd = 0.0;
 #pragma unroll
             for (int j = 0; j < DPL; ++j) {
-                xp[j] = x[j];
-                if (i0 + j < d) {
-                    const double xv = (double)x[j];
-                    const double ga = -(xv - (double)pv.m[i0 + j]) * c.inv_s2r + beta * g[j];
-                    xp[j] = (float)(xv + h * ga + eps * z[j]);
-                    const double rr = (double)xp[j] - xv - h * ga;
-                    fwd = fma(rr, rr, fwd);
-                }
+                const double xv = (double)x[j];
+                const double ga = -(xv - ref(pv, r, j)) * c.inv_s2r + beta * g[j];
+                xp[j] = (float)(xv + h * ga + eps * z[j]);
+                const double rr = (double)xp[j] - xv - h * ga;
+                fwd = fma(rr, rr, fwd);
             }
             ellp = eval<true>(tg, c, pv, r, xp, gp);
 #pragma unroll
             for (int j = 0; j < DPL; ++j) {
-                if (i0 + j < d) {
-                    const double xv = (double)x[j];
-                    const double xpv = (double)xp[j];
-                    const double gap = -(xpv - (double)pv.m[i0 + j]) * c.inv_s2r + beta * gp[j];
-                    const double rr = xv - xpv - h * gap;
-                    bwd = fma(rr, rr, bwd);
-                    const double a = xv - (double)pv.m[i0 + j];
-                    const double b = xpv - (double)pv.m[i0 + j];
-                    dle += a * a - b * b;
-                }
+                const double xv = (double)x[j];
+                const double xpv = (double)xp[j];
+                const double gap = -(xpv - ref(pv, r, j)) * c.inv_s2r + beta * gp[j];
+                const double rr = xv - xpv - h * gap;
+                bwd = fma(rr, rr, bwd);
+                const double a = xv - ref(pv, r, j);
+                const double b = xpv - ref(pv, r, j);
+                dle += a * a - b * b;
             }
             const double inv2e2 = 1.0 / (2.0 * eps * eps);
             log_alpha = group_sum<LPP>(dle) * c.half_inv_s2r + beta * (ellp - ell) -
@@ -374,36 +389,29 @@ struct Particle {
                 mom[j] = z[j];
                 xp[j] = x[j];
                 gp[j] = g[j];
-                if (i0 + j < d) kin0 += 0.5 * mom[j] * mom[j];
+                kin0 += 0.5 * mom[j] * mom[j];
             }
             ellp = ell;
             const double he = 0.5 * eps;
             for (int l = 0; l < L; ++l) {
 #pragma unroll
                 for (int j = 0; j < DPL; ++j) {
-                    if (i0 + j < d) {
-                        const double xv = (double)xp[j];
-                        mom[j] += he * (-(xv - (double)pv.m[i0 + j]) * c.inv_s2r + beta * gp[j]);
-                        xp[j] = (float)(xv + eps * mom[j]);
-                    }
+                    const double xv = (double)xp[j];
+                    mom[j] += he * (-(xv - ref(pv, r, j)) * c.inv_s2r + beta * gp[j]);
+                    xp[j] = (float)(xv + eps * mom[j]);
                 }
                 ellp = eval<true>(tg, c, pv, r, xp, gp);
 #pragma unroll
-                for (int j = 0; j < DPL; ++j) {
-                    if (i0 + j < d)
-                        mom[j] += he * (-((double)xp[j] - (double)pv.m[i0 + j]) * c.inv_s2r +
-                                        beta * gp[j]);
-                }
+                for (int j = 0; j < DPL; ++j)
+                    mom[j] += he * (-((double)xp[j] - ref(pv, r, j)) * c.inv_s2r + beta * gp[j]);
             }
             double kin1 = 0.0, dle = 0.0;
 #pragma unroll
             for (int j = 0; j < DPL; ++j) {
-                if (i0 + j < d) {
-                    kin1 += 0.5 * mom[j] * mom[j];
-                    const double a = (double)x[j] - (double)pv.m[i0 + j];
-                    const double b = (double)xp[j] - (double)pv.m[i0 + j];
-                    dle += a * a - b * b;
-                }
+                kin1 += 0.5 * mom[j] * mom[j];
+                const double a = (double)x[j] - ref(pv, r, j);
+                const double b = (double)xp[j] - ref(pv, r, j);
+                dle += a * a - b * b;
             }
             log_alpha = group_sum<LPP>(dle) * c.half_inv_s2r + beta * (ellp - ell) -
                         group_sum<LPP>(kin1) + group_sum<LPP>(kin0);
@@ -568,7 +576,7 @@ __global__ void __launch_bounds__(256) k_oais_valu(SweepArgs a)
     __shared__ double2 sh_rec[kWavesPerBlock][kTC][kWave / LPP];
     __shared__ uint32_t sh_cnt[kWavesPerBlock][kTC];
     extern __shared__ __align__(16) char sh_dyn[];
-    const ParView pv = stage_params(a.tg, sh_dyn);
+    const ParView pv = stage_params_lanes<LPP, DPL>(a.tg, sh_dyn);
     const Consts c = make_consts(a.tg);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
     const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + wv;
@@ -612,7 +620,7 @@ __global__ void __launch_bounds__(256) k_asmc_init(SweepArgs a, AsmcState z)
 {
     constexpr int P = kWave / LPP;
     extern __shared__ __align__(16) char sh_dyn[];
-    const ParView pv = stage_params(a.tg, sh_dyn);
+    const ParView pv = stage_params_lanes<LPP, DPL>(a.tg, sh_dyn);
     const Consts c = make_consts(a.tg);
     const int lane = threadIdx.x & (kWave - 1);
     const int r = lane % LPP, pl = lane / LPP;
@@ -645,7 +653,7 @@ __global__ void __launch_bounds__(256, MinWaves<DPL>::value)
 {
     constexpr int P = kWave / LPP;
     extern __shared__ __align__(16) char sh_dyn[];
-    const ParView pv = stage_params(a.tg, sh_dyn);
+    const ParView pv = stage_params_lanes<LPP, DPL>(a.tg, sh_dyn);
     const Consts c = make_consts(a.tg);
     const int lane = threadIdx.x & (kWave - 1);
     const int r = lane % LPP, pl = lane / LPP;
@@ -727,7 +735,7 @@ struct Launch {
     {
         const int blocks = (grid_waves + kWavesPerBlock - 1) / kWavesPerBlock;
         hipLaunchKernelGGL((k_oais_valu<FAM, MOVE, LPP, DPL>), dim3(blocks), dim3(256),
-                           params_bytes(a.tg), st, a);
+                           params_bytes_lanes(a.tg, LPP, DPL), st, a);
         return hipGetLastError();
     }
     static hipError_t batch(const SweepArgs* args, const ParView* views, const int2* items,
@@ -742,14 +750,14 @@ struct Launch {
     {
         const int64_t blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
         hipLaunchKernelGGL((k_asmc_init<FAM, MOVE, LPP, DPL>), dim3((unsigned)blocks), dim3(256),
-                           params_bytes(a.tg), st, a, z);
+                           params_bytes_lanes(a.tg, LPP, DPL), st, a, z);
         return hipGetLastError();
     }
     static hipError_t step(const SweepArgs& a, const AsmcState& z, int t, hipStream_t st)
     {
         const int64_t blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
         hipLaunchKernelGGL((k_asmc_step<FAM, MOVE, LPP, DPL>), dim3((unsigned)blocks), dim3(256),
-                           params_bytes(a.tg), st, a, z, t);
+                           params_bytes_lanes(a.tg, LPP, DPL), st, a, z, t);
         return hipGetLastError();
     }
 };
