@@ -45,8 +45,16 @@ struct ParView {
     const double* lmu;  // [K or 1][DPL][LPP]
 };
 
-// Means held by the lane layout: the Gaussian mean, or the K mixture means.
-__host__ __device__ inline int lane_means(const TargetDev& tg) { return tg.family == kGmm ? tg.K : 1; }
+// Mixture components handled together by the particle code (the lane layout
+// and the per-component constants are zero-padded to whole blocks).
+constexpr int kKBlock = 4;
+static_assert(kMaxK % kKBlock == 0, "whole blocks of components");
+// Means held by the lane layout: the Gaussian mean, or the mixture means
+// padded to whole blocks of kKBlock components.
+__host__ __device__ inline int lane_means(const TargetDev& tg)
+{
+    return tg.family == kGmm ? (tg.K + kKBlock - 1) / kKBlock * kKBlock : 1;
+}
 // Doubles of the lane-layout arrays lm and lmu for one sweep shape.
 __host__ __device__ inline size_t lane_param_doubles(const TargetDev& tg, int lpp, int dpl)
 {
@@ -86,6 +94,7 @@ __device__ __forceinline__ double lane_param(const TargetDev& tg, int lpp, int d
     const int i = r * dpl + j;
     if (i >= tg.d) return 0.0;
     if (k == 0) return tg.ref_mean ? (double)tg.ref_mean[i] : 0.0;
+    if (tg.family == kGmm && k > tg.K) return 0.0;  // padding of the last block
     const float* src = (tg.family == kGmm) ? tg.means : tg.mu;
     return (double)src[(size_t)(k - 1) * tg.d + i];
 }

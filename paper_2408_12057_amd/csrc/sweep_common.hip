@@ -443,12 +443,13 @@ __global__ void k_batch_params(const TargetDev* __restrict__ tgs, const BatchPar
     if (tg.family == kLogreg || bp.m == nullptr) return;
     for (int i = threadIdx.x; i < tg.d; i += blockDim.x)
         bp.m[i] = tg.ref_mean ? tg.ref_mean[i] : 0.f;
-    if (tg.family == kGmm)
-        for (int k = threadIdx.x; k < tg.K; k += blockDim.x) {
-            const double v = exp(2.0 * (double)tg.log_scales[k]);
-            bp.hiv[k] = 0.5 / v;
-            bp.iv[k] = 1.0 / v;
-        }
+    // 1/(2 v_k), 1/v_k; zero beyond K (padded components of a block)
+    for (int k = threadIdx.x; k < kMaxK; k += blockDim.x) {
+        const bool on = tg.family == kGmm && k < tg.K;
+        const double v = on ? exp(2.0 * (double)tg.log_scales[k]) : 1.0;
+        bp.hiv[k] = on ? 0.5 / v : 0.0;
+        bp.iv[k] = on ? 1.0 / v : 0.0;
+    }
     const int nl = (int)lane_param_doubles(tg, bp.lpp, bp.dpl);
     for (int e = threadIdx.x; e < nl; e += blockDim.x) bp.lane[e] = lane_param(tg, bp.lpp, bp.dpl, e);
 }

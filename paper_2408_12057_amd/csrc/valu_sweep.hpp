@@ -69,12 +69,13 @@ __device__ __forceinline__ ParView stage_params(const TargetDev& tg, char* sh)
     for (int i = threadIdx.x; i < d; i += blockDim.x) m[i] = tg.ref_mean ? tg.ref_mean[i] : 0.f;
     const float* src = (tg.family == kGmm) ? tg.means : tg.mu;
     for (int i = threadIdx.x; i < nmu; i += blockDim.x) mu[i] = src[i];
-    if (tg.family == kGmm)
-        for (int k = threadIdx.x; k < tg.K; k += blockDim.x) {
-            const double v = exp(2.0 * (double)tg.log_scales[k]);
-            hv[k] = 0.5 / v;
-            iv[k] = 1.0 / v;
-        }
+    // 1/(2 v_k), 1/v_k; zero beyond K (padded components of a block)
+    for (int k = threadIdx.x; k < kMaxK; k += blockDim.x) {
+        const bool on = tg.family == kGmm && k < tg.K;
+        const double v = on ? exp(2.0 * (double)tg.log_scales[k]) : 1.0;
+        hv[k] = on ? 0.5 / v : 0.0;
+        iv[k] = on ? 1.0 / v : 0.0;
+    }
     __syncthreads();
     return ParView{m, mu, hv, iv};
 }
@@ -237,19 +238,32 @@ struct Particle {
         double eo[KO];
 #pragma unroll
         for (int q = 0; q < KO; ++q) eo[q] = -INFINITY;
+        // exponents in blocks of kKBlock components without a branch inside a
+        // block, so the independent distance chains and reductions of a block
+        // interleave; the lane layout and 1/(2 v_k) are zero-padded to whole
+        // blocks and a padded component gets e_k = -inf (weight 0)
         double M = -INFINITY;
 #pragma unroll
-        for (int k = 0; k < kMaxK; ++k) {
-            if (k < K) {
-                double sq = 0.0;
+        for (int k0 = 0; k0 < kMaxK; k0 += kKBlock) {
+            if (k0 < K) {
+                double sq[kKBlock];
 #pragma unroll
-                for (int j = 0; j < DPL; ++j) {
-                    const double a = (double)x[j] - mean(pv, k, r, j);
-                    sq = fma(a, a, sq);
+                for (int u = 0; u < kKBlock; ++u) {
+                    sq[u] = 0.0;
+#pragma unroll
+                    for (int j = 0; j < DPL; ++j) {
+                        const double a = (double)x[j] - mean(pv, k0 + u, r, j);
+                        sq[u] = fma(a, a, sq[u]);
+                    }
                 }
-                const double ek = -group_sum<LPP>(sq) * pv.hiv[k];
-                M = fmax(M, ek);
-                if ((k % LPP) == r) eo[k / LPP] = ek;
+#pragma unroll
+                for (int u = 0; u < kKBlock; ++u) {
+                    const int k = k0 + u;
+                    double ek = -group_sum<LPP>(sq[u]) * pv.hiv[k];
+                    if (k >= K) ek = -INFINITY;
+                    M = fmax(M, ek);
+                    if ((k % LPP) == r) eo[k / LPP] = ek;
+                }
             }
         }
         double wo[KO];
