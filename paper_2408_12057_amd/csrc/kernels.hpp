@@ -117,6 +117,9 @@ struct AsmcState {
     // scalars updated on the device
     double* scal;      // [0] log Z_hat, [1] max(lw) at event, [2] flag, [3] u word
     int* nres;         // [1]
+    unsigned* ticket;  // [2] arrival counters of the per-step merge and of the
+                       // resampler's scan; zero between launches (the last
+                       // arriving block resets its counter)
     double* log_g;     // [3*T] device
     double* ess;       // [T]
     int* resampled;    // [T]

@@ -854,6 +854,7 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
         HIP_TRY(wget(h, B_RES, T, &z.resampled));
         HIP_TRY(wget(h, B_C, N, &z.C));
         HIP_TRY(wget(h, B_BTOT, resample_blocks(N), &z.btot));
+        z.ticket = reinterpret_cast<unsigned*>(z.nres + 1);  // cleared with nres below
         z.scal = dscal;
         z.log_g = dlogg;
         z.accept = dacc;

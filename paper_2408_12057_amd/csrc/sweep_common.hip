@@ -57,9 +57,9 @@ __global__ void __launch_bounds__(kWave) k_merge_slots(const double* __restrict_
 // The per-step merge of the resampling variant, in two levels with a fixed
 // order (deterministic, independent of timing): block b of the first level
 // reduces a contiguous range of tile records to one record (log-sum-exps as a
-// maximum and then a sum of exp(x - max)); one wave then merges the block
-// records, records the moments, ESS and CESS, decides the event and adds the
-// log Z_hat increment.
+// maximum and then a sum of exp(x - max)); one wave of the last block to
+// finish then merges the block records, records the moments, ESS and CESS,
+// decides the event and adds the log Z_hat increment (one launch).
 constexpr int kMergeThreads = 256;
 
 __device__ __forceinline__ int merge_blocks(int64_t ntiles)
@@ -68,7 +68,45 @@ __device__ __forceinline__ int merge_blocks(int64_t ntiles)
     return (int)(nb < kAsmcMergeBlocks ? nb : kAsmcMergeBlocks);
 }
 
-__global__ void __launch_bounds__(kMergeThreads) k_asmc_merge_part(SweepArgs a, AsmcState z)
+// Second level, by one wave: the block records, the moments, ESS and CESS,
+// the event decision and the log Z_hat increment.
+__device__ __forceinline__ void asmc_merge_final(const SweepArgs& a, const AsmcState& z, int t,
+                                                 int trigger, double nu, int lane)
+{
+    const int nb = merge_blocks(a.ntiles);
+    const double* rec = z.blk_part + (size_t)lane * 8;
+    const bool have = lane < nb;
+    double L[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) L[i] = wave_lse(have ? rec[i] : -INFINITY);
+    const double mx = wave_max(have ? rec[4] : -INFINITY);
+    const double total = wave_sum(have ? rec[5] : 0.0);
+    if (lane != 0) return;
+    const int T = a.T;
+    const double logN = log((double)a.N);
+    for (int i = 0; i < 3; ++i) z.log_g[(size_t)i * T + (t - 1)] = L[i];
+    z.accept[t - 1] = total;
+    const double rel_ess = exp(2.0 * L[1] - L[3] - logN);
+    const double rel_cess = exp(-(L[2] - 2.0 * L[1] + L[0]));
+    z.ess[t - 1] = rel_ess;
+    const bool fire = (trigger == 0) ? (rel_ess < nu) : (rel_cess < nu);
+    z.resampled[t - 1] = 0;
+    z.scal[2] = 0.0;
+    if (t == T) {
+        z.scal[0] += L[1] - logN;
+    } else if (fire) {
+        z.scal[0] += L[1] - logN;
+        z.scal[1] = mx;
+        z.scal[2] = 1.0;
+        const uint4 wd = draw_block(a.key, 0xFFFFFFFFu, (uint32_t)t, kStreamResample, 0u, 0u);
+        z.scal[3] = (double)wd.x;
+        z.resampled[t - 1] = 1;
+        z.nres[0] += 1;
+    }
+}
+
+__global__ void __launch_bounds__(kMergeThreads) k_asmc_merge(SweepArgs a, AsmcState z, int t,
+                                                                int trigger, double nu)
 {
     constexpr int W = kMergeThreads / kWave;
     __shared__ double shm[W][6];
@@ -136,42 +174,18 @@ __global__ void __launch_bounds__(kMergeThreads) k_asmc_merge_part(SweepArgs a, 
         out[4] = res[4];
         out[5] = res[5];
     }
-}
-
-__global__ void __launch_bounds__(kWave) k_asmc_merge(SweepArgs a, AsmcState z, int t,
-                                                      int trigger, double nu)
-{
-    const int lane = threadIdx.x;
-    const int nb = merge_blocks(a.ntiles);
-    const double* rec = z.blk_part + (size_t)lane * 8;
-    const bool have = lane < nb;
-    double L[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) L[i] = wave_lse(have ? rec[i] : -INFINITY);
-    const double mx = wave_max(have ? rec[4] : -INFINITY);
-    const double total = wave_sum(have ? rec[5] : 0.0);
-    if (lane != 0) return;
-    const int T = a.T;
-    const double logN = log((double)a.N);
-    for (int i = 0; i < 3; ++i) z.log_g[(size_t)i * T + (t - 1)] = L[i];
-    z.accept[t - 1] = total;
-    const double rel_ess = exp(2.0 * L[1] - L[3] - logN);
-    const double rel_cess = exp(-(L[2] - 2.0 * L[1] + L[0]));
-    z.ess[t - 1] = rel_ess;
-    const bool fire = (trigger == 0) ? (rel_ess < nu) : (rel_cess < nu);
-    z.resampled[t - 1] = 0;
-    z.scal[2] = 0.0;
-    if (t == T) {
-        z.scal[0] += L[1] - logN;
-    } else if (fire) {
-        z.scal[0] += L[1] - logN;
-        z.scal[1] = mx;
-        z.scal[2] = 1.0;
-        const uint4 wd = draw_block(a.key, 0xFFFFFFFFu, (uint32_t)t, kStreamResample, 0u, 0u);
-        z.scal[3] = (double)wd.x;
-        z.resampled[t - 1] = 1;
-        z.nres[0] += 1;
+    // the last block to finish merges the block records; the arrival counter
+    // only elects that block (no block waits for another)
+    __shared__ bool last;
+    if (tid == 0) {
+        __threadfence();  // this block's record before its arrival
+        last = atomicAdd(z.ticket, 1u) == (unsigned)(nb - 1);
     }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();  // the other blocks' records
+    if (w == 0) asmc_merge_final(a, z, t, trigger, nu, lane);
+    if (tid == 0) z.ticket[0] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -190,10 +204,40 @@ __device__ __forceinline__ int quant_bits(int64_t N)
     return 62 - lg;
 }
 
+// Inclusive scan of the block totals (one block, sequential chunks).
+__device__ __forceinline__ void scan_block_totals(int64_t nb, uint64_t* btot)
+{
+    __shared__ uint64_t sh[kScanThreads];
+    uint64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+        const int64_t b = b0 + threadIdx.x;
+        sh[threadIdx.x] = (b < nb) ? btot[b] : 0;
+        __syncthreads();
+        for (int o = 1; o < kScanThreads; o <<= 1) {
+            const uint64_t v = (threadIdx.x >= (unsigned)o) ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (b < nb) btot[b] = sh[threadIdx.x] + carry;
+        __syncthreads();
+        carry += sh[kScanThreads - 1];
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_rs_scan_blocks(int64_t nb, const double* scal,
+                                                                 uint64_t* btot)
+{
+    if (scal[2] == 0.0) return;
+    scan_block_totals(nb, btot);
+}
+
 // q_m and the block-local inclusive prefix; block totals into btot.
+// With a ticket, the last block to finish also scans the block totals.
 __global__ void __launch_bounds__(kScanThreads) k_rs_quant_scan(int64_t N, const double* lw,
                                                                 const double* scal, uint64_t* C,
-                                                                uint64_t* btot)
+                                                                uint64_t* btot, unsigned* ticket)
 {
     if (scal[2] == 0.0) return;
     __shared__ uint64_t sh[kScanThreads];
@@ -228,31 +272,21 @@ __global__ void __launch_bounds__(kScanThreads) k_rs_quant_scan(int64_t N, const
         const int64_t m = base + k;
         if (m < N) C[m] = before + q[k];
     }
-    if (threadIdx.x == kScanThreads - 1) btot[blockIdx.x] = sh[threadIdx.x];
-}
-
-// Inclusive scan of the block totals (one block, sequential chunks).
-__global__ void __launch_bounds__(kScanThreads) k_rs_scan_blocks(int64_t nb, const double* scal,
-                                                                 uint64_t* btot)
-{
-    if (scal[2] == 0.0) return;
-    __shared__ uint64_t sh[kScanThreads];
-    uint64_t carry = 0;
-    for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
-        const int64_t b = b0 + threadIdx.x;
-        sh[threadIdx.x] = (b < nb) ? btot[b] : 0;
-        __syncthreads();
-        for (int o = 1; o < kScanThreads; o <<= 1) {
-            const uint64_t v = (threadIdx.x >= (unsigned)o) ? sh[threadIdx.x - o] : 0;
-            __syncthreads();
-            sh[threadIdx.x] += v;
-            __syncthreads();
-        }
-        if (b < nb) btot[b] = sh[threadIdx.x] + carry;
-        __syncthreads();
-        carry += sh[kScanThreads - 1];
-        __syncthreads();
+    if (ticket == nullptr) {
+        if (threadIdx.x == kScanThreads - 1) btot[blockIdx.x] = sh[threadIdx.x];
+        return;
     }
+    __shared__ bool last;
+    if (threadIdx.x == kScanThreads - 1) {
+        btot[blockIdx.x] = sh[threadIdx.x];
+        __threadfence();  // this block's total before its arrival
+        last = atomicAdd(ticket, 1u) == (unsigned)(gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();  // the other blocks' totals
+    scan_block_totals((int64_t)gridDim.x, btot);
+    if (threadIdx.x == 0) ticket[0] = 0u;
 }
 
 // floor(num_hi:num_lo / den) for a quotient below 2^64 (restoring division).
@@ -301,15 +335,16 @@ __device__ __forceinline__ int64_t find_ancestor(int64_t n, int64_t N, uint32_t 
 __global__ void k_rs_gather(int64_t N, int d, AsmcState z, int64_t nb)
 {
     if (z.scal[2] == 0.0) return;
-    const int64_t n = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
-    if (n >= N) return;
     const uint32_t u = (uint32_t)z.scal[3];
-    const int64_t an = find_ancestor(n, N, u, z.C, z.btot, nb);
-    for (int i = threadIdx.x; i < d; i += blockDim.x) {
-        z.X2[(size_t)n * d + i] = z.X[(size_t)an * d + i];
-        if (z.G) z.G2[(size_t)n * d + i] = z.G[(size_t)an * d + i];
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.y + threadIdx.y; n < N;
+         n += (int64_t)gridDim.x * blockDim.y) {
+        const int64_t an = find_ancestor(n, N, u, z.C, z.btot, nb);
+        for (int i = threadIdx.x; i < d; i += blockDim.x) {
+            z.X2[(size_t)n * d + i] = z.X[(size_t)an * d + i];
+            if (z.G) z.G2[(size_t)n * d + i] = z.G[(size_t)an * d + i];
+        }
+        if (threadIdx.x == 0) z.ell2[n] = z.ell[an];
     }
-    if (threadIdx.x == 0) z.ell2[n] = z.ell[an];
 }
 
 __global__ void k_rs_commit(int64_t N, int d, AsmcState z)
@@ -479,28 +514,30 @@ hipError_t launch_asmc_step(const SweepArgs& a, const ValuShape& s, const AsmcSt
     if (e != hipSuccess) return e;
     const int64_t nb = std::min<int64_t>((a.ntiles + kMergeThreads - 1) / kMergeThreads,
                                          kAsmcMergeBlocks);
-    hipLaunchKernelGGL(k_asmc_merge_part, dim3((unsigned)nb), dim3(kMergeThreads), 0, st, a, z);
-    hipLaunchKernelGGL(k_asmc_merge, dim3(1), dim3(kWave), 0, st, a, z, t, trigger, nu);
+    hipLaunchKernelGGL(k_asmc_merge, dim3((unsigned)nb), dim3(kMergeThreads), 0, st, a, z, t,
+                       trigger, nu);
     return hipGetLastError();
 }
+
+// Grid cap of the gather and commit kernels of the resampling variant.
+constexpr int64_t kIdleGrid = 2048;
 
 hipError_t launch_resample_step(const SweepArgs& a, const AsmcState& z, int t, hipStream_t st)
 {
     (void)t;
     const int64_t N = a.N;
     const int64_t nb = resample_blocks(N);
+    // launched every step and idle unless the trigger fired: grids are capped
+    // (grid-stride loops) so that an idle launch stays cheap
     hipLaunchKernelGGL(k_rs_quant_scan, dim3((unsigned)nb), dim3(kScanThreads), 0, st, N,
-                       (const double*)z.lw, (const double*)z.scal, z.C, z.btot);
-    hipLaunchKernelGGL(k_rs_scan_blocks, dim3(1), dim3(kScanThreads), 0, st, nb,
-                       (const double*)z.scal, z.btot);
+                       (const double*)z.lw, (const double*)z.scal, z.C, z.btot, z.ticket + 1);
     const int d = a.tg.d;
     const int tx = d >= 32 ? 32 : (d >= 16 ? 16 : (d >= 8 ? 8 : 4));
     const int ty = 256 / tx;
-    hipLaunchKernelGGL(k_rs_gather, dim3((unsigned)((N + ty - 1) / ty)), dim3(tx, ty), 0, st, N,
-                       d, z, nb);
+    const int64_t gblocks = std::min<int64_t>((N + ty - 1) / ty, kIdleGrid);
+    hipLaunchKernelGGL(k_rs_gather, dim3((unsigned)gblocks), dim3(tx, ty), 0, st, N, d, z, nb);
     const int64_t total = N * (int64_t)d;
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, kIdleGrid);
     hipLaunchKernelGGL(k_rs_commit, dim3((unsigned)blocks), dim3(256), 0, st, N, d, z);
     return hipGetLastError();
 }
@@ -519,7 +556,7 @@ hipError_t launch_resample_plain(int64_t N, const double* lw, uint32_t u, int32_
     const int64_t nb = resample_blocks(N);
     hipLaunchKernelGGL(k_rs_prepare, dim3(1), dim3(256), 0, st, N, lw, u, scal);
     hipLaunchKernelGGL(k_rs_quant_scan, dim3((unsigned)nb), dim3(kScanThreads), 0, st, N, lw,
-                       (const double*)scal, C, btot);
+                       (const double*)scal, C, btot, (unsigned*)nullptr);
     hipLaunchKernelGGL(k_rs_scan_blocks, dim3(1), dim3(kScanThreads), 0, st, nb,
                        (const double*)scal, btot);
     hipLaunchKernelGGL(k_rs_ancestors, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N,
