@@ -24,10 +24,20 @@
 
 namespace oasmc {
 
+// Waves per SIMD requested from the compiler: two for lanes of at most 8
+// coordinates and blocks of at most 4 components (a few registers spill, the
+// second wave hides the binary64 latencies), its own choice for wider shapes
+// (which would spill heavily).
+template <int DPL, int KB>
+struct AdjMinWaves {
+    static constexpr int value = (DPL <= 8 && KB <= 4) ? 2 : 1;
+};
+
 template <int LPP, int DPL, int KB>
-__global__ void __launch_bounds__(256) k_adjoint_gmm(AdjointArgs A)
+__global__ void __launch_bounds__(256, (AdjMinWaves<DPL, KB>::value)) k_adjoint_gmm(AdjointArgs A)
 {
     constexpr int P = kWave / LPP;
+    using PT = Particle<kGmm, LPP, DPL>;
     const SweepArgs& a = A.a;
     extern __shared__ __align__(16) char sh_dyn[];
     const ParView pv = stage_params_lanes<LPP, DPL>(a.tg, sh_dyn);
@@ -88,6 +98,9 @@ __global__ void __launch_bounds__(256) k_adjoint_gmm(AdjointArgs A)
             const double db = a.beta[t] - a.beta[t - 1];
             const double bt = a.beta[t];
             const double h = 0.5 * a.eps[t - 1] * a.eps[t - 1];
+            // the means in the zero-padded lane layout (re-read each step): the
+            // coordinates of a lane beyond d stay exact zeros, no branch needed
+            const ParView pq = PT::fresh(pv);
             double xv[DPL];
 #pragma unroll
             for (int j = 0; j < DPL; ++j) xv[j] = (i0 + j < d) ? (double)segp[u * d + i0 + j] : 0.0;
@@ -100,11 +113,10 @@ __global__ void __launch_bounds__(256) k_adjoint_gmm(AdjointArgs A)
                 if (k < K) {
                     double sq = 0.0;
 #pragma unroll
-                    for (int j = 0; j < DPL; ++j)
-                        if (i0 + j < d) {
-                            const double df = xv[j] - (double)pv.mu[k * d + i0 + j];
-                            sq = fma(df, df, sq);
-                        }
+                    for (int j = 0; j < DPL; ++j) {
+                        const double df = xv[j] - PT::mean(pq, k, r, j);
+                        sq = fma(df, df, sq);
+                    }
                     sq = group_sum<LPP>(sq);
                     qk[k] = sq * pv.iv[k];
                     e[k] = -sq * pv.hiv[k];
@@ -125,8 +137,7 @@ __global__ void __launch_bounds__(256) k_adjoint_gmm(AdjointArgs A)
                 gv[j] = 0.0;
 #pragma unroll
                 for (int k = 0; k < KB; ++k)
-                    if (k < K && i0 + j < d)
-                        gv[j] += rk[k] * ((double)pv.mu[k * d + i0 + j] - xv[j]) * pv.iv[k];
+                    if (k < K) gv[j] += rk[k] * (PT::mean(pq, k, r, j) - xv[j]) * pv.iv[k];
             }
             // weight term: d ell / d theta
 #pragma unroll
@@ -134,8 +145,7 @@ __global__ void __launch_bounds__(256) k_adjoint_gmm(AdjointArgs A)
                 if (k < K) {
 #pragma unroll
                     for (int j = 0; j < DPL; ++j)
-                        if (i0 + j < d)
-                            tm[k][j] -= db * rk[k] * ((double)pv.mu[k * d + i0 + j] - xv[j]) * pv.iv[k];
+                        tm[k][j] -= db * rk[k] * (PT::mean(pq, k, r, j) - xv[j]) * pv.iv[k];
                     ts[k] += db * rk[k] * qk[k];
                 }
             }
@@ -152,8 +162,7 @@ __global__ void __launch_bounds__(256) k_adjoint_gmm(AdjointArgs A)
                         double sdot = 0.0;
 #pragma unroll
                         for (int j = 0; j < DPL; ++j)
-                            if (i0 + j < d)
-                                sdot += ((double)pv.mu[k * d + i0 + j] - xv[j]) * pv.iv[k] * xb[j];
+                            sdot += (PT::mean(pq, k, r, j) - xv[j]) * pv.iv[k] * xb[j];
                         ua[k] = group_sum<LPP>(sdot);
                     }
                 }
@@ -164,8 +173,8 @@ __global__ void __launch_bounds__(256) k_adjoint_gmm(AdjointArgs A)
                     double Hu = -gv[j] * ug + xb[j] * c.inv_s2r;
 #pragma unroll
                     for (int k = 0; k < KB; ++k)
-                        if (k < K && i0 + j < d) {
-                            const double akj = ((double)pv.mu[k * d + i0 + j] - xv[j]) * pv.iv[k];
+                        if (k < K) {
+                            const double akj = (PT::mean(pq, k, r, j) - xv[j]) * pv.iv[k];
                             Hu += rk[k] * (akj * ua[k] - xb[j] * pv.iv[k]);
                             tm[k][j] += hb * rk[k] * (xb[j] * pv.iv[k] - (ua[k] - ug) * akj);
                         }
@@ -175,11 +184,11 @@ __global__ void __launch_bounds__(256) k_adjoint_gmm(AdjointArgs A)
                 for (int k = 0; k < KB; ++k)
                     if (k < K) ts[k] += hb * (rk[k] * qk[k] * (ua[k] - ug) - 2.0 * rk[k] * ua[k]);
 #pragma unroll
-                for (int j = 0; j < DPL; ++j) xb[j] = (i0 + j < d) ? nx[j] : 0.0;
+                for (int j = 0; j < DPL; ++j) xb[j] = nx[j];
             }
 #pragma unroll
             for (int j = 0; j < DPL; ++j)
-                if (i0 + j < d) xb[j] += db * (gv[j] + (xv[j] - (double)pv.m[i0 + j]) * c.inv_s2r);
+                xb[j] += db * (gv[j] + (xv[j] - PT::ref(pq, r, j)) * c.inv_s2r);
         }
     }
     // weighted sums over the tile's particles (butterfly over particle slots)
