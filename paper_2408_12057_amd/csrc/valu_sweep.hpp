@@ -451,14 +451,15 @@ constexpr int kTC = 8;      // steps buffered before a transposed reduction
 constexpr int kWavesPerBlock = 4;
 
 // Minimum waves per SIMD requested from the compiler for the resampling
-// variant's step kernel: three for particles with at most 8 coordinates per
-// lane (the register budget then costs a few spills and buys a third wave:
-// 15% faster for the mixture/HMC step), the compiler's choice otherwise (wider
-// lanes would spill heavily).  The AIS sweeps, which keep more state across
-// their time loop, measured slower with the same request.
+// variant's step kernel: four for particles with at most 8 coordinates per
+// lane (the 128-register budget costs some spills and buys latency hiding:
+// for the mixture/HMC step 5% faster than three waves and 30% faster than
+// two), the compiler's choice otherwise (wider lanes would spill heavily).
+// The AIS sweeps, which keep more state across their time loop, measured
+// slower with such a request.
 template <int DPL>
 struct MinWaves {
-    static constexpr int value = DPL <= 8 ? 3 : 1;
+    static constexpr int value = DPL <= 8 ? 4 : 1;
 };
 
 // All tiles of one slot of one problem, in tile order (one wave).  The
