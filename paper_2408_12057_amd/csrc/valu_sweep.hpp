@@ -294,35 +294,34 @@ struct Particle {
         return lse + sse * c.half_inv_s2r + c.cst_eta;
     }
 
+    // Normals of this lane's coordinates 4 bb .. 4 bb + 3 (zero beyond d) of
+    // one (particle, step, stream) sequence: block r DPL / 4 + bb of it.
+    static __device__ __forceinline__ void normals_block(const RngKey& key, uint32_t n,
+                                                         uint32_t t, uint32_t stream, int r,
+                                                         int d, int bb, double (&q)[4])
+    {
+        static_assert(DPL % 4 == 0, "lane slices are whole blocks of 4 coordinates");
+        const int b = r * (DPL / 4) + bb;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = 0.0;
+        if (4 * b < d) {
+            double w[4];
+            normals4(key, n, t, stream, (uint32_t)b, w);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = (4 * b + u < d) ? w[u] : 0.0;
+        }
+    }
+
     // d normals of one (particle, step, stream) split over the group's lanes.
     static __device__ __forceinline__ void normals(const RngKey& key, uint32_t n, uint32_t t,
                                                    uint32_t stream, int r, int d, double (&z)[DPL])
     {
 #pragma unroll
-        for (int j = 0; j < DPL; ++j) z[j] = 0.0;
-        if constexpr (LPP == 1) {
+        for (int bb = 0; bb < DPL / 4; ++bb) {
+            double q[4];
+            normals_block(key, n, t, stream, r, d, bb, q);
 #pragma unroll
-            for (int b = 0; b < (DPL + 3) / 4; ++b) {
-                if (4 * b < d) {
-                    double q[4];
-                    normals4(key, n, t, stream, (uint32_t)b, q);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (4 * b + u < DPL) z[4 * b + u] = (4 * b + u < d) ? q[u] : 0.0;
-                }
-            }
-        } else {
-            static_assert(DPL % 4 == 0, "multi-lane particles need 4-aligned lane slices");
-#pragma unroll
-            for (int bb = 0; bb < DPL / 4; ++bb) {
-                const int b = r * (DPL / 4) + bb;
-                if (4 * b < d) {
-                    double q[4];
-                    normals4(key, n, t, stream, (uint32_t)b, q);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) z[4 * bb + u] = (4 * b + u < d) ? q[u] : 0.0;
-                }
-            }
+            for (int u = 0; u < 4; ++u) z[4 * bb + u] = q[u];
         }
     }
 
@@ -351,8 +350,10 @@ struct Particle {
                                                 float (&x)[DPL], double& ell, double (&g)[DPL],
                                                 int forced = -1)
     {
+        // RWMH draws its normals block by block inside the proposal loop
+        // (shorter live ranges); MALA and HMC draw them all first
         double z[DPL];
-        normals(key, n, t, kStreamMove, r, tg.d, z);
+        if constexpr (MOVE != kRwmh) normals(key, n, t, kStreamMove, r, tg.d, z);
         float xp[DPL];
         double gp[DPL];
         double ellp;
@@ -360,11 +361,17 @@ struct Particle {
         if constexpr (MOVE == kRwmh) {
             double dle = 0.0;
 #pragma unroll
-            for (int j = 0; j < DPL; ++j) {
-                xp[j] = (float)((double)x[j] + eps * z[j]);
-                const double a = (double)x[j] - ref(pv, r, j);
-                const double b = (double)xp[j] - ref(pv, r, j);
-                dle += a * a - b * b;
+            for (int bb = 0; bb < DPL / 4; ++bb) {
+                double q[4];
+                normals_block(key, n, t, kStreamMove, r, tg.d, bb, q);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int j = 4 * bb + u;
+                    xp[j] = (float)((double)x[j] + eps * q[u]);
+                    const double a = (double)x[j] - ref(pv, r, j);
+                    const double b = (double)xp[j] - ref(pv, r, j);
+                    dle += a * a - b * b;
+                }
             }
             ellp = eval<false>(tg, c, pv, r, xp, gp);
             log_alpha = group_sum<LPP>(dle) * c.half_inv_s2r + beta * (ellp - ell);
