@@ -14,9 +14,10 @@
 //    steps; the moments g_hat_{t,i} (eq. CESS) are streamed into a fixed number
 //    of slots S of O(T) memory each, independent of N and of the grid shape.
 //  * k_asmc_step / k_asmc_merge / resampler -- the adaptive-resampling case
-//    (Alg. 1 with AR): one launch per step t, state in HBM, a one-block merge
-//    that evaluates the trigger on the device, and the integer-CDF systematic
-//    resampler (launched every step, does nothing unless the trigger fired).
+//    (Alg. 1 with AR): one launch per step t, state in HBM, a two-level merge
+//    in one launch that evaluates the trigger on the device, and the
+//    integer-CDF systematic resampler (launched every step, does nothing
+//    unless the trigger fired).
 #pragma once
 #include "kernels.hpp"
 
