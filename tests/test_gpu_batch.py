@@ -46,6 +46,10 @@ def _mixed_specs():
                       params=wl.random_gmm(rng, 20, 4), eps0=0.4, eps_adapt=True, eps_kappa=2.0))
     specs.append(dict(family="gmm", d=6, N=70, T=9, move="hmc",
                       params=wl.random_gmm(rng, 6, 3), eps0=0.3, eps_adapt=True, eps_kappa=1.0))
+    # 4 lanes x 16 coordinates, K = 6: per-problem lane-layout means with a
+    # padded block of components, read from global memory
+    specs.append(dict(family="gmm", d=40, N=130, T=8, move="mala",
+                      params=wl.random_gmm(rng, 40, 6), eps0=0.3, eps_adapt=True, eps_kappa=2.0))
     for d, n, N, T in [(7, 300, 64, 8), (50, 1000, 200, 16), (33, 777, 65, 4)]:
         X, y, _ = wl.logreg_data(n, d, n + d)
         specs.append(dict(family="logreg", d=d, N=N, T=T, move="mala", params=dict(X=X, y=y),

@@ -85,6 +85,9 @@ def test_ais_round_matches_oracle(oa, family, d, move, N, T, K):
 @pytest.mark.parametrize("trigger", ["ess", "cess"])
 @pytest.mark.parametrize("family,d,move,N,T,K", [("gauss", 4, "hmc", 300, 12, 0),
                                                  ("gmm", 20, "mala", 2100, 10, 4),
+                                                 # 16 lanes x 8 coordinates, K = 5: a
+                                                 # padded block of mixture components
+                                                 ("gmm", 100, "hmc", 300, 8, 5),
                                                  # > 64 x 256 tiles: several tile records
                                                  # per thread in the first merge level
                                                  ("gauss", 4, "rwmh", 2200000, 3, 0)])
