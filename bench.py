@@ -37,7 +37,7 @@ ALU_WORK = {"gauss": 700.0, "gauss_sat": 700.0, "asmc": 1.0e4, "asmc_ess": 1.0e4
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by the copy-kernel calibration); absent until measured
 # for the current kernel.
-TRAFFIC = {"logreg": 4.391e9}
+TRAFFIC = {"logreg": 3.968e9}
 METRIC = "particle-steps/sec and fraction of roofline at matched log Z error"
 
 

