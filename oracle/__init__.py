@@ -100,7 +100,7 @@ def _declare(L):
     L.orc_asmc.argtypes = [C.POINTER(_Problem), C.POINTER(_Opts), C.c_int64, C.c_int, _dp, _dp,
                            C.c_uint64, C.c_uint32, C.c_uint32, _dp, _dp, _dp, _dp, _dp,
                            C.POINTER(C.c_int), C.POINTER(C.c_ubyte), _dp, C.POINTER(C.c_int),
-                           _dp, C.POINTER(C.c_int64), C.c_int64]
+                           _dp, C.POINTER(C.c_int64), C.c_int64, _dp]
     L.orc_asmc.restype = C.c_int
     L.orc_run.argtypes = [C.POINTER(_Problem), C.POINTER(_Opts), C.POINTER(_RunOpts), C.c_int64,
                           C.c_int, C.c_uint64, C.c_uint32, C.c_int, _dp,
@@ -276,6 +276,7 @@ def asmc(problem: Problem, opts: Opts, N: int, beta, eps, seed: int, round_k: in
     nres = C.c_int(0)
     acc_tr = np.zeros(M * T, dtype=np.uint8) if traces else None
     mar_tr = np.zeros(M * T) if traces else None
+    lw_tr = np.zeros(M * T) if traces else None
     sub = None if subset is None else np.ascontiguousarray(np.asarray(subset, dtype=np.int64))
     P = problem.c()
     O = opts.c()
@@ -285,7 +286,7 @@ def asmc(problem: Problem, opts: Opts, N: int, beta, eps, seed: int, round_k: in
         C.byref(nres), None if acc_tr is None else acc_tr.ctypes.data_as(C.POINTER(C.c_ubyte)),
         _ptr(mar_tr), out["resampled"].ctypes.data_as(C.POINTER(C.c_int)), _ptr(out["ess"]),
         None if sub is None else sub.ctypes.data_as(C.POINTER(C.c_int64)),
-        0 if sub is None else sub.shape[0])
+        0 if sub is None else sub.shape[0], _ptr(lw_tr))
     out["status"] = st
     out["logZ"] = logZ.value
     out["n_resample"] = nres.value
@@ -294,6 +295,7 @@ def asmc(problem: Problem, opts: Opts, N: int, beta, eps, seed: int, round_k: in
     if traces:
         out["accept"] = acc_tr.reshape(M, T)
         out["margin"] = mar_tr.reshape(M, T)
+        out["lw_minus"] = lw_tr.reshape(M, T)  # log w_{t^-} after the reweight of step t
     return out
 
 

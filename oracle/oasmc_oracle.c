@@ -570,6 +570,8 @@ int orc_systematic(int64_t N, const double* lw, uint32_t u, int32_t* anc)
  *   accept[N*T]  per particle and step accept flag, margin[N*T] log alpha - log u
  *   resampled[T] 1 where a resampling event happened at t
  *   ess[T]       relative ESS of w_{t^-}
+ *   lw_trace[N*T] log w_{t^-} of every particle after the reweight of step t
+ *                (before any resampling at t), at [n*T + t-1]
  * subset/n_subset (AIS only): run only these global particle indices; every
  *   per-particle output is then indexed by position in the subset and every
  *   cross-particle statistic is over the subset.
@@ -578,7 +580,7 @@ int orc_asmc(const orc_problem* P, const orc_opts* O, int64_t N, int T, const do
              const double* eps, uint64_t seed, uint32_t round_k, uint32_t problem_id,
              double* log_g, double* acc, double* logZ, double* lw_out, double* x_out,
              int* n_resample, unsigned char* accept, double* margin, int* resampled,
-             double* ess, const int64_t* subset, int64_t n_subset)
+             double* ess, const int64_t* subset, int64_t n_subset, double* lw_trace)
 {
     if (!P || !O || T < 1 || P->d < 1 || !beta || !eps) return ORC_EINVAL;
     if (beta[0] != 0.0 || beta[T] != 1.0) return ORC_EINVAL;
@@ -623,6 +625,7 @@ int orc_asmc(const orc_problem* P, const orc_opts* O, int64_t N, int T, const do
                     LG[(size_t)j * T + (t - 1)] = lg;
                     lw += lg;
                     LW[(size_t)j * (T + 1) + t] = lw;
+                    if (lw_trace) lw_trace[(size_t)j * T + (t - 1)] = lw;
                     double mg = 0.0;
                     const int forced = O->force_accept ? O->force_accept[(size_t)j * T + (t - 1)] : -1;
                     A[(size_t)j * T + (t - 1)] =
@@ -684,6 +687,8 @@ int orc_asmc(const orc_problem* P, const orc_opts* O, int64_t N, int T, const do
             moments(M, lw, lg, m3, tmp);
             for (int i = 0; i < 3; ++i) log_g[i * T + (t - 1)] = m3[i];
             for (int64_t j = 0; j < M; ++j) lw[j] += lg[j];
+            if (lw_trace)
+                for (int64_t j = 0; j < M; ++j) lw_trace[(size_t)j * T + (t - 1)] = lw[j];
             int na = 0;
 #pragma omp parallel reduction(+ : na)
             {
@@ -1016,7 +1021,7 @@ int orc_run(const orc_problem* P, const orc_opts* O, const orc_run_opts* R, int6
         double lz = 0.0;
         int nres = 0;
         status = orc_asmc(P, O, N, T, beta, eps, seed, (uint32_t)k, problem_id, lg, acc, &lz, lw,
-                          xo, &nres, NULL, NULL, NULL, NULL, NULL, 0);
+                          xo, &nres, NULL, NULL, NULL, NULL, NULL, 0, NULL);
         free(lw);
         free(xo);
         if (status != ORC_OK && status != ORC_ENONFINITE) break;

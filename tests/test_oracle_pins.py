@@ -461,3 +461,87 @@ def test_run_budget_rules(orc):
     r = orc.run(P, orc.Opts(move=orc.MOVE_RWMH), ro, 100, 6, seed=1)
     assert list(r["N"]) == [100, 141, 199, 281, 281, 281]
     assert list(r["T"]) == [4, 6, 8, 11, 22, 44]
+
+
+# --------------------------------------------------------------------------- trigger statistics
+def _lse(a, axis=0):
+    m = np.max(a, axis=axis, keepdims=True)
+    return np.squeeze(m, axis=axis) + np.log(np.sum(np.exp(a - m), axis=axis))
+
+
+@pytest.mark.parametrize("trigger", [0, 1])
+def test_ess_cess_and_events_recomputed(orc, trigger):
+    """The relative ESS of w_{t^-} (AR strategy), CESS_t / N = exp(-D_hat_t)
+    (eq. CESS), the moments log g_hat_{t,i}, the trigger decisions and the AR
+    estimator of log Z (eq. estimator_Z) recomputed in numpy from the oracle's
+    per-particle log w_{t^-} trace.  The weights before the reweight are
+    w_{t-1} = w_{(t-1)^-}, or 1 after an event at t-1, so the trace fixes
+    every statistic.  A wrong variant (the ESS of w_{t-1} instead of w_{t^-})
+    is computed here too and must disagree, so the pin has power."""
+    d, N, T = 4, 300, 8
+    mu = np.array([2.0, -1.0, 1.5, 0.5])
+    P = _gauss_problem(orc, d, mu, 0.02, s2_ref=1.5)
+    beta = np.linspace(0, 1, T + 1) ** 2
+    o = orc.asmc(P, orc.Opts(move=orc.MOVE_HMC, leapfrog=3, resample=1, trigger=trigger, nu=0.5,
+                             state_f32=1), N, beta, 0.25, seed=5, traces=True)
+    assert o["status"] == 0
+    lwm = o["lw_minus"]                      # [N, T]: log w_{t^-}
+    res = o["resampled"]
+    assert 2 <= o["n_resample"] <= T - 2     # several events, not every step
+    prev = np.zeros((N, T))                  # log w_{t-1}
+    for t in range(1, T):
+        prev[:, t] = 0.0 if res[t - 1] else lwm[:, t - 1]
+    lg = lwm - prev
+    # moments
+    for i in range(3):
+        np.testing.assert_allclose(o["log_g"][i], _lse(prev + i * lg), rtol=0, atol=1e-10)
+    # relative ESS of w_{t^-}: (sum w)^2 / (N sum w^2)
+    ess = np.exp(2 * _lse(lwm) - _lse(2 * lwm) - np.log(N))
+    np.testing.assert_allclose(o["ess"], ess, rtol=1e-11, atol=0)
+    wrong = np.exp(2 * _lse(prev) - _lse(2 * prev) - np.log(N))
+    assert np.max(np.abs(wrong - o["ess"])) > 1e-2
+    # trigger decisions (none at T: the final event only closes the estimate)
+    D = _lse(prev + 2 * lg) - 2 * _lse(prev + lg) + _lse(prev)
+    stat = ess if trigger == 0 else np.exp(-D)
+    np.testing.assert_array_equal(res[:-1], (stat[:-1] < 0.5).astype(np.int32))
+    assert res[-1] == 0
+    # AR estimator: sum over events (and T) of logmeanexp(log w_{tau^-})
+    ev = [t for t in range(T - 1) if res[t]] + [T - 1]
+    lz = sum(_lse(lwm[:, t]) - np.log(N) for t in ev)
+    assert abs(lz - o["logZ"]) < 1e-10
+    np.testing.assert_allclose(o["lw"], lwm[:, -1], rtol=0, atol=0)
+
+
+def test_step_size_rule_recomputed(orc):
+    """Step sizes across rounds (kernel adaptation between rounds): round 1 uses
+    eps0 (1 + beta_t kappa)^(-1/2); round k+1 uses
+    exp(L(beta)) with L the piecewise-linear function through the knots
+    (beta_t^{(k)}, log eps_t^{(k)} + acc_t^{(k)} - a*), t >= 1, constant beyond
+    its ends, evaluated at the new schedule.  Recomputed with numpy.interp from
+    the oracle's own round outputs.  Wrong variants (knots at t/T instead of
+    beta_t, the new round's acceptance instead of the old one's) must
+    disagree."""
+    d = 3
+    P = _gauss_problem(orc, d, 1.0, 0.3, s2_ref=2.0)
+    a_star, eps0, kappa = 0.65, 0.6, 3.0
+    ro = orc.RunOpts(budget=2, T1=4, Tmax=32, eps_adapt=1, eps0=eps0, eps_kappa=kappa,
+                     accept_target=a_star)
+    r = orc.run(P, orc.Opts(move=orc.MOVE_HMC, leapfrog=3), ro, 200, 4, seed=3)
+    assert r["status"] == 0 and list(r["T"]) == [4, 8, 16, 32]
+    T0 = r["T"][0]
+    b0 = r["beta"][0][:T0 + 1]
+    np.testing.assert_allclose(r["eps"][0][:T0], eps0 / np.sqrt(1 + b0[1:] * kappa),
+                               rtol=1e-15)
+    far = []
+    for k in range(3):
+        T, Tn = r["T"][k], r["T"][k + 1]
+        b, bn = r["beta"][k][:T + 1], r["beta"][k + 1][:Tn + 1]
+        ky = np.log(r["eps"][k][:T]) + r["acc"][k][:T] - a_star
+        want = np.exp(np.interp(bn[1:], b[1:], ky))
+        np.testing.assert_allclose(r["eps"][k + 1][:Tn], want, rtol=1e-13)
+        # wrong variants
+        w1 = np.exp(np.interp(np.arange(1, Tn + 1) / Tn, np.arange(1, T + 1) / T, ky))
+        acc_new = np.interp(bn[1:], bn[1:], r["acc"][k + 1][:Tn])
+        w2 = np.exp(np.interp(bn[1:], b[1:], np.log(r["eps"][k][:T])) + acc_new - a_star)
+        far.append((np.max(np.abs(w1 / want - 1)), np.max(np.abs(w2 / want - 1))))
+    assert max(f[0] for f in far) > 1e-3 and max(f[1] for f in far) > 1e-3
