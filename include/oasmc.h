@@ -259,6 +259,25 @@ int oasmc_resample(oasmc_handle* h, int64_t N, const double* lw, uint32_t u, int
                    void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * systematic resampling as oasmc_resample, with the same kernels and bitwise
+ * the same ancestors, but its scratch (integer CDF, block totals, flag words)
+ * is a fixed static device array of about 8.0 MiB (OASMC_NOALLOC_MAX_N
+ * uint64 words plus 4 KiB), one copy per GPU, held until the process ends.
+ * No handle; runs on the current HIP device, whose scratch address is looked
+ * up on the first call on that device.  lw[N] (device, binary64) and anc[N]
+ * (device, int32) are the caller's; N must lie in [1, OASMC_NOALLOC_MAX_N]
+ * (else OASMC_EINVAL before any device work).  Asynchronous: the call only
+ * enqueues kernels on `stream` and synchronises nothing; when no weight is
+ * finite every anc[n] is -1.  Every call on one GPU shares that GPU's
+ * scratch, so calls that overlap on one GPU (other streams or threads) race
+ * and must be ordered by the caller.  Allocates nothing.
+ */
+#define OASMC_NOALLOC_MAX_N ((int64_t)1 << 20)
+int oasmc_resample_noalloc(int64_t N, const double* lw, uint32_t u, int32_t* anc, void* stream);
+
+/*
  * Gradient of log Z_hat with respect to the mixture target's parameters
  * theta = (means[K][d], log_scales[K]) for one AIS pass with MALA moves
  * (same arguments and random streams as oasmc_asmc), differentiating the

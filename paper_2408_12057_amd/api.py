@@ -100,6 +100,7 @@ def _load():
     L.oasmc_run.argtypes = [vp, C.POINTER(_Problem), C.POINTER(_Kernel), C.POINTER(_RunOpts),
                             C.c_int64, C.c_uint64, C.c_uint32, C.POINTER(_RunOut), vp]
     L.oasmc_resample.argtypes = [vp, C.c_int64, vp, C.c_uint32, vp, vp]
+    L.oasmc_resample_noalloc.argtypes = [C.c_int64, vp, C.c_uint32, vp, vp]
     L.oasmc_philox.argtypes = [vp, C.c_uint64, vp, vp, C.c_int64, vp]
     L.oasmc_logZ_backward.argtypes = [vp, C.POINTER(_Problem), C.POINTER(_Kernel), C.c_int64,
                                       C.c_int32, vp, vp, C.c_uint64, C.c_uint32, C.c_uint32,
@@ -110,7 +111,7 @@ def _load():
     L.oasmc_profile.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for f in ("oasmc_handle_create", "oasmc_handle_destroy", "oasmc_asmc", "oasmc_adapt_schedule",
-              "oasmc_run", "oasmc_resample", "oasmc_philox", "oasmc_logreg_eval",
+              "oasmc_run", "oasmc_resample", "oasmc_resample_noalloc", "oasmc_philox", "oasmc_logreg_eval",
               "oasmc_profile", "oasmc_logZ_backward", "oasmc_run_batch"):
         getattr(L, f).restype = C.c_int
     _lib = L
@@ -296,6 +297,23 @@ def resample(lw: torch.Tensor, u: int) -> torch.Tensor:
     _check(_load().oasmc_resample(_handle(lw.device.index or 0), int(lw.numel()),
                                   C.c_void_p(lw.data_ptr()), int(u) & 0xFFFFFFFF,
                                   C.c_void_p(anc.data_ptr()), _stream(lw.device)))
+    return anc
+
+
+NOALLOC_MAX_N = 1 << 20
+
+
+def resample_noalloc(lw: torch.Tensor, u: int, anc: torch.Tensor) -> torch.Tensor:
+    """oasmc_resample_noalloc: the same resampling into the caller's int32
+    buffer anc[N], with the library's static scratch (nothing allocated;
+    asynchronous on the current stream).  lw must already be float64 and
+    contiguous on the same device."""
+    assert lw.dtype == torch.float64 and lw.is_contiguous()
+    assert anc.dtype == torch.int32 and anc.is_contiguous() and anc.numel() == lw.numel()
+    with torch.cuda.device(lw.device):
+        _check(_load().oasmc_resample_noalloc(int(lw.numel()), C.c_void_p(lw.data_ptr()),
+                                              int(u) & 0xFFFFFFFF, C.c_void_p(anc.data_ptr()),
+                                              _stream(lw.device)))
     return anc
 
 

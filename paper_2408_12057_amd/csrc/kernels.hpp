@@ -233,6 +233,10 @@ size_t logreg_shared_bytes();
 // Packs X and y into the kernel's padded, column-permuted layout in ws.
 hipError_t logreg_prepare(const TargetDev& tg, void* ws, hipStream_t st);
 int64_t logreg_tiles(int64_t N);
+// Sets / clears the message oasmc_last_error() returns on this thread.
+int record_error(int code, const char* fmt, ...);
+void clear_error();
+
 // Clears small device scalars with a kernel (no memset nodes, so callers may capture it).
 hipError_t launch_zero(double* a, int na, int* b, int nb, hipStream_t st);
 

@@ -33,6 +33,25 @@ int fail(int code, const char* fmt, ...)
     return code;
 }
 
+}  // namespace
+
+namespace oasmc {
+// Error reporting for entry points defined in other source files.
+int record_error(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+void clear_error() { g_err.clear(); }
+}  // namespace oasmc
+
+namespace {
+
 #define HIP_TRY(expr)                                                                   \
     do {                                                                                \
         hipError_t e_ = (expr);                                                         \

@@ -365,10 +365,10 @@ __global__ void k_rs_commit(int64_t N, int d, AsmcState z)
 __global__ void k_rs_ancestors(int64_t N, const double* scal, const uint64_t* C,
                                const uint64_t* btot, int64_t nb, int32_t* anc)
 {
-    if (scal[2] == 0.0) return;
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
-    anc[n] = (int32_t)find_ancestor(n, N, (uint32_t)scal[3], C, btot, nb);
+    // no finite weight: every ancestor is -1 (the host call also reports it)
+    anc[n] = (scal[2] == 0.0) ? -1 : (int32_t)find_ancestor(n, N, (uint32_t)scal[3], C, btot, nb);
 }
 
 // Max of lw, the flag and the word for the plain resampling entry point.
