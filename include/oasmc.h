@@ -83,6 +83,12 @@ typedef struct {
  *   trigger  : 0 = relative ESS of w_{t^-} < nu, 1 = CESS_t / N < nu
  *              (CESS of the section connecting to online CESS optimisation).
  *   nu       : threshold in (0, 1).
+ *   slots    : AIS passes only: number S of O(T) moment accumulators the
+ *              particle tiles are folded into (tile i into slot i mod S, in
+ *              tile order).  0 = min(#tiles, 2048), the default; otherwise
+ *              min(#tiles, slots).  Trajectories do not depend on S; the
+ *              moments and log Z_hat change only by rounding (a smaller S
+ *              folds several tiles into each accumulator).
  */
 typedef struct {
     int32_t move;
@@ -90,6 +96,7 @@ typedef struct {
     int32_t resample;
     int32_t trigger;
     double nu;
+    int32_t slots;
 } oasmc_kernel;
 
 /* Outputs of one ASMC pass.  Host arrays sized by the caller; NULL skips. */

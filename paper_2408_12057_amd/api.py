@@ -36,7 +36,7 @@ class _Problem(C.Structure):
 
 class _Kernel(C.Structure):
     _fields_ = [("move", C.c_int32), ("leapfrog", C.c_int32), ("resample", C.c_int32),
-                ("trigger", C.c_int32), ("nu", C.c_double)]
+                ("trigger", C.c_int32), ("nu", C.c_double), ("slots", C.c_int32)]
 
 
 class _RoundOut(C.Structure):
@@ -198,15 +198,16 @@ class Problem:
                         p(self.means), p(self.log_scales), p(self.ref_mean), self.ref_sigma2)
 
 
-def _kernel(move, leapfrog, resample_, trigger, nu) -> _Kernel:
+def _kernel(move, leapfrog, resample_, trigger, nu, slots=0) -> _Kernel:
     return _Kernel(MOVES[move] if isinstance(move, str) else int(move), int(leapfrog),
                    int(bool(resample_)), TRIGGERS[trigger] if isinstance(trigger, str)
-                   else int(trigger), float(nu))
+                   else int(trigger), float(nu), int(slots))
 
 
 def asmc(problem: Problem, N: int, beta, eps, seed: int, round_k: int = 1, problem_id: int = 0,
          move="rwmh", leapfrog: int = 5, resample_: bool = False, trigger="ess",
-         nu: float = 0.5, return_state: bool = True, accept_bits: bool = False) -> dict:
+         nu: float = 0.5, return_state: bool = True, accept_bits: bool = False,
+         slots: int = 0) -> dict:
     """Alg. 1, ASMC(N, B_T): one pass with schedule ``beta`` (T+1) and step sizes ``eps`` (T)."""
     dev = problem.device
     beta = _host_f64(beta)
@@ -228,7 +229,7 @@ def asmc(problem: Problem, N: int, beta, eps, seed: int, round_k: int = 1, probl
         bits = torch.zeros((N, (T + 31) // 32), dtype=torch.int32, device=dev)
         out.accept_bits = bits.data_ptr()
     P = problem.c()
-    K = _kernel(move, leapfrog, resample_, trigger, nu)
+    K = _kernel(move, leapfrog, resample_, trigger, nu, slots)
     code = _load().oasmc_asmc(_handle(dev.index or 0), C.byref(P), C.byref(K), int(N), int(T),
                               _np_ptr(beta), _np_ptr(eps), int(seed) & (2 ** 64 - 1),
                               int(round_k), int(problem_id), C.byref(out), _stream(dev))
@@ -260,7 +261,8 @@ def run(problem: Problem, N1: int, rounds: int, seed: int, problem_id: int = 0, 
         leapfrog: int = 5, resample_: bool = False, trigger="ess", nu: float = 0.5,
         budget="double_n", T1: int = 64, T_max: int = 0, N_max: int = 1 << 40,
         eps0: float = 0.1, eps_adapt: bool = False, eps_kappa: float = 0.0,
-        accept_target: float = 0.574, interp: int = 0, Tcap: Optional[int] = None) -> dict:
+        accept_target: float = 0.574, interp: int = 0, Tcap: Optional[int] = None,
+        slots: int = 0) -> dict:
     """Alg. 2, OASMC: `rounds` rounds with Budget and OptimiseSchedule between them."""
     dev = problem.device
     b = BUDGETS[budget] if isinstance(budget, str) else int(budget)
@@ -281,7 +283,7 @@ def run(problem: Problem, N1: int, rounds: int, seed: int, problem_id: int = 0, 
     ro = _RunOpts(b, int(T1), int(T_max), int(N_max), int(bool(eps_adapt)), float(eps0),
                   float(eps_kappa), float(accept_target), int(interp))
     P = problem.c()
-    K = _kernel(move, leapfrog, resample_, trigger, nu)
+    K = _kernel(move, leapfrog, resample_, trigger, nu, slots)
     code = _load().oasmc_run(_handle(dev.index or 0), C.byref(P), C.byref(K), C.byref(ro),
                              int(N1), int(seed) & (2 ** 64 - 1), int(problem_id), C.byref(out),
                              _stream(dev))
@@ -352,7 +354,7 @@ def profile(enable: bool, device: int = 0) -> dict:
 
 
 def logZ_backward(problem: Problem, N: int, beta, eps, seed: int, round_k: int = 1,
-                  problem_id: int = 0):
+                  problem_id: int = 0, slots: int = 0):
     """(log Z_hat, grad of log Z_hat w.r.t. (means.ravel(), log_scales)) for the mixture
     target with MALA, accept decisions held fixed."""
     dev = problem.device
@@ -363,7 +365,7 @@ def logZ_backward(problem: Problem, N: int, beta, eps, seed: int, round_k: int =
     grad = np.zeros(K * problem.d + K)
     lz = C.c_double(0.0)
     P = problem.c()
-    Kn = _kernel("mala", 1, False, "ess", 0.5)
+    Kn = _kernel("mala", 1, False, "ess", 0.5, slots)
     _check(_load().oasmc_logZ_backward(_handle(dev.index or 0), C.byref(P), C.byref(Kn), int(N),
                                        int(T), _np_ptr(beta), _np_ptr(eps),
                                        int(seed) & (2 ** 64 - 1), int(round_k), int(problem_id),
@@ -409,6 +411,7 @@ class BatchItem:
     accept_target: float = 0.574
     seed: int = 0
     problem_id: int = 0
+    slots: int = 0
 
 
 def run_batch(items, rounds: int, use_graph: bool = True) -> dict:
@@ -419,7 +422,7 @@ def run_batch(items, rounds: int, use_graph: bool = True) -> dict:
     arr = (_BatchProblem * P)()
     for i, it in enumerate(items):
         arr[i].problem = it.problem.c()
-        arr[i].kernel = _kernel(it.move, it.leapfrog, False, "ess", 0.5)
+        arr[i].kernel = _kernel(it.move, it.leapfrog, False, "ess", 0.5, it.slots)
         arr[i].N = int(it.N)
         arr[i].T = int(it.T)
         arr[i].eps_adapt = int(bool(it.eps_adapt))

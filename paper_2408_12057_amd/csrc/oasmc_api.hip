@@ -123,6 +123,13 @@ hipError_t wget(oasmc_handle* h, int id, size_t count, T** p)
     return e;
 }
 
+// Moment slots of an AIS pass over `ntiles` tiles (oasmc_kernel.slots).
+int64_t slot_count(int64_t ntiles, int32_t slots)
+{
+    const int64_t cap = slots > 0 ? (int64_t)slots : 2048;
+    return std::min<int64_t>(ntiles, cap);
+}
+
 int check_schedule(int T, const double* beta)
 {
     if (T < 1) return fail(OASMC_EINVAL, "T must be >= 1 (got %d)", T);
@@ -145,6 +152,7 @@ int check_problem(const oasmc_problem* p, const oasmc_kernel* k)
         return fail(OASMC_EINVAL, "unknown move %d", k->move);
     if (k->move == OASMC_HMC && k->leapfrog < 1)
         return fail(OASMC_EINVAL, "HMC needs leapfrog >= 1");
+    if (k->slots < 0) return fail(OASMC_EINVAL, "slots must be >= 0 (0 = default)");
     if (k->resample && !(k->nu > 0.0 && k->nu < 1.0))
         return fail(OASMC_EINVAL, "nu must lie in (0, 1)");
     switch (p->family) {
@@ -693,7 +701,7 @@ int prepare_dev_problem(oasmc_handle* h, DevProblem& q)
         q.kh = 0;
         q.ntiles = valu_tiles(q.N, q.shape);
     }
-    q.S = std::min<int64_t>(q.ntiles, 2048);
+    q.S = slot_count(q.ntiles, q.kern.slots);
     q.Tcap = 1;
     for (int T : q.Ts) q.Tcap = std::max(q.Tcap, T);
     return OASMC_OK;
@@ -809,7 +817,7 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
                 return fail(OASMC_EUNSUPPORTED, "no kernel shape for d=%d", problem->d);
             ntiles = valu_tiles(N, shape);
         }
-        const int64_t S = std::min<int64_t>(ntiles, 2048);
+        const int64_t S = slot_count(ntiles, kernel->slots);
         double* part;
         HIP_TRY(wget(h, B_PART, (size_t)S * (T + 1) * 4, &part));
         a.part = part;
@@ -995,7 +1003,7 @@ int oasmc_logZ_backward(oasmc_handle* h, const oasmc_problem* problem, const oas
     a.eps = deps;
     a.lw_out = dlw;
     const int64_t ntiles = valu_tiles(N, shape);
-    const int64_t S = std::min<int64_t>(ntiles, 2048);
+    const int64_t S = slot_count(ntiles, kernel->slots);
     double* part;
     HIP_TRY(wget(h, B_PART, (size_t)S * (T + 1) * 4, &part));
     a.part = part;

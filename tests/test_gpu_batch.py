@@ -100,3 +100,51 @@ def test_full_batch_sampled_against_plain(oa):
         s = specs[i]
         r = _plain(oa, probs[i], s, 4, 99, int(i))
         np.testing.assert_array_equal(b["logZ"][i], r["logZ"], err_msg=f"problem {i}")
+
+
+def test_batch_against_oracle_runs(oa):
+    """Batched closed-form problems against the oracle's own Alg. 2 runs (not
+    against plain GPU runs): per-round log Z_hat and Lambda_hat_T.  One
+    problem (Gaussian d = 150 on 16 lanes per particle, N = 8203, i.e. 2051
+    tiles) folds several tiles into a moment slot; the small ones use a slot
+    cap of 2.  Tolerances are the stated ones (log Z_hat within 1e-6)."""
+    import oracle as orc
+    rng = np.random.default_rng(31)
+    rounds = 2
+    specs = [
+        dict(family="gauss", d=150, N=8203, T=4, move="rwmh", params=wl.random_gauss(rng, 150),
+             eps0=0.04, eps_adapt=False, eps_kappa=0.0, slots=0),
+        dict(family="gauss", d=12, N=700, T=8, move="rwmh", params=wl.random_gauss(rng, 12),
+             eps0=0.3, eps_adapt=False, eps_kappa=0.0, slots=2),
+        dict(family="gmm", d=20, N=300, T=8, move="mala", params=wl.random_gmm(rng, 20, 4),
+             eps0=0.4, eps_adapt=True, eps_kappa=2.0, slots=2),
+        dict(family="gmm", d=70, N=90, T=4, move="hmc", params=wl.random_gmm(rng, 70, 5),
+             eps0=0.2, eps_adapt=True, eps_kappa=1.0, slots=2),
+    ]
+    probs = [_problem(oa, s) for s in specs]
+    items = [oa.BatchItem(problem=p, N=s["N"], T=s["T"], move=s["move"], leapfrog=3,
+                          eps0=s["eps0"], eps_adapt=s["eps_adapt"], eps_kappa=s["eps_kappa"],
+                          seed=500 + i, problem_id=i, slots=s["slots"])
+             for i, (p, s) in enumerate(zip(probs, specs))]
+    b = oa.run_batch(items, rounds, use_graph=True)
+    assert np.all(b["status"] == 0)
+    moves = {"rwmh": orc.MOVE_RWMH, "mala": orc.MOVE_MALA, "hmc": orc.MOVE_HMC}
+    for i, s in enumerate(specs):
+        if s["family"] == "gauss":
+            op = orc.Problem(family=orc.FAM_GAUSS, d=s["d"], mu=s["params"]["mu"],
+                             sigma2=s["params"]["sigma2"], ref_sigma2=1.0)
+        else:
+            op = orc.Problem(family=orc.FAM_GMM, d=s["d"], means=s["params"]["means"],
+                             log_scales=s["params"]["log_scales"], ref_sigma2=4.0)
+        T = s["T"]
+        o = orc.run(op, orc.Opts(move=moves[s["move"]], leapfrog=3, state_f32=1),
+                    orc.RunOpts(budget=2, T1=max(1, T >> (rounds - 1)), Tmax=T,
+                                eps_adapt=int(s["eps_adapt"]), eps0=s["eps0"],
+                                eps_kappa=s["eps_kappa"], accept_target=0.574),
+                    s["N"], rounds, seed=500 + i, problem_id=i, Tcap=T)
+        assert o["status"] == 0
+        np.testing.assert_allclose(b["logZ"][i], o["logZ"], rtol=0, atol=1e-6,
+                                   err_msg=f"problem {i}")
+        lam_T = np.array([o["Lambda"][k][o["T"][k]] for k in range(rounds)])
+        np.testing.assert_allclose(b["Lambda_T"][i], lam_T, rtol=1e-6, atol=1e-8,
+                                   err_msg=f"problem {i}")

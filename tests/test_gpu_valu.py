@@ -82,6 +82,62 @@ def test_ais_round_matches_oracle(oa, family, d, move, N, T, K):
     _compare_round(g, o, T, N)
 
 
+# Several tiles folded into one moment slot (the accumulation branch that the
+# default min(#tiles, 2048) slots reach only above 2048 tiles): a slot cap on
+# small runs, and one run above 2048 tiles with the default cap.
+SLOT_CASES = [
+    # family, d, move, N, T, K, slots
+    ("gauss", 10, "rwmh", 1000, 9, 0, 3),    # 16 tiles of 64 particles into 3 slots
+    ("gauss", 100, "mala", 37, 6, 0, 2),     # 16 lanes per particle, 10 tiles (ragged)
+    ("gmm", 20, "mala", 300, 7, 4, 2),       # 4 lanes x 8 coordinates, 19 tiles
+    ("gmm", 60, "hmc", 90, 5, 16, 1),        # every tile into one slot
+]
+
+
+@pytest.mark.parametrize("family,d,move,N,T,K,slots", SLOT_CASES)
+def test_ais_several_tiles_per_slot(oa, family, d, move, N, T, K, slots):
+    rng = np.random.default_rng(d * 77 + N)
+    params = wl.random_gauss(rng, d) if family == "gauss" else wl.random_gmm(rng, d, K)
+    beta = np.concatenate([[0.0], np.sort(rng.random(T - 1)), [1.0]])
+    eps = rng.uniform(0.1, 0.4, size=T)
+    gp = gpu_problem(oa, family, params, 1.3)
+    g = oa.asmc(gp, N, beta, eps, 99, round_k=2, move=move, leapfrog=3, accept_bits=True,
+                slots=slots)
+    op = oracle_problem(family, d, params, 1.3)
+    o = orc.asmc(op, orc.Opts(move=ORC_MOVE[move], leapfrog=3, state_f32=1), N, beta, eps, 99,
+                 round_k=2, traces=True)
+    assert o["status"] == 0
+    _compare_round(g, o, T, N)
+
+
+def test_ais_above_2048_tiles_matches_oracle(oa):
+    """Gaussian d = 100 on 16 lanes per particle (4 particles per tile) with
+    N = 8203: 2051 tiles, so the default 2048 slots fold three of them twice.
+    At this size the comparison uses the stated tolerances (trajectories
+    within 1e-5 relative, decisions excused within 1e-6 of the threshold)
+    rather than bitwise equality."""
+    rng = np.random.default_rng(8203)
+    params = wl.random_gauss(rng, 100)
+    T, N = 3, 8203
+    beta = np.array([0.0, 0.2, 0.6, 1.0])
+    eps = np.full(T, 0.05)
+    gp = gpu_problem(oa, "gauss", params, 1.0)
+    g = oa.asmc(gp, N, beta, eps, 5, move="rwmh", accept_bits=True)
+    op = oracle_problem("gauss", 100, params, 1.0)
+    o = orc.asmc(op, orc.Opts(move=orc.MOVE_RWMH, state_f32=1), N, beta, eps, 5, traces=True)
+    acc_g = unpack_bits(g["accept_bits"].cpu().numpy(), T)
+    excused, bad = first_flips(acc_g, o["accept"], o["margin"], 1e-6)
+    assert not bad, bad[:5]
+    keep = np.ones(N, dtype=bool)
+    keep[[n for n, _, _ in excused]] = False
+    xg = g["x"].cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(xg[keep], o["x"][keep], rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(g["lw"].cpu().numpy()[keep], o["lw"][keep], rtol=1e-9, atol=1e-9)
+    if not excused:
+        np.testing.assert_allclose(g["log_g"], o["log_g"], rtol=1e-10, atol=1e-10)
+        assert abs(g["logZ"] - o["logZ"]) < 1e-6
+
+
 @pytest.mark.parametrize("trigger", ["ess", "cess"])
 @pytest.mark.parametrize("family,d,move,N,T,K", [("gauss", 4, "hmc", 300, 12, 0),
                                                  ("gmm", 20, "mala", 2100, 10, 4),
