@@ -66,7 +66,7 @@ class _Opts(C.Structure):
     _fields_ = [
         ("move", C.c_int), ("leapfrog", C.c_int), ("resample", C.c_int),
         ("trigger", C.c_int), ("nu", C.c_double), ("state_f32", C.c_int),
-        ("nthreads", C.c_int), ("force_accept", C.c_void_p),
+        ("nthreads", C.c_int), ("force_accept", C.c_void_p), ("resample_at", C.c_void_p),
     ]
 
 
@@ -74,7 +74,7 @@ class _RunOpts(C.Structure):
     _fields_ = [
         ("budget", C.c_int), ("T1", C.c_int), ("Tmax", C.c_int), ("Nmax", C.c_int64),
         ("eps_adapt", C.c_int), ("eps0", C.c_double), ("eps_kappa", C.c_double),
-        ("accept_target", C.c_double), ("interp", C.c_int),
+        ("accept_target", C.c_double), ("interp", C.c_int), ("dar", C.c_int),
     ]
 
 
@@ -115,6 +115,9 @@ def _declare(L):
                                 _dp, C.c_uint64, C.c_uint32, C.c_uint32, _dp,
                                 C.POINTER(C.c_double), C.POINTER(C.c_ubyte)]
     L.orc_logZ_grad.restype = C.c_int
+    L.orc_dar_times.argtypes = [C.c_int, _dp, _dp, C.c_int, _dp, C.c_int, C.c_double,
+                                C.POINTER(C.c_ubyte), _dp]
+    L.orc_dar_times.restype = C.c_int
 
 
 def _f64(a) -> np.ndarray:
@@ -181,14 +184,18 @@ class Opts:
     state_f32: int = 1
     nthreads: int = 0
     force_accept: Optional[np.ndarray] = None  # uint8 [N, T]: replayed MH decisions (AIS)
+    resample_at: Optional[np.ndarray] = None   # trigger 3: [T], 1 = resample after step t
 
     def c(self) -> _Opts:
-        fa = None
+        fa = ra = None
         if self.force_accept is not None:
             self._fa = np.ascontiguousarray(self.force_accept, dtype=np.uint8)
             fa = self._fa.ctypes.data
+        if self.resample_at is not None:
+            self._ra = np.ascontiguousarray(self.resample_at, dtype=np.uint8)
+            ra = self._ra.ctypes.data
         return _Opts(self.move, self.leapfrog, self.resample, self.trigger, self.nu,
-                     self.state_f32, self.nthreads, fa)
+                     self.state_f32, self.nthreads, fa, ra)
 
 
 @dataclass
@@ -202,10 +209,11 @@ class RunOpts:
     eps_kappa: float = 0.0
     accept_target: float = 0.574
     interp: int = 0
+    dar: int = 0
 
     def c(self) -> _RunOpts:
         return _RunOpts(self.budget, self.T1, self.Tmax, self.Nmax, self.eps_adapt, self.eps0,
-                        self.eps_kappa, self.accept_target, self.interp)
+                        self.eps_kappa, self.accept_target, self.interp, self.dar)
 
 
 def philox4x32_10(ctr: Sequence[int], key: Sequence[int]) -> np.ndarray:
@@ -252,6 +260,19 @@ def optimise_schedule(beta, log_g, T_new: int, interp: int = 0):
     lam = np.zeros(T + 1)
     st = lib().orc_optimise_schedule(T, _ptr(beta), _ptr(lg), T_new, interp, _ptr(bn), _ptr(lam))
     return bn, lam, st
+
+
+def dar_times(beta, log_g, beta_new, nu: float, interp: int = 0):
+    """DAR resampling times on schedule beta_new predicted from a previous
+    round (beta, log_g [3, T]).  Returns (flags uint8 [T_new], D_pred [T_new], status)."""
+    beta, beta_new = _f64(beta), _f64(beta_new)
+    T, Tn = beta.shape[0] - 1, beta_new.shape[0] - 1
+    lg = _f64(np.asarray(log_g).reshape(3, T))
+    flags = np.zeros(Tn, dtype=np.uint8)
+    Dp = np.zeros(Tn)
+    st = lib().orc_dar_times(T, _ptr(beta), _ptr(lg), Tn, _ptr(beta_new), interp, float(nu),
+                             flags.ctypes.data_as(C.POINTER(C.c_ubyte)), _ptr(Dp))
+    return flags, Dp, st
 
 
 def ell(problem: Problem, x) -> tuple:

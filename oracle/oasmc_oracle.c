@@ -350,11 +350,15 @@ typedef struct {
     int move;         /* MOVE_RWMH / MOVE_MALA / MOVE_HMC */
     int leapfrog;     /* HMC: number of leapfrog steps per trajectory */
     int resample;     /* 0: AIS (no resampling), 1: adaptive resampling */
-    int trigger;      /* 0: ESS < nu N, 1: CESS < nu N */
+    int trigger;      /* resampling times (Sec. "Resample step", strategies):
+                       * 0: ESS < nu N (AR), 1: CESS < nu N (AR with the
+                       * conditional ESS), 2: every step (SIR), 3: at the steps
+                       * flagged in resample_at (deterministic times, e.g. DAR) */
     double nu;
     int state_f32;
     int nthreads;     /* 0: OpenMP default */
     const unsigned char* force_accept; /* AIS only, [N*T] or NULL: replay these decisions */
+    const unsigned char* resample_at;  /* trigger 3: [T], 1 = resample after step t (t < T) */
 } orc_opts;
 
 typedef struct {
@@ -713,7 +717,11 @@ int orc_asmc(const orc_problem* P, const orc_opts* O, int64_t N, int T, const do
             double rel_ess = exp(2.0 * log_sum_w - logsumexp(tmp, M, 1) - log((double)M));
             double rel_cess = exp(-(m3[2] - 2.0 * m3[1] + m3[0]));
             if (ess) ess[t - 1] = rel_ess;
-            int fire = (O->trigger == 0) ? (rel_ess < O->nu) : (rel_cess < O->nu);
+            int fire;
+            if (O->trigger == 0) fire = rel_ess < O->nu;
+            else if (O->trigger == 1) fire = rel_cess < O->nu;
+            else if (O->trigger == 2) fire = 1;
+            else fire = O->resample_at ? (O->resample_at[t - 1] != 0) : 0;
             if (resampled) resampled[t - 1] = 0;
             if (t == T) {
                 /* the final event at tau_R = T: no resampling needed for Z_hat */
@@ -915,6 +923,79 @@ int orc_optimise_schedule(int T, const double* beta, const double* log_g, int T_
     return ORC_OK;
 }
 
+/*
+ * Deterministic adaptive resampling times on a new schedule (DAR: Sec.
+ * "Effective resample size for deterministic adaptive resampling", eq.
+ * (DAR-times); AR converges to it as N grows, appendix "Adaptive resampling
+ * in the large particle limit").  The true incremental discrepancies are
+ * replaced by a prediction from a previous round's moments:
+ *   - D_hat_t and Lambda_hat_t on the previous schedule beta[0..T] (as in
+ *     Alg. 3, negative D_hat clamped to 0);
+ *   - the cumulative barrier as a function of beta, the monotone interpolant
+ *     (interp 0: PCHIP, 1: linear) through the knots (beta_t, Lambda_hat_t);
+ *   - sqrt D(b, b') ~ Lambda(b') - Lambda(b) (the root-discrepancy estimate
+ *     of the dense-schedule analysis), so on the new schedule
+ *     D_pred_t = (Lambda(bn_t) - Lambda(bn_{t-1}))^2;
+ *   - tau_r is the first t > tau_{r-1} with exp(-sum_{s=tau_{r-1}+1}^t D_pred_s) < nu.
+ * flags[t-1] = 1 where t = tau_r < T_new (the event at T_new is the final one
+ * of the estimator, not a resampling).  D_pred (may be NULL) gets the
+ * predictions.  Non-finite moments: no flags, ORC_ENONFINITE.
+ */
+int orc_dar_times(int T, const double* beta, const double* log_g, int T_new,
+                  const double* beta_new, int interp, double nu, unsigned char* flags,
+                  double* D_pred)
+{
+    if (T < 1 || T_new < 1 || !beta || !log_g || !beta_new || !flags) return ORC_EINVAL;
+    if (!(nu > 0.0 && nu < 1.0)) return ORC_EINVAL;
+    for (int t = 0; t < T_new; ++t) flags[t] = 0;
+    double* Lam = (double*)malloc(sizeof(double) * (T + 1));
+    double* at = (double*)malloc(sizeof(double) * (T_new + 1));
+    Lam[0] = 0.0;
+    int finite = 1;
+    for (int t = 1; t <= T; ++t) {
+        double D = log_g[2 * T + t - 1] - 2.0 * log_g[T + t - 1] + log_g[t - 1];
+        if (!isfinite(D)) finite = 0;
+        if (!(D > 0.0)) D = 0.0;
+        Lam[t] = Lam[t - 1] + sqrt(D);
+    }
+    if (!finite) {
+        if (D_pred)
+            for (int t = 0; t < T_new; ++t) D_pred[t] = NAN;
+        free(Lam);
+        free(at);
+        return ORC_ENONFINITE;
+    }
+    /* Lambda at the new knots */
+    if (interp == 1) {
+        for (int tp = 0; tp <= T_new; ++tp) {
+            double b = beta_new[tp];
+            int k = 0;
+            while (k < T - 1 && b >= beta[k + 1]) ++k;
+            double w = (b - beta[k]) / (beta[k + 1] - beta[k]);
+            if (w < 0.0) w = 0.0;
+            if (w > 1.0) w = 1.0;
+            at[tp] = Lam[k] + w * (Lam[k + 1] - Lam[k]);
+        }
+    } else {
+        orc_pchip_eval(T + 1, beta, Lam, T_new + 1, beta_new, at);
+    }
+    const double thr = -log(nu);
+    double accum = 0.0;
+    for (int t = 1; t <= T_new; ++t) {
+        double r = at[t] - at[t - 1];
+        double D = r * r;
+        if (D_pred) D_pred[t - 1] = D;
+        accum += D;
+        if (t < T_new && accum > thr) { /* exp(-accum) < nu */
+            flags[t - 1] = 1;
+            accum = 0.0;
+        }
+    }
+    free(Lam);
+    free(at);
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Alg. 2: OASMC round loop with Budget and step-size adaptation.            */
 /* ------------------------------------------------------------------------ */
@@ -925,6 +1006,10 @@ typedef struct {
     int eps_adapt;       /* 0: eps_t = eps0; 1: adapt across rounds */
     double eps0, eps_kappa, accept_target;
     int interp;
+    int dar;             /* with resampling: 1 = each round resamples at the DAR times
+                          * predicted from the previous round (orc_dar_times, threshold
+                          * nu of the options); round 1, with no previous round, resamples
+                          * at no intermediate step */
 } orc_run_opts;
 
 /*
@@ -1015,12 +1100,19 @@ int orc_run(const orc_problem* P, const orc_opts* O, const orc_run_opts* R, int6
     uniform_schedule(T, beta);
     eps_first(R, T, beta, eps);
     int status = ORC_OK;
+    const int dar = R->dar && O->resample;
+    unsigned char* flags = (unsigned char*)calloc((size_t)Tcap + 1, 1);
+    orc_opts Ok = *O;
+    if (dar) {
+        Ok.trigger = 3;
+        Ok.resample_at = flags;
+    }
     for (int k = 1; k <= rounds; ++k) {
         double* lw = (double*)malloc(sizeof(double) * (size_t)N);
         double* xo = (double*)malloc(sizeof(double) * (size_t)N * P->d);
         double lz = 0.0;
         int nres = 0;
-        status = orc_asmc(P, O, N, T, beta, eps, seed, (uint32_t)k, problem_id, lg, acc, &lz, lw,
+        status = orc_asmc(P, &Ok, N, T, beta, eps, seed, (uint32_t)k, problem_id, lg, acc, &lz, lw,
                           xo, &nres, NULL, NULL, NULL, NULL, NULL, 0, NULL);
         free(lw);
         free(xo);
@@ -1031,7 +1123,8 @@ int orc_run(const orc_problem* P, const orc_opts* O, const orc_run_opts* R, int6
         Ts[r] = T;
         nres_out[r] = nres;
         memcpy(beta_out + (size_t)r * (Tcap + 1), beta, sizeof(double) * (T + 1));
-        memcpy(log_g_out + (size_t)r * 3 * Tcap, lg, sizeof(double) * 3 * T);
+        for (int i = 0; i < 3; ++i) /* layout [rounds][3][Tcap] */
+            memcpy(log_g_out + ((size_t)r * 3 + i) * Tcap, lg + (size_t)i * T, sizeof(double) * T);
         memcpy(acc_out + (size_t)r * Tcap, acc, sizeof(double) * T);
         memcpy(eps_out + (size_t)r * Tcap, eps, sizeof(double) * T);
         /* Lambda_hat of this round and the next round's schedule (Alg. 3) */
@@ -1044,6 +1137,10 @@ int orc_run(const orc_problem* P, const orc_opts* O, const orc_run_opts* R, int6
         int s2 = orc_optimise_schedule(T, beta, lg, Tn, R->interp, bn,
                                        Lambda_out + (size_t)r * (Tcap + 1));
         if (status == ORC_OK && s2 != ORC_OK) status = s2;
+        if (dar) {
+            int s3 = orc_dar_times(T, beta, lg, Tn, bn, R->interp, O->nu, flags, NULL);
+            if (status == ORC_OK && s3 != ORC_OK) status = s3;
+        }
         eps_next(R, T, beta, eps, acc, Tn, bn, en);
         memcpy(beta, bn, sizeof(double) * (Tn + 1));
         memcpy(eps, en, sizeof(double) * Tn);
@@ -1057,6 +1154,7 @@ int orc_run(const orc_problem* P, const orc_opts* O, const orc_run_opts* R, int6
     free(eps);
     free(lg);
     free(acc);
+    free(flags);
     return status;
 }
 

@@ -1195,7 +1195,9 @@ extern "C" int oasmc_run(oasmc_handle* h, const oasmc_problem* problem, const oa
             std::copy(eps_all + (size_t)k * r.Tcap, eps_all + (size_t)k * r.Tcap + T,
                       out->eps + (size_t)k * Tcap);
             const double* lg = reinterpret_cast<const double*>(base + o.log_g) + (size_t)k * 3 * r.Tcap;
-            std::copy(lg, lg + 3 * T, out->log_g + (size_t)k * 3 * Tcap);
+            for (int i = 0; i < 3; ++i)  // layout [rounds][3][Tcap]
+                std::copy(lg + (size_t)i * T, lg + (size_t)(i + 1) * T,
+                          out->log_g + ((size_t)k * 3 + i) * Tcap);
             const double* ac = reinterpret_cast<const double*>(base + o.acc) + (size_t)k * r.Tcap;
             std::copy(ac, ac + T, out->accept + (size_t)k * Tcap);
             const double* la = reinterpret_cast<const double*>(base + o.Lambda) + (size_t)k * (r.Tcap + 1);
@@ -1232,7 +1234,9 @@ extern "C" int oasmc_run(oasmc_handle* h, const oasmc_problem* problem, const oa
         out->T[r] = T;
         out->n_resample[r] = ro.n_resample;
         std::copy(beta.begin(), beta.end(), out->beta + (size_t)r * (Tcap + 1));
-        std::copy(lg.begin(), lg.end(), out->log_g + (size_t)r * 3 * Tcap);
+        for (int i = 0; i < 3; ++i)  // layout [rounds][3][Tcap]
+            std::copy(lg.begin() + (size_t)i * T, lg.begin() + (size_t)(i + 1) * T,
+                      out->log_g + ((size_t)r * 3 + i) * Tcap);
         std::copy(acc.begin(), acc.end(), out->accept + (size_t)r * Tcap);
         std::copy(eps.begin(), eps.end(), out->eps + (size_t)r * Tcap);
         int64_t Nn;
