@@ -33,7 +33,8 @@ PEAK_LANE_CYCLES = 256 * 64 * 2.4e9
 # algorithmic ALU work per particle-step in lane-cycles (Philox blocks, binary64
 # Box-Muller, target and gradient arithmetic, moment statistics; the model is
 # derived per workload alongside the kernel descriptions)
-ALU_WORK = {"gauss": 700.0, "gauss_sat": 700.0, "asmc": 1.0e4, "asmc_ess": 1.0e4}
+ALU_WORK = {"gauss": 700.0, "gauss_sat": 700.0, "asmc": 1.0e4, "asmc_ess": 1.0e4,
+            "asmc_dar": 1.0e4}
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by the copy-kernel calibration); absent until measured
 # for the current kernel.
@@ -81,19 +82,22 @@ def gauss_sat_spec(oa, wl):
 
 def asmc_spec(oa, wl, trigger):
     """8-component mixture in d = 100, HMC (5 leapfrogs), resampling when the
-    trigger (CESS_t / N or the relative ESS) drops below 0.5, N = 65536,
+    trigger (CESS_t / N or the relative ESS) drops below 0.5, or at the DAR
+    times predicted from the previous round (trigger "dar"), N = 65536,
     T = 1, 2, ..., 1024, 2000 (log Z = 50 ln(0.2 pi))."""
     w = wl.gmm8_d100()
     prob = oa.Problem.gmm(w.params["means"], w.params["log_scales"], w.ref_sigma2)
-    kw = dict(move="hmc", leapfrog=5, resample_=True, trigger=trigger, nu=0.5, budget="double_t",
-              T1=1, T_max=2000, eps0=w.eps0, eps_adapt=True, eps_kappa=25.0 / 0.1 - 1.0,
-              accept_target=0.65)
+    dar = trigger == "dar"
+    kw = dict(move="hmc", leapfrog=5, resample_=True, trigger="ess" if dar else trigger, nu=0.5,
+              budget="double_t", T1=1, T_max=2000, eps0=w.eps0, eps_adapt=True,
+              eps_kappa=25.0 / 0.1 - 1.0, accept_target=0.65, dar=dar)
     return Spec(w, prob, kw, 12, w.N, 50 * np.log(0.2 * np.pi), "closed form", 4)
 
 
 WORKLOADS = {"logreg": logreg_spec, "gauss": gauss_spec, "gauss_sat": gauss_sat_spec,
              "asmc": lambda oa, wl: asmc_spec(oa, wl, "cess"),
-             "asmc_ess": lambda oa, wl: asmc_spec(oa, wl, "ess")}
+             "asmc_ess": lambda oa, wl: asmc_spec(oa, wl, "ess"),
+             "asmc_dar": lambda oa, wl: asmc_spec(oa, wl, "dar")}
 
 
 def cpu_baseline(w, res, budget_s: float = 15.0) -> dict:
@@ -320,7 +324,8 @@ def main() -> int:
         "config": {"workload": w.name, "N_per_round": res["N"].tolist(), "d": w.d,
                    "rounds": spec.rounds, "T_per_round": res["T"].tolist(),
                    "n": int(w.params["X"].shape[0]) if w.family == "logreg" else None,
-                   "trigger": spec.kw.get("trigger") if spec.kw.get("resample_") else None,
+                   "trigger": (("dar" if spec.kw.get("dar") else spec.kw.get("trigger"))
+                               if spec.kw.get("resample_") else None),
                    "n_resample_per_round": res["n_resample"].tolist(),
                    "Lambda_hat_last_round": float(res["Lambda"][-1][res["T"][-1]]),
                    "parallelism": "single GPU"},

@@ -79,10 +79,19 @@ typedef struct {
  *   move     : pi_beta-invariant MH kernel K_{beta_t} (one step per t).
  *   leapfrog : HMC leapfrog steps per trajectory (>= 1).
  *   resample : 0 = AIS (no intermediate resampling; particle and time loops
- *              swapped, Sec. "Optimised AIS"), 1 = adaptive resampling.
- *   trigger  : 0 = relative ESS of w_{t^-} < nu, 1 = CESS_t / N < nu
- *              (CESS of the section connecting to online CESS optimisation).
- *   nu       : threshold in (0, 1).
+ *              swapped, Sec. "Optimised AIS"), 1 = resampling at the times
+ *              `trigger` selects (Sec. "Resample step", resampling strategies).
+ *   trigger  : 0 = relative ESS of w_{t^-} < nu (adaptive, AR),
+ *              1 = CESS_t / N < nu (CESS of the section connecting to online
+ *                  CESS optimisation),
+ *              2 = after every step t < T (SIR),
+ *              3 = after the steps t < T with resample_at[t-1] != 0 (times fixed
+ *                  in advance, e.g. the DAR times of oasmc_dar_times).  Between
+ *                  two such times the particles run loop-swapped as in an AIS
+ *                  pass (state in registers, no per-step synchronisation); the
+ *                  per-step relative ESS is then not streamed (NaN).
+ *   nu       : threshold in (0, 1) (triggers 0 and 1; also the DAR threshold of
+ *              oasmc_run_opts.dar).
  *   slots    : AIS passes only: number S of O(T) moment accumulators the
  *              particle tiles are folded into (tile i into slot i mod S, in
  *              tile order).  0 = min(#tiles, 2048), the default; otherwise
@@ -97,6 +106,7 @@ typedef struct {
     int32_t trigger;
     double nu;
     int32_t slots;
+    const int32_t* resample_at; /* host [T] (trigger 3), read during the call; else unused */
 } oasmc_kernel;
 
 /* Outputs of one ASMC pass.  Host arrays sized by the caller; NULL skips. */
@@ -153,6 +163,27 @@ int oasmc_adapt_schedule(int32_t T, const double* beta, const double* log_g, int
                          int32_t interp, double* beta_new, double* Lambda_hat);
 
 /*
+ * Deterministic adaptive resampling (DAR) times for a new schedule, predicted
+ * from a previous round (Sec. "Effective resample size for deterministic
+ * adaptive resampling", eq. (DAR-times); AR converges to DAR as N grows, by the
+ * appendix on adaptive resampling in the large particle limit).  Host only:
+ *   - D_hat_t, Lambda_hat_t = sum_{s<=t} sqrt(D_hat_s) on the previous schedule
+ *     beta[T+1] from its moments log_g[3*T] (layout of oasmc_round_out.log_g;
+ *     negative D_hat clamped to 0, as in Alg. 3);
+ *   - Lambda(b): the monotone interpolant through (beta_t, Lambda_hat_t)
+ *     (interp 0: Fritsch-Carlson cubic, 1: linear);
+ *   - predicted D_pred_t = (Lambda(beta_new_t) - Lambda(beta_new_{t-1}))^2 from
+ *     sqrt D(b, b') ~ integral of the local barrier over [b, b'];
+ *   - an event at the first t after the previous one whose summed D_pred
+ *     exceeds -log nu; flags[t-1] = 1 for each event t < T_new.
+ * Outputs flags[T_new] (int32) and D_pred[T_new] (may be NULL), host.  nu in
+ * (0, 1).  Non-finite moments: no events and OASMC_ENONFINITE.
+ */
+int oasmc_dar_times(int32_t T, const double* beta, const double* log_g, int32_t T_new,
+                    const double* beta_new, int32_t interp, double nu, int32_t* flags,
+                    double* D_pred);
+
+/*
  * Budget rule between rounds (Alg. 2, Sec. on increasing N and T):
  *   OASMC_BUDGET_FIXED   : N, T unchanged
  *   OASMC_BUDGET_DOUBLE_N: N doubles, T unchanged
@@ -185,6 +216,10 @@ typedef struct {
     double eps_kappa;
     double accept_target;
     int32_t interp;
+    int32_t dar;   /* with resample = 1: rounds k >= 2 resample at the DAR times that
+                      oasmc_dar_times predicts from round k-1 for round k's schedule
+                      (threshold kernel->nu; trigger and resample_at are ignored);
+                      round 1, with no previous round, resamples at no step before T */
 } oasmc_run_opts;
 
 /* Per-round outputs (host arrays sized by the caller, row capacity Tcap). */

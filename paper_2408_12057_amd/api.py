@@ -15,7 +15,7 @@ _LIB_PATH = os.path.join(_HERE, "liboasmc.so")
 OK, EINVAL, EHIP, ENOMEM, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 GAUSS, LOGREG, GMM = 1, 2, 3
 MOVES = {"rwmh": 1, "mala": 2, "hmc": 3}
-TRIGGERS = {"ess": 0, "cess": 1}
+TRIGGERS = {"ess": 0, "cess": 1, "sir": 2, "fixed": 3}
 BUDGETS = {"fixed": 0, "double_n": 1, "double_t": 2, "sqrt2": 3}
 
 
@@ -36,7 +36,8 @@ class _Problem(C.Structure):
 
 class _Kernel(C.Structure):
     _fields_ = [("move", C.c_int32), ("leapfrog", C.c_int32), ("resample", C.c_int32),
-                ("trigger", C.c_int32), ("nu", C.c_double), ("slots", C.c_int32)]
+                ("trigger", C.c_int32), ("nu", C.c_double), ("slots", C.c_int32),
+                ("resample_at", C.c_void_p)]
 
 
 class _RoundOut(C.Structure):
@@ -51,7 +52,7 @@ class _RunOpts(C.Structure):
     _fields_ = [
         ("budget", C.c_int32), ("T1", C.c_int32), ("T_max", C.c_int32), ("N_max", C.c_int64),
         ("eps_adapt", C.c_int32), ("eps0", C.c_double), ("eps_kappa", C.c_double),
-        ("accept_target", C.c_double), ("interp", C.c_int32),
+        ("accept_target", C.c_double), ("interp", C.c_int32), ("dar", C.c_int32),
     ]
 
 
@@ -97,6 +98,8 @@ def _load():
     L.oasmc_asmc.argtypes = [vp, C.POINTER(_Problem), C.POINTER(_Kernel), C.c_int64, C.c_int32,
                              vp, vp, C.c_uint64, C.c_uint32, C.c_uint32, C.POINTER(_RoundOut), vp]
     L.oasmc_adapt_schedule.argtypes = [C.c_int32, vp, vp, C.c_int32, C.c_int32, vp, vp]
+    L.oasmc_dar_times.argtypes = [C.c_int32, vp, vp, C.c_int32, vp, C.c_int32, C.c_double, vp,
+                                  vp]
     L.oasmc_run.argtypes = [vp, C.POINTER(_Problem), C.POINTER(_Kernel), C.POINTER(_RunOpts),
                             C.c_int64, C.c_uint64, C.c_uint32, C.POINTER(_RunOut), vp]
     L.oasmc_resample.argtypes = [vp, C.c_int64, vp, C.c_uint32, vp, vp]
@@ -111,6 +114,7 @@ def _load():
     L.oasmc_profile.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for f in ("oasmc_handle_create", "oasmc_handle_destroy", "oasmc_asmc", "oasmc_adapt_schedule",
+              "oasmc_dar_times",
               "oasmc_run", "oasmc_resample", "oasmc_resample_noalloc", "oasmc_philox", "oasmc_logreg_eval",
               "oasmc_profile", "oasmc_logZ_backward", "oasmc_run_batch"):
         getattr(L, f).restype = C.c_int
@@ -198,17 +202,21 @@ class Problem:
                         p(self.means), p(self.log_scales), p(self.ref_mean), self.ref_sigma2)
 
 
-def _kernel(move, leapfrog, resample_, trigger, nu, slots=0) -> _Kernel:
+def _kernel(move, leapfrog, resample_, trigger, nu, slots=0, resample_at=None) -> _Kernel:
+    """resample_at: host int32 array (trigger "fixed"), kept alive by the caller."""
     return _Kernel(MOVES[move] if isinstance(move, str) else int(move), int(leapfrog),
                    int(bool(resample_)), TRIGGERS[trigger] if isinstance(trigger, str)
-                   else int(trigger), float(nu), int(slots))
+                   else int(trigger), float(nu), int(slots),
+                   None if resample_at is None else C.c_void_p(resample_at.ctypes.data))
 
 
 def asmc(problem: Problem, N: int, beta, eps, seed: int, round_k: int = 1, problem_id: int = 0,
          move="rwmh", leapfrog: int = 5, resample_: bool = False, trigger="ess",
          nu: float = 0.5, return_state: bool = True, accept_bits: bool = False,
-         slots: int = 0) -> dict:
-    """Alg. 1, ASMC(N, B_T): one pass with schedule ``beta`` (T+1) and step sizes ``eps`` (T)."""
+         slots: int = 0, resample_at=None) -> dict:
+    """Alg. 1, ASMC(N, B_T): one pass with schedule ``beta`` (T+1) and step sizes ``eps`` (T).
+    ``trigger``: "ess", "cess" (adaptive), "sir" (every step) or "fixed" (after the
+    steps t with ``resample_at[t-1]`` nonzero)."""
     dev = problem.device
     beta = _host_f64(beta)
     T = beta.shape[0] - 1
@@ -229,7 +237,11 @@ def asmc(problem: Problem, N: int, beta, eps, seed: int, round_k: int = 1, probl
         bits = torch.zeros((N, (T + 31) // 32), dtype=torch.int32, device=dev)
         out.accept_bits = bits.data_ptr()
     P = problem.c()
-    K = _kernel(move, leapfrog, resample_, trigger, nu, slots)
+    ra = None
+    if resample_at is not None:
+        ra = np.ascontiguousarray(np.asarray(resample_at, dtype=np.int32))
+        assert ra.shape == (T,)
+    K = _kernel(move, leapfrog, resample_, trigger, nu, slots, ra)
     code = _load().oasmc_asmc(_handle(dev.index or 0), C.byref(P), C.byref(K), int(N), int(T),
                               _np_ptr(beta), _np_ptr(eps), int(seed) & (2 ** 64 - 1),
                               int(round_k), int(problem_id), C.byref(out), _stream(dev))
@@ -262,8 +274,10 @@ def run(problem: Problem, N1: int, rounds: int, seed: int, problem_id: int = 0, 
         budget="double_n", T1: int = 64, T_max: int = 0, N_max: int = 1 << 40,
         eps0: float = 0.1, eps_adapt: bool = False, eps_kappa: float = 0.0,
         accept_target: float = 0.574, interp: int = 0, Tcap: Optional[int] = None,
-        slots: int = 0) -> dict:
-    """Alg. 2, OASMC: `rounds` rounds with Budget and OptimiseSchedule between them."""
+        slots: int = 0, dar: bool = False) -> dict:
+    """Alg. 2, OASMC: `rounds` rounds with Budget and OptimiseSchedule between them.
+    ``dar`` (with ``resample_``): rounds after the first resample at the DAR times
+    predicted from the previous round."""
     dev = problem.device
     b = BUDGETS[budget] if isinstance(budget, str) else int(budget)
     if Tcap is None:
@@ -281,7 +295,7 @@ def run(problem: Problem, N1: int, rounds: int, seed: int, problem_id: int = 0, 
     out = _RunOut(R, Tcap, _np_ptr(logZ), _np_ptr(Ns), _np_ptr(Ts), _np_ptr(beta), _np_ptr(lam),
                   _np_ptr(lg), _np_ptr(acc), _np_ptr(eps), _np_ptr(nres), 0)
     ro = _RunOpts(b, int(T1), int(T_max), int(N_max), int(bool(eps_adapt)), float(eps0),
-                  float(eps_kappa), float(accept_target), int(interp))
+                  float(eps_kappa), float(accept_target), int(interp), int(bool(dar)))
     P = problem.c()
     K = _kernel(move, leapfrog, resample_, trigger, nu, slots)
     code = _load().oasmc_run(_handle(dev.index or 0), C.byref(P), C.byref(K), C.byref(ro),
@@ -290,6 +304,20 @@ def run(problem: Problem, N1: int, rounds: int, seed: int, problem_id: int = 0, 
     _check(code)
     return dict(logZ=logZ, N=Ns, T=Ts, beta=beta, Lambda=lam, log_g=lg, acc=acc, eps=eps,
                 n_resample=nres, rounds_done=out.rounds_done)
+
+
+def dar_times(beta, log_g, beta_new, nu: float, interp: int = 0):
+    """DAR resampling times for schedule ``beta_new`` predicted from a previous round
+    (``beta``, ``log_g`` [3, T]): (flags int32 [T_new], D_pred [T_new])."""
+    beta, bn = _host_f64(beta), _host_f64(beta_new)
+    T, Tn = beta.shape[0] - 1, bn.shape[0] - 1
+    lg = _host_f64(np.asarray(log_g).reshape(3 * T))
+    flags = np.zeros(Tn, dtype=np.int32)
+    Dp = np.zeros(Tn)
+    code = _load().oasmc_dar_times(T, _np_ptr(beta), _np_ptr(lg), Tn, _np_ptr(bn), int(interp),
+                                   float(nu), _np_ptr(flags), _np_ptr(Dp))
+    _check(code)
+    return flags, Dp
 
 
 def resample(lw: torch.Tensor, u: int) -> torch.Tensor:

@@ -80,6 +80,18 @@ struct SweepArgs {
     int acc_words;
     float* ckpt;           // device [N][ceil(T/ckpt_every)][d] states before steps 1, 1+every, ... or null
     int ckpt_every;
+    // A segment between resampling times fixed in advance: the pass runs steps
+    // t_begin + 1 .. t_end (t_end = 0 means T) from the particle state in
+    // sx [N*d], sg [N*d] (MALA, HMC), sell [N], slw [N], saccw [N] and writes
+    // that state back.  sx = null for an AIS pass (start from eta, log w = 0).
+    // Entry T of the slot partials then holds the log-sum-exp of log w at the
+    // segment's end and, in its fourth field, the largest log w.
+    int t_begin, t_end;
+    float* sx;
+    double* sg;
+    double* sell;
+    double* slw;
+    uint32_t* saccw;
 };
 
 // Element e of the lane layout of (reference mean, target means) for a shape
@@ -169,6 +181,10 @@ hipError_t launch_asmc_init(const SweepArgs& a, const ValuShape& s, const AsmcSt
 hipError_t launch_asmc_step(const SweepArgs& a, const ValuShape& s, const AsmcState& z, int t,
                             int trigger, double nu, hipStream_t st);
 hipError_t launch_resample_step(const SweepArgs& a, const AsmcState& z, int t, hipStream_t st);
+// Merge of a segment's slot partials (steps t_begin+1 .. t_end and the segment's
+// final log-weights in entry T): moments, accepted counts, the log Z_hat factor
+// and, when t_end < T, the resampling event (flag, largest log w, uniform word).
+hipError_t launch_segment_merge(const SweepArgs& a, const AsmcState& z, hipStream_t st);
 hipError_t launch_merge_slots(const double* part, int64_t S, int T, int64_t N, double* log_g,
                               double* acc, double* logZ, hipStream_t st);
 hipError_t launch_resample_plain(int64_t N, const double* lw, uint32_t u, int32_t* anc,

@@ -155,6 +155,8 @@ int check_problem(const oasmc_problem* p, const oasmc_kernel* k)
     if (k->slots < 0) return fail(OASMC_EINVAL, "slots must be >= 0 (0 = default)");
     if (k->resample && !(k->nu > 0.0 && k->nu < 1.0))
         return fail(OASMC_EINVAL, "nu must lie in (0, 1)");
+    if (k->resample && (k->trigger < 0 || k->trigger > 3))
+        return fail(OASMC_EINVAL, "unknown resampling trigger %d", k->trigger);
     switch (p->family) {
     case OASMC_GAUSS:
         if (!p->mu) return fail(OASMC_EINVAL, "Gaussian target needs mu");
@@ -311,6 +313,51 @@ int adapt_schedule_impl(int T, const double* beta, const double* log_g, int Tn, 
         if (!(beta_new[tp] > beta_new[tp - 1])) beta_new[tp] = std::nextafter(beta_new[tp - 1], 2.0);
     for (int tp = Tn - 1; tp >= 1; --tp)
         if (!(beta_new[tp] < beta_new[tp + 1])) beta_new[tp] = std::nextafter(beta_new[tp + 1], -1.0);
+    return OASMC_OK;
+}
+
+// DAR times on a new schedule from a previous round's moments (eq.
+// (DAR-times)): predicted incremental discrepancies as squared differences of
+// the interpolated cumulative barrier, an event where their running sum since
+// the last event exceeds -log nu.
+int dar_times_impl(int T, const double* beta, const double* log_g, int Tn,
+                   const double* beta_new, int interp, double nu, int32_t* flags,
+                   double* D_pred)
+{
+    std::fill(flags, flags + Tn, 0);
+    MonotoneCubic f;
+    f.x.assign(beta, beta + T + 1);
+    f.y.assign(T + 1, 0.0);
+    for (int t = 1; t <= T; ++t) {
+        const double D = log_g[2 * T + t - 1] - 2.0 * log_g[T + t - 1] + log_g[t - 1];
+        if (!std::isfinite(D)) {
+            if (D_pred) std::fill(D_pred, D_pred + Tn, NAN);
+            return fail(OASMC_ENONFINITE, "non-finite moments: no DAR times");
+        }
+        f.y[t] = f.y[t - 1] + (D > 0.0 ? std::sqrt(D) : 0.0);
+    }
+    if (interp == 0) f.fit();
+    auto lam_at = [&](double b) {
+        if (interp == 0) return f(b);
+        if (b <= f.x.front()) return f.y.front();
+        if (b >= f.x.back()) return f.y.back();
+        const size_t i = std::upper_bound(f.x.begin(), f.x.end(), b) - f.x.begin() - 1;
+        const double w = (b - f.x[i]) / (f.x[i + 1] - f.x[i]);
+        return f.y[i] + w * (f.y[i + 1] - f.y[i]);
+    };
+    const double thr = -std::log(nu);
+    double prev = lam_at(beta_new[0]), sum = 0.0;
+    for (int t = 1; t <= Tn; ++t) {
+        const double cur = lam_at(beta_new[t]);
+        const double D = (cur - prev) * (cur - prev);
+        prev = cur;
+        if (D_pred) D_pred[t - 1] = D;
+        sum += D;
+        if (t < Tn && sum > thr) {
+            flags[t - 1] = 1;
+            sum = 0.0;
+        }
+    }
     return OASMC_OK;
 }
 
@@ -747,6 +794,22 @@ int oasmc_handle_destroy(oasmc_handle* h)
     return OASMC_OK;
 }
 
+int oasmc_dar_times(int32_t T, const double* beta, const double* log_g, int32_t T_new,
+                    const double* beta_new, int32_t interp, double nu, int32_t* flags,
+                    double* D_pred)
+{
+    if (T < 1 || T_new < 1) return fail(OASMC_EINVAL, "T and T_new must be >= 1");
+    if (!log_g || !beta_new || !flags) return fail(OASMC_EINVAL, "NULL argument");
+    if (!(nu > 0.0 && nu < 1.0)) return fail(OASMC_EINVAL, "nu must lie in (0, 1)");
+    int s = check_schedule(T, beta);
+    if (s) return s;
+    s = check_schedule(T_new, beta_new);
+    if (s) return s;
+    s = dar_times_impl(T, beta, log_g, T_new, beta_new, interp, nu, flags, D_pred);
+    if (s == OASMC_OK) g_err.clear();
+    return s;
+}
+
 int oasmc_adapt_schedule(int32_t T, const double* beta, const double* log_g, int32_t T_new,
                          int32_t interp, double* beta_new, double* Lambda_hat)
 {
@@ -886,14 +949,48 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
         z.log_g = dlogg;
         z.accept = dacc;
         a.ntiles = ntiles;
-        if (h->prof) HIP_TRY(hipEventRecord(h->ev0, st));
-        HIP_TRY(launch_zero(dscal, 8, z.nres, 4, st));
-        HIP_TRY(launch_asmc_init(a, shape, z, st));
-        for (int t = 1; t <= T; ++t) {
-            HIP_TRY(launch_asmc_step(a, shape, z, t, kernel->trigger, kernel->nu, st));
-            if (t < T) HIP_TRY(launch_resample_step(a, z, t, st));
+        if (kernel->trigger == 3) {
+            // times fixed in advance: each segment between two of them runs as
+            // a loop-swapped pass (particles in registers, moments streamed
+            // into O(T) slots), then its merge and the resampler
+            const int64_t S = slot_count(ntiles, kernel->slots);
+            double* part;
+            HIP_TRY(wget(h, B_PART, (size_t)S * (T + 1) * 4, &part));
+            a.part = part;
+            a.S = S;
+            a.lw_out = nullptr;
+            a.x_out = nullptr;
+            a.sx = z.X;
+            a.sg = z.G;
+            a.sell = z.ell;
+            a.slw = z.lw;
+            a.saccw = z.accw;
+            const int grid_waves = (int)std::min<int64_t>(S, (int64_t)h->cus * 8);
+            if (h->prof) HIP_TRY(hipEventRecord(h->ev0, st));
+            HIP_TRY(launch_zero(dscal, 8, z.nres, 4, st));
+            HIP_TRY(launch_asmc_init(a, shape, z, st));
+            int t0 = 0;
+            for (int t = 1; t <= T; ++t) {
+                const bool ev = t < T && kernel->resample_at && kernel->resample_at[t - 1] != 0;
+                if (!ev && t < T) continue;
+                a.t_begin = t0;
+                a.t_end = t;
+                HIP_TRY(launch_oais_valu(a, shape, grid_waves, st));
+                HIP_TRY(launch_segment_merge(a, z, st));
+                if (t < T) HIP_TRY(launch_resample_step(a, z, t, st));
+                t0 = t;
+            }
+            if (h->prof) HIP_TRY(hipEventRecord(h->ev1, st));
+        } else {
+            if (h->prof) HIP_TRY(hipEventRecord(h->ev0, st));
+            HIP_TRY(launch_zero(dscal, 8, z.nres, 4, st));
+            HIP_TRY(launch_asmc_init(a, shape, z, st));
+            for (int t = 1; t <= T; ++t) {
+                HIP_TRY(launch_asmc_step(a, shape, z, t, kernel->trigger, kernel->nu, st));
+                if (t < T) HIP_TRY(launch_resample_step(a, z, t, st));
+            }
+            if (h->prof) HIP_TRY(hipEventRecord(h->ev1, st));
         }
-        if (h->prof) HIP_TRY(hipEventRecord(h->ev1, st));
         std::vector<double> cnt(T);
         HIP_TRY(hipMemcpyAsync(out->log_g, dlogg, sizeof(double) * 3 * T, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipMemcpyAsync(cnt.data(), dacc, sizeof(double) * T, hipMemcpyDeviceToHost, st));
@@ -1216,6 +1313,15 @@ extern "C" int oasmc_run(oasmc_handle* h, const oasmc_problem* problem, const oa
     int T = opts->T1;
     std::vector<double> beta(T + 1), eps(T);
     uniform_schedule(T, beta.data());
+    // DAR: round k >= 2 resamples at the times predicted from round k - 1;
+    // round 1 at none before T
+    const bool dar = opts->dar && kernel->resample;
+    oasmc_kernel kdar = *kernel;
+    std::vector<int32_t> flags(T, 0);
+    if (dar) {
+        kdar.trigger = 3;
+        kdar.resample_at = flags.data();
+    }
     for (int t = 1; t <= T; ++t)
         eps[t - 1] = opts->eps_adapt ? opts->eps0 / std::sqrt(1.0 + beta[t] * opts->eps_kappa)
                                      : opts->eps0;
@@ -1225,8 +1331,8 @@ extern "C" int oasmc_run(oasmc_handle* h, const oasmc_problem* problem, const oa
         oasmc_round_out ro{};
         ro.log_g = lg.data();
         ro.accept = acc.data();
-        status = oasmc_asmc(h, problem, kernel, N, T, beta.data(), eps.data(), seed, (uint32_t)k,
-                            problem_id, &ro, stream);
+        status = oasmc_asmc(h, problem, dar ? &kdar : kernel, N, T, beta.data(), eps.data(), seed,
+                            (uint32_t)k, problem_id, &ro, stream);
         if (status != OASMC_OK && status != OASMC_ENONFINITE) break;
         const int r = k - 1;
         out->logZ[r] = ro.logZ;
@@ -1247,6 +1353,14 @@ extern "C" int oasmc_run(oasmc_handle* h, const oasmc_problem* problem, const oa
         const int s2 = adapt_schedule_impl(T, beta.data(), lg.data(), Tn, opts->interp, bn.data(),
                                            out->Lambda_hat + (size_t)r * (Tcap + 1));
         if (status == OASMC_OK && s2 != OASMC_OK) status = s2;
+        if (dar) {
+            std::vector<int32_t> fn(Tn, 0);
+            const int s3 = dar_times_impl(T, beta.data(), lg.data(), Tn, bn.data(), opts->interp,
+                                          kernel->nu, fn.data(), nullptr);
+            if (status == OASMC_OK && s3 != OASMC_OK) status = s3;
+            flags.swap(fn);
+            kdar.resample_at = flags.data();
+        }
         if (opts->eps_adapt) {
             std::vector<double> kx(T), ky(T);
             for (int t = 1; t <= T; ++t) {

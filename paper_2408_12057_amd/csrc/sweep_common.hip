@@ -89,7 +89,11 @@ __device__ __forceinline__ void asmc_merge_final(const SweepArgs& a, const AsmcS
     const double rel_ess = exp(2.0 * L[1] - L[3] - logN);
     const double rel_cess = exp(-(L[2] - 2.0 * L[1] + L[0]));
     z.ess[t - 1] = rel_ess;
-    const bool fire = (trigger == 0) ? (rel_ess < nu) : (rel_cess < nu);
+    // trigger 2 (SIR) resamples after every step; times fixed in advance
+    // (trigger 3) run as segments and never reach this per-step merge
+    const bool fire = (trigger == 0)   ? (rel_ess < nu)
+                      : (trigger == 1) ? (rel_cess < nu)
+                                       : (trigger == 2 && L[1] > -INFINITY);
     z.resampled[t - 1] = 0;
     z.scal[2] = 0.0;
     if (t == T) {
@@ -186,6 +190,47 @@ __global__ void __launch_bounds__(kMergeThreads) k_asmc_merge(SweepArgs a, AsmcS
     __threadfence();  // the other blocks' records
     if (w == 0) asmc_merge_final(a, z, t, trigger, nu, lane);
     if (tid == 0) z.ticket[0] = 0u;
+}
+
+// Merge of one segment between resampling times fixed in advance (one wave
+// per entry, the slot order of k_merge_slots): blocks 0 .. t_end - t_begin - 1
+// take the entries of steps t_begin + 1 .. t_end (moments, accepted counts; no
+// per-step ESS), the last block entry T, whose log-sum-exp of the segment's
+// final log-weights gives the log Z_hat factor of this event and whose fourth
+// field holds the largest log w (the shift of the resampler's integer
+// weights).  Each output element is written by one block.
+__global__ void __launch_bounds__(kWave) k_seg_merge(SweepArgs a, AsmcState z)
+{
+    const int T = a.T;
+    const int nsteps = a.t_end - a.t_begin;
+    const bool fin = (int)blockIdx.x == nsteps;
+    const int e = fin ? T : a.t_begin + (int)blockIdx.x;
+    double L[3], cnt;
+    merge_entry(a.part, a.S, T, e, L, cnt);
+    double mx = -INFINITY;
+    if (fin) {
+        for (int64_t s = threadIdx.x; s < a.S; s += kWave)
+            mx = fmax(mx, a.part[((size_t)s * (T + 1) + T) * 4 + 3]);
+        mx = wave_max(mx);
+    }
+    if (threadIdx.x != 0) return;
+    if (!fin) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) z.log_g[(size_t)i * T + e] = L[i];
+        z.accept[e] = cnt;
+        z.ess[e] = NAN;
+        z.resampled[e] = (e == a.t_end - 1 && a.t_end < T) ? 1 : 0;
+        return;
+    }
+    z.scal[0] += L[0] - log((double)a.N);
+    const bool fire = a.t_end < T && mx > -INFINITY && mx < INFINITY;
+    z.scal[2] = fire ? 1.0 : 0.0;
+    if (fire) {
+        z.scal[1] = mx;
+        const uint4 wd = draw_block(a.key, 0xFFFFFFFFu, (uint32_t)a.t_end, kStreamResample, 0u, 0u);
+        z.scal[3] = (double)wd.x;
+        z.nres[0] += 1;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -539,6 +584,13 @@ hipError_t launch_resample_step(const SweepArgs& a, const AsmcState& z, int t, h
     const int64_t total = N * (int64_t)d;
     const int64_t blocks = std::min<int64_t>((total + 255) / 256, kIdleGrid);
     hipLaunchKernelGGL(k_rs_commit, dim3((unsigned)blocks), dim3(256), 0, st, N, d, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_segment_merge(const SweepArgs& a, const AsmcState& z, hipStream_t st)
+{
+    const int nsteps = a.t_end - a.t_begin;
+    hipLaunchKernelGGL(k_seg_merge, dim3(nsteps + 1), dim3(kWave), 0, st, a, z);
     return hipGetLastError();
 }
 

@@ -487,8 +487,10 @@ __device__ __forceinline__ void oais_slot(const SweepArgs& a, const ParView& pv,
     const int d = a.tg.d;
     const bool grad = (MOVE != kRwmh);
 
-    // Fold TC buffered steps of this tile into the slot's accumulators.
-    auto flush = [&](int64_t slot, bool first, int e0, int cnt) {
+    // Fold TC buffered steps of this tile into the slot's accumulators.  For
+    // the final entry (fin) the fourth field keeps the largest log w instead
+    // of an accepted count.
+    auto flush = [&](int64_t slot, bool first, int e0, int cnt, bool fin) {
         wave_sync();
         const int tcl = lane % kTC;
         const int part = lane / kTC;
@@ -531,7 +533,10 @@ __device__ __forceinline__ void oais_slot(const SweepArgs& a, const ParView& pv,
                 const double L = lse_value(m[i], s[i]);
                 e[i] = first ? L : log_add(e[i], L);
             }
-            e[3] = (first ? 0.0 : e[3]) + (double)cntb[tcl];
+            if (fin)
+                e[3] = first ? m[0] : fmax(e[3], m[0]);
+            else
+                e[3] = (first ? 0.0 : e[3]) + (double)cntb[tcl];
         }
         wave_sync();
     };
@@ -544,10 +549,30 @@ __device__ __forceinline__ void oais_slot(const SweepArgs& a, const ParView& pv,
             const uint32_t n = (uint32_t)n64;
             float x[DPL];
             double g[DPL];
-            double ell = Particle<FAM, LPP, DPL>::init(a.tg, c, pv, a.key, n, r, x, g, grad);
-            double lw = 0.0;
-            uint32_t accw = 0;
-            for (int t = 1; t <= T; ++t) {
+            double ell, lw;
+            uint32_t accw;
+            if (a.sx) {
+                // a segment between fixed resampling times: the state the
+                // previous segment (or the initial draw) left; lanes past N
+                // work on a copy of the last particle and write nothing
+                const int64_t nl = valid ? n64 : a.N - 1;
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) {
+                    const int i = r * DPL + j;
+                    x[j] = (i < d) ? a.sx[(size_t)nl * d + i] : 0.f;
+                    g[j] = (grad && i < d) ? a.sg[(size_t)nl * d + i] : 0.0;
+                }
+                ell = a.sell[nl];
+                lw = a.slw[nl];
+                accw = a.saccw[nl];
+            } else {
+                ell = Particle<FAM, LPP, DPL>::init(a.tg, c, pv, a.key, n, r, x, g, grad);
+                lw = 0.0;
+                accw = 0;
+            }
+            const int tb = a.t_begin;
+            const int te = a.t_end > 0 ? a.t_end : T;
+            for (int t = tb + 1; t <= te; ++t) {
                 if (a.ckpt && ((t - 1) % a.ckpt_every) == 0 && valid) {
                     const int nseg = (T + a.ckpt_every - 1) / a.ckpt_every;
                     float* cp = a.ckpt + ((size_t)n64 * nseg + (t - 1) / a.ckpt_every) * d;
@@ -558,7 +583,7 @@ __device__ __forceinline__ void oais_slot(const SweepArgs& a, const ParView& pv,
                     }
                 }
                 const double lg = (a.beta[t] - a.beta[t - 1]) * ell;
-                const int tc = (t - 1) % kTC;
+                const int tc = (t - tb - 1) % kTC;
                 if (r == 0)
                     rec[tc][pl] = valid ? make_double2(lw, lg) : make_double2(-INFINITY, 0.0);
                 lw += lg;
@@ -573,13 +598,28 @@ __device__ __forceinline__ void oais_slot(const SweepArgs& a, const ParView& pv,
                         a.acc_bits[(size_t)n64 * a.acc_words + (t - 1) / 32] = accw;
                     accw = 0;
                 }
-                if (tc == kTC - 1 || t == T) flush(slot, first, t - 1 - tc, tc + 1);
+                if (tc == kTC - 1 || t == te) flush(slot, first, t - 1 - tc, tc + 1, false);
             }
-            // final weights -> entry T (log-sum-exp of log w_T over the tile)
+            // final weights -> entry T (log-sum-exp and maximum of log w over the tile)
             if (r == 0) rec[0][pl] = valid ? make_double2(lw, 0.0) : make_double2(-INFINITY, 0.0);
             if (lane == 0) cntb[0] = 0u;
-            flush(slot, first, T, 1);
+            flush(slot, first, T, 1, true);
             if (valid) {
+                if (a.sx) {
+#pragma unroll
+                    for (int j = 0; j < DPL; ++j) {
+                        const int i = r * DPL + j;
+                        if (i < d) {
+                            a.sx[(size_t)n64 * d + i] = x[j];
+                            if (grad) a.sg[(size_t)n64 * d + i] = g[j];
+                        }
+                    }
+                    if (r == 0) {
+                        a.sell[n64] = ell;
+                        a.slw[n64] = lw;
+                        a.saccw[n64] = accw;
+                    }
+                }
                 if (a.lw_out && r == 0) a.lw_out[n64] = lw;
                 if (a.x_out) {
 #pragma unroll

@@ -47,3 +47,29 @@ def gpu_problem(oa, family: str, params: dict, ref_sigma2: float, ref_mean=None)
 
 
 ORC_MOVE = {"rwmh": orc.MOVE_RWMH, "mala": orc.MOVE_MALA, "hmc": orc.MOVE_HMC}
+
+
+def compare_round(g, o, T, N, flip_tol=1e-9, rtol_lw=1e-12, exact=True):
+    """GPU pass ``g`` against the oracle pass ``o`` (traces on): MH decisions
+    equal except excused flips; states (bitwise, or within 1e-5 relative) and
+    final log-weights of the particles that followed the oracle; moments,
+    acceptance and log Z_hat when nothing was excused.  Returns the number of
+    excused particles."""
+    acc_g = unpack_bits(g["accept_bits"].cpu().numpy(), T)
+    excused, bad = first_flips(acc_g, o["accept"], o["margin"], flip_tol)
+    assert not bad, f"unexcused MH disagreements (particle, step, margin): {bad[:5]}"
+    keep = np.ones(N, dtype=bool)
+    for n, _, _ in excused:
+        keep[n] = False
+    xg = g["x"].cpu().numpy().astype(np.float64)
+    lwg = g["lw"].cpu().numpy()
+    if exact:
+        np.testing.assert_array_equal(xg[keep], o["x"][keep])
+    else:
+        np.testing.assert_allclose(xg[keep], o["x"][keep], rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(lwg[keep], o["lw"][keep], rtol=rtol_lw, atol=rtol_lw)
+    if not excused:
+        np.testing.assert_allclose(g["log_g"], o["log_g"], rtol=1e-11, atol=1e-11)
+        np.testing.assert_allclose(g["accept"], o["acc"], rtol=0, atol=1e-15)
+        assert abs(g["logZ"] - o["logZ"]) < 1e-10
+    return len(excused)

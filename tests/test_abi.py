@@ -84,3 +84,25 @@ def test_adapt_schedule_rejects_bad_input():
         oa.adapt_schedule(np.array([0.0, 0.7, 0.5, 1.0]), np.zeros((3, 3)), 4)
     with pytest.raises(oa.OasmcError):
         oa.adapt_schedule(np.array([0.1, 1.0]), np.zeros((3, 1)), 4)
+
+
+@pytest.mark.parametrize("T,T_new,interp,nu", [(1, 8, 0, 0.5), (7, 16, 0, 0.5), (40, 64, 1, 0.7),
+                                              (40, 80, 0, 0.3), (300, 1000, 0, 0.5)])
+def test_dar_times_match_oracle(orc, T, T_new, interp, nu):
+    """DAR resampling times (eq. (DAR-times)) on the host, product against the
+    oracle's independent code: predicted discrepancies to rounding, identical
+    event flags, on random moments and random new schedules."""
+    import paper_2408_12057_amd as oa
+    rng = np.random.default_rng(T * 7 + T_new)
+    beta = np.concatenate([[0.0], np.sort(rng.random(T - 1)), [1.0]]) if T > 1 else np.array([0, 1.0])
+    bn = np.concatenate([[0.0], np.sort(rng.random(T_new - 1)), [1.0]])
+    D = rng.gamma(0.5, 2.0 * T_new / T / T_new, size=T) * 10
+    D[rng.random(T) < 0.1] = 0.0
+    lg0, lg1 = rng.normal(size=T), rng.normal(size=T)
+    lg = np.stack([lg0, lg1, D + 2 * lg1 - lg0])
+    f, Dp = oa.dar_times(beta, lg, bn, nu, interp)
+    of, oDp, st = orc.dar_times(beta, lg, bn, nu, interp)
+    assert st == 0
+    np.testing.assert_allclose(Dp, oDp, rtol=1e-11, atol=1e-14)
+    np.testing.assert_array_equal(f, of.astype(np.int32))
+    assert f[-1] == 0
