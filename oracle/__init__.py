@@ -118,6 +118,10 @@ def _declare(L):
     L.orc_dar_times.argtypes = [C.c_int, _dp, _dp, C.c_int, _dp, C.c_int, C.c_double,
                                 C.POINTER(C.c_ubyte), _dp]
     L.orc_dar_times.restype = C.c_int
+    L.orc_rejuvenate.argtypes = [C.POINTER(_Problem), C.POINTER(_Opts), C.c_int64, C.c_int,
+                                 C.c_double, C.c_uint64, C.c_uint32, C.c_uint32, _dp, _dp, _dp,
+                                 _dp, _dp, _dp]
+    L.orc_rejuvenate.restype = C.c_int
 
 
 def _f64(a) -> np.ndarray:
@@ -273,6 +277,27 @@ def dar_times(beta, log_g, beta_new, nu: float, interp: int = 0):
     st = lib().orc_dar_times(T, _ptr(beta), _ptr(lg), Tn, _ptr(beta_new), interp, float(nu),
                              flags.ctypes.data_as(C.POINTER(C.c_ubyte)), _ptr(Dp))
     return flags, Dp, st
+
+
+def rejuvenate(problem: Problem, opts: Opts, lw, x, T: int, eps_T: float, seed: int,
+               round_k: int = 1, problem_id: int = 0, want_states: bool = False) -> dict:
+    """Final-iteration rejuvenation: resample (lw [N], x [N, d]) and run N chains
+    for T steps at beta = 1.  Returns mean [d], second [d], accept (and x [N, d])."""
+    lw = _f64(lw)
+    x = _f64(x)
+    N, d = x.shape
+    mean, second = np.zeros(d), np.zeros(d)
+    acc = C.c_double(0.0)
+    xo = np.zeros((N, d)) if want_states else None
+    P = problem.c()
+    O = opts.c()
+    st = lib().orc_rejuvenate(C.byref(P), C.byref(O), N, T, float(eps_T), seed, round_k,
+                              problem_id, _ptr(lw), _ptr(x), _ptr(mean), _ptr(second),
+                              C.cast(C.byref(acc), _dp), _ptr(xo))
+    out = dict(status=st, mean=mean, second=second, accept=acc.value)
+    if want_states:
+        out["x"] = xo
+    return out
 
 
 def ell(problem: Problem, x) -> tuple:

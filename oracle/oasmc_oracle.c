@@ -772,6 +772,83 @@ int orc_asmc(const orc_problem* P, const orc_opts* O, int64_t N, int T, const do
 }
 
 /* ------------------------------------------------------------------------ */
+/* Final-iteration rejuvenation (Sec. "Computing expectations").             */
+/* ------------------------------------------------------------------------ */
+/*
+ * After the last annealing step, resample the final population (weights
+ * lw[N], states x[N*d]) and run N MCMC chains for T steps, chain n starting at
+ * its resampled particle; the TN states visited estimate expectations under
+ * the target.  Readings: the chains use the pass's forward kernel at beta = 1
+ * with the last step size eps_T; the event's uniform is the resampling word of
+ * step T (stream 3, particle word 0xFFFFFFFF); chain n draws with counters
+ * (n, T + s), s = 1..T, so nothing collides with the annealing pass.  Test
+ * functions: f(x) = x_i and x_i^2.
+ * Outputs: mean[d] and second[d] (averages of x_i and x_i^2 over the TN
+ * samples), *accept (fraction of accepted chain moves), x_out[N*d] (chain end
+ * states, may be NULL).
+ */
+int orc_rejuvenate(const orc_problem* P, const orc_opts* O, int64_t N, int T, double eps_T,
+                   uint64_t seed, uint32_t round_k, uint32_t problem_id, const double* lw,
+                   const double* x, double* mean, double* second, double* accept,
+                   double* x_out)
+{
+    if (!P || !O || N < 1 || T < 1 || !lw || !x || !mean || !second) return ORC_EINVAL;
+    int d = P->d;
+    rng_key K = {seed, round_k, problem_id};
+    if (O->nthreads > 0) omp_set_num_threads(O->nthreads);
+    uint32_t w[4];
+    draw_block(&K, 0xFFFFFFFFu, (uint32_t)T, STREAM_RESAMPLE, 0, 0, w);
+    int32_t* anc = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+    double* S1 = (double*)calloc((size_t)N * d, sizeof(double));
+    double* S2 = (double*)calloc((size_t)N * d, sizeof(double));
+    int64_t* na = (int64_t*)calloc((size_t)N, sizeof(int64_t));
+    int st = orc_systematic(N, lw, w[0], anc);
+    if (st != ORC_OK) {
+        free(anc); free(S1); free(S2); free(na);
+        return st;
+    }
+#pragma omp parallel
+    {
+        double* work = (double*)malloc(sizeof(double) * 6 * d);
+        double* px = (double*)malloc(sizeof(double) * d);
+        double* pg = (double*)malloc(sizeof(double) * d);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t n = 0; n < N; ++n) {
+            memcpy(px, x + (size_t)anc[n] * d, sizeof(double) * d);
+            particle p = {px, ell(P, px), pg};
+            if (O->move != MOVE_RWMH) grad_ell(P, px, pg);
+            for (int s = 1; s <= T; ++s) {
+                na[n] += mh_step(P, O, &K, (uint32_t)n, (uint32_t)(T + s), 1.0, eps_T, &p, work,
+                                 NULL, -1);
+                for (int i = 0; i < d; ++i) {
+                    S1[(size_t)n * d + i] += p.x[i];
+                    S2[(size_t)n * d + i] += p.x[i] * p.x[i];
+                }
+            }
+            if (x_out) memcpy(x_out + (size_t)n * d, p.x, sizeof(double) * d);
+        }
+        free(work);
+        free(px);
+        free(pg);
+    }
+    double tot = (double)N * (double)T;
+    int64_t acc = 0;
+    for (int i = 0; i < d; ++i) {
+        double a = 0.0, b = 0.0;
+        for (int64_t n = 0; n < N; ++n) {
+            a += S1[(size_t)n * d + i];
+            b += S2[(size_t)n * d + i];
+        }
+        mean[i] = a / tot;
+        second[i] = b / tot;
+    }
+    for (int64_t n = 0; n < N; ++n) acc += na[n];
+    if (accept) *accept = (double)acc / tot;
+    free(anc); free(S1); free(S2); free(na);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Alg. 3: OptimiseSchedule.                                                  */
 /* ------------------------------------------------------------------------ */
 /* Fritsch-Carlson monotone piecewise-cubic Hermite interpolation (PCHIP):
