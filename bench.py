@@ -100,9 +100,10 @@ WORKLOADS = {"logreg": logreg_spec, "gauss": gauss_spec, "gauss_sat": gauss_sat_
              "asmc_dar": lambda oa, wl: asmc_spec(oa, wl, "dar")}
 
 
-def cpu_baseline(w, res, budget_s: float = 15.0) -> dict:
+def cpu_baseline(w, res, spec, budget_s: float = 15.0) -> dict:
     """The CPU oracle on a bounded sample of the same workload: a particle
-    subset of the last round (same schedule, step sizes and seed)."""
+    subset of the last round (same schedule, step sizes and seed); for the
+    resampling variant, whose particles interact, the last round at a smaller N."""
     import oracle as orc
 
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -110,30 +111,44 @@ def cpu_baseline(w, res, budget_s: float = 15.0) -> dict:
     T = int(res["T"][k])
     beta = res["beta"][k][: T + 1]
     eps = res["eps"][k][:T]
+    resample = bool(spec.kw.get("resample_"))
     if w.family == "logreg":
         P = orc.Problem(family=orc.FAM_LOGREG, d=w.d, X=w.params["X"], y=w.params["y"],
                         ref_sigma2=w.ref_sigma2)
         move = orc.MOVE_MALA
+    elif w.family == "gmm":
+        P = orc.Problem(family=orc.FAM_GMM, d=w.d, means=w.params["means"],
+                        log_scales=w.params["log_scales"], ref_sigma2=w.ref_sigma2)
+        move = orc.MOVE_HMC
     else:
         P = orc.Problem(family=orc.FAM_GAUSS, d=w.d, mu=w.params["mu"], sigma2=w.params["sigma2"],
                         ref_sigma2=w.ref_sigma2)
         move = orc.MOVE_RWMH
-    opts = orc.Opts(move=move, state_f32=1, nthreads=cores)
+    trig = {"ess": 0, "cess": 1}.get(spec.kw.get("trigger"), 0)
+    opts = orc.Opts(move=move, leapfrog=spec.kw.get("leapfrog", 5), state_f32=1, nthreads=cores,
+                    resample=int(resample), trigger=trig, nu=spec.kw.get("nu", 0.5))
+
+    def go(n):
+        if resample:
+            orc.asmc(P, opts, n, beta, eps, 1234, round_k=k + 1)
+        else:
+            orc.asmc(P, opts, int(res["N"][k]), beta, eps, 1234, round_k=k + 1,
+                     subset=np.arange(n), traces=False)
+
     # calibrate on a small sample, then size the timed sample to the budget
     n0 = cores
     t0 = time.perf_counter()
-    orc.asmc(P, opts, int(res["N"][k]), beta, eps, 1234, round_k=k + 1,
-             subset=np.arange(n0), traces=False)
+    go(n0)
     dt0 = time.perf_counter() - t0
     n1 = max(cores, int(n0 * budget_s / max(dt0, 1e-3)) // cores * cores)
     n1 = min(n1, int(res["N"][k]))
     t0 = time.perf_counter()
-    orc.asmc(P, opts, int(res["N"][k]), beta, eps, 1234, round_k=k + 1,
-             subset=np.arange(n1), traces=False)
+    go(n1)
     dt = time.perf_counter() - t0
+    what = (f"the last round (schedule, step sizes, trigger) at N={n1}" if resample else
+            f"{n1} particles x T={T} (last round's schedule) of the same workload")
     return {"value": n1 * T / dt, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n1} particles x T={T} (last round's schedule) of the same workload, "
-                      f"{dt:.1f} s"}
+            "sample": f"{what}, {dt:.1f} s"}
 
 
 def long_run_reference(oa, spec, res, N: int = 1 << 17, T: int = 4000) -> float:
@@ -169,10 +184,47 @@ def logz_error(oa, spec, args, last_logz, res) -> dict:
             "sd": float(np.std(vals, ddof=1)) if len(vals) > 1 else None}
 
 
+# ALU work models (lane-cycles per particle-step) of the extra workloads:
+#  * gradient (mixture d = 20, K = 4, MALA): forward about 1.1e3 (5 Philox
+#    blocks, 10 Box-Muller pairs, the mixture gradient) plus reverse about
+#    2.8e3 (recomputation and the Hessian-vector adjoint);
+#  * rejuvenation chains (Gaussian d = 10, RWMH): the sweep's 700 without the
+#    moment statistics (100) plus the test-function sums (20): 620;
+#  * a d-dimensional Gaussian RWMH problem of the batch: 140 per Philox block of
+#    normals (ceil(d/4)), 22 per Box-Muller pair (ceil(d/2)), 3 per coordinate
+#    for proposal and Delta log pi, 140 for the accept block, statistics and MH
+#    (700 at d = 10, the sweep's model).
+GRAD_WORK = 3.9e3
+REJUV_WORK = 620.0
+
+
+def gauss_work(d: int) -> float:
+    return 140.0 * -(-d // 4) + 22.0 * -(-d // 2) + 3.0 * d + 140.0
+
+
+def oracle_rate(fn, n_lo: int, cap: int, budget_s: float = 12.0):
+    """Times fn(n) for a calibrated n (particles) so that it takes about budget_s;
+    returns (n, seconds)."""
+    n0 = n_lo
+    t0 = time.perf_counter()
+    fn(n0)
+    dt0 = time.perf_counter() - t0
+    n1 = max(n_lo, min(cap, int(n0 * budget_s / max(dt0, 1e-3))))
+    t0 = time.perf_counter()
+    fn(n1)
+    return n1, time.perf_counter() - t0
+
+
 def extra_workload(args, oa, wl, torch) -> int:
     """The gradient (mixture d = 20, K = 4, N = 8192, T = 256 MALA, checkpoints
-    every 16) and the 256-problem batch (4 rounds: one hipGraph, or the same
-    problems one plain run after another)."""
+    every 16), final-iteration rejuvenation (N = 2^20 chains of 64 RWMH steps on
+    the d = 10 Gaussian target), and the 256-problem batch (4 rounds: one
+    hipGraph, or the same problems one plain run after another)."""
+    import oracle as orc
+
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cpu = roof = None
+    err = None
     if args.workload == "grad":
         w = wl.gmm4_d20()
         T = 256
@@ -182,6 +234,34 @@ def extra_workload(args, oa, wl, torch) -> int:
         run = lambda i: oa.logZ_backward(prob, w.N, beta, eps, args.seed + i)
         steps_per = float(w.N * T)
         name, cfg = w.name + "_gradient", {"N": w.N, "T": T, "d": w.d, "K": 4}
+        work, work_note = GRAD_WORK, "forward + reverse lane-cycles per particle-step"
+        kern = "k_oais_valu (forward) + k_merge_slots + k_adjoint_gmm + k_adjoint_reduce"
+
+        def cpu_fn(n):
+            P = orc.Problem(family=orc.FAM_GMM, d=w.d, means=w.params["means"],
+                            log_scales=w.params["log_scales"], ref_sigma2=w.ref_sigma2)
+            orc.logZ_grad(P, orc.Opts(move=orc.MOVE_MALA, state_f32=1, nthreads=cores), n, beta,
+                          eps, args.seed)
+        cpu_what = "forward-mode gradient of log Z_hat over {n} particles x T=256 (same schedule)"
+    elif args.workload == "rejuv":
+        w = wl.gaussian_d10(N=1 << 20, T=64)
+        T = 64
+        prob = oa.Problem.gauss(w.params["mu"], w.params["sigma2"], w.ref_sigma2)
+        beta = np.linspace(0, 1, T + 1)
+        fin = oa.asmc(prob, w.N, beta, w.eps0, args.seed, move="rwmh")
+        run = lambda i: oa.rejuvenate(prob, fin["lw"], fin["x"], T, w.eps0, args.seed + i)
+        steps_per = float(w.N * T)
+        name, cfg = w.name + "_rejuvenation", {"N": w.N, "T": T, "d": w.d}
+        work, work_note = REJUV_WORK, "lane-cycles per chain step"
+        kern = "k_rejuv"
+        lw_h, x_h = fin["lw"].cpu().numpy(), fin["x"].cpu().numpy().astype(np.float64)
+
+        def cpu_fn(n):
+            P = orc.Problem(family=orc.FAM_GAUSS, d=w.d, mu=w.params["mu"],
+                            sigma2=w.params["sigma2"], ref_sigma2=w.ref_sigma2)
+            orc.rejuvenate(P, orc.Opts(move=orc.MOVE_RWMH, state_f32=1, nthreads=cores),
+                           lw_h[:n], x_h[:n], T, w.eps0, args.seed)
+        cpu_what = "rejuvenation of the first {n} particles of the population, T=64 chain steps"
     else:
         specs = wl.batch_problems()
         probs = []
@@ -202,24 +282,84 @@ def extra_workload(args, oa, wl, torch) -> int:
             for it in items:
                 oa.run_batch([it], rounds, use_graph=False)
 
-        steps_per = float(sum(s["N"] * sum(min(max(1, s["T"] >> (rounds - 1)) << k, s["T"])
-                                           for k in range(rounds)) for s in specs))
+        Tks = [[min(max(1, s["T"] >> (rounds - 1)) << k, s["T"]) for k in range(rounds)]
+               for s in specs]
+        steps_per = float(sum(s["N"] * sum(tk) for s, tk in zip(specs, Tks)))
+        # roofline time of one batch: each problem at its own bound (ALU model
+        # for the Gaussian problems, FP32 MFMA for the contraction of the
+        # logistic-regression problems, T + 1 evaluations per pass)
+        roof_time = 0.0
+        for s, tk in zip(specs, Tks):
+            if s["family"] == "gauss":
+                roof_time += s["N"] * sum(tk) * gauss_work(s["d"]) / PEAK_LANE_CYCLES
+            else:
+                n = s["params"]["X"].shape[0]
+                roof_time += (s["N"] * sum(t + 1 for t in tk) * 4.0 * s["d"] * n /
+                              (PEAK_FP32_MFMA_TFLOPS * 1e12))
         name = "batch_256_problems" + ("_sequential" if sequential else "_graph")
-        cfg = {"problems": len(specs), "rounds": rounds}
+        cfg = {"problems": len(specs), "rounds": rounds,
+               "d_logreg_max": max(s["d"] for s in specs if s["family"] == "logreg")}
+        work = None
+        kern = "k_oais_valu_batch + k_oais_logreg_batch + k_round_merge + k_round_schedule"
+        g0 = next(i for i, s in enumerate(specs) if s["family"] == "gauss")
+        l0 = next(i for i, s in enumerate(specs) if s["family"] == "logreg")
+
+        def cpu_fn(n):
+            for j in (g0, l0):
+                s = specs[j]
+                if s["family"] == "gauss":
+                    P = orc.Problem(family=orc.FAM_GAUSS, d=s["d"], mu=s["params"]["mu"],
+                                    sigma2=s["params"]["sigma2"])
+                    mv = orc.MOVE_RWMH
+                else:
+                    P = orc.Problem(family=orc.FAM_LOGREG, d=s["d"], X=s["params"]["X"],
+                                    y=s["params"]["y"])
+                    mv = orc.MOVE_MALA
+                T = s["T"]
+                orc.asmc(P, orc.Opts(move=mv, state_f32=1, nthreads=cores), s["N"],
+                         np.linspace(0, 1, T + 1), s["eps0"], args.seed, subset=np.arange(n))
+        cpu_what = ("the last round of problems {g0} (Gaussian) and {l0} (logistic regression) "
+                    "on the first {n} particles each")
+        cpu_steps = lambda n: n * (specs[g0]["T"] + specs[l0]["T"])
+    oa.profile(True)
     for i in range(args.warmup):
         run(i)
     torch.cuda.synchronize()
+    oa.profile(True)  # totals cleared: the timed region only
     t0 = time.perf_counter()
     for i in range(args.steps):
         run(i)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    prof = oa.profile(False)
+    if work is not None and prof["kernel_ms"] > 0:
+        rate = prof["particle_steps"] / (prof["kernel_ms"] * 1e-3)
+        peak = PEAK_LANE_CYCLES / work
+        roof = {"bound": "alu", "achieved": rate, "peak": peak, "unit": "particle-steps/s",
+                "frac": rate / peak, "traffic": None, "kernel": kern,
+                "work_lane_cycles_per_particle_step": work, "work_note": work_note,
+                "avg_launch_ms": prof["kernel_ms"] / max(prof["launches"], 1),
+                "launches": prof["launches"]}
+    elif work is None:
+        t_batch = el / args.steps
+        roof = {"bound": "mixed (alu per Gaussian problem, mfma per logistic-regression problem)",
+                "achieved": steps_per / t_batch, "peak": steps_per / roof_time,
+                "unit": "particle-steps/s", "frac": roof_time / t_batch, "traffic": None,
+                "kernel": kern, "roofline_time_s": roof_time, "measured_time_s": t_batch}
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample ...")
+        cap = {"grad": 8192, "rejuv": 1 << 20}.get(args.workload, 4096)
+        n, dt = oracle_rate(cpu_fn, cores, cap)
+        steps = cpu_steps(n) if args.workload in ("batch", "batch_seq") else n * T
+        cpu = {"value": steps / dt, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+               "sample": cpu_what.format(n=n, g0=locals().get("g0"), l0=locals().get("l0")) +
+               f", {dt:.1f} s"}
     line = {"metric": METRIC, "value": steps_per * args.steps / el, "unit": "particle-steps/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32 state / f64 arithmetic and weights",
-            "data": "synthetic", "config": dict(workload=name, **cfg), "roofline": None,
-            "cpu_baseline": None}
+            "data": "synthetic", "config": dict(workload=name, **cfg), "logZ_error": err,
+            "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)
     return 0
 
@@ -230,7 +370,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="logreg",
-                    choices=sorted(WORKLOADS) + ["grad", "batch", "batch_seq"])
+                    choices=sorted(WORKLOADS) + ["grad", "rejuv", "batch", "batch_seq"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rmse-seeds", type=int, default=-1,
                     help="seeds for the log Z error (default per workload; 0 skips it)")
@@ -261,7 +401,7 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": nbytes, "repeats": 3}), flush=True)
         return 0
-    if args.workload in ("grad", "batch", "batch_seq"):
+    if args.workload in ("grad", "rejuv", "batch", "batch_seq"):
         return extra_workload(args, oa, wl, torch)
     spec = WORKLOADS[args.workload](oa, wl)
     w = spec.w
@@ -305,9 +445,9 @@ def main() -> int:
         log("log Z error over seeds (untimed) ...")
         err = logz_error(oa, spec, args, last_logz, res)
     cpu = None
-    if not args.no_cpu_baseline and w.family in ("logreg", "gauss"):
+    if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample ...")
-        cpu = cpu_baseline(w, res)
+        cpu = cpu_baseline(w, res, spec)
     line = {
         "metric": METRIC,
         "value": value,

@@ -148,6 +148,25 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
                uint32_t round_k, uint32_t problem_id, oasmc_round_out* out, void* stream);
 
 /*
+ * Final-iteration rejuvenation (Sec. "Computing expectations"): after a pass,
+ * resample its final population (log-weights lw[N], states x[N*d], both
+ * device, e.g. oasmc_round_out.lw / .x) with the systematic resampler and the
+ * event word of step T (stream 3, particle word 0xFFFFFFFF), then run N chains
+ * of T steps of the kernel's move at beta = 1 with step size eps_T, chain n
+ * from its resampled particle and drawing with counters (n, T + s), s = 1..T.
+ * The TN chain states estimate expectations under the target: host outputs
+ * mean[d] and second[d] (averages of x_i and x_i^2), *accept (fraction of
+ * accepted chain moves, may be NULL), and the chain end states x_out[N*d]
+ * (device, may be NULL).  Gaussian and mixture families; seed, round_k and
+ * problem_id those of the pass.  OASMC_ENONFINITE when no weight is finite.
+ * Synchronises `stream`.
+ */
+int oasmc_rejuvenate(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel* kernel,
+                     int64_t N, int32_t T, double eps_T, uint64_t seed, uint32_t round_k,
+                     uint32_t problem_id, const double* lw, const float* x, double* mean,
+                     double* second, double* accept, float* x_out, void* stream);
+
+/*
  * Alg. 3, OptimiseSchedule(T_new, B_T, g_hat) on the host:
  *   D_hat_t = log g_hat_{t,2} - 2 log g_hat_{t,1} + log g_hat_{t,0} (negative
  *   roundoff clamped to 0), Lambda_hat_t = sum_{s<=t} sqrt(D_hat_s), a monotone
@@ -236,6 +255,9 @@ typedef struct {
     double* eps;          /* [rounds][Tcap] */
     int32_t* n_resample;  /* [rounds] */
     int32_t rounds_done;  /* out: rounds whose outputs are valid (anytime property) */
+    double* rejuv_mean;   /* [rounds][d] or NULL: with rejuv_second, final-iteration */
+    double* rejuv_second; /* rejuvenation after every round (oasmc_rejuvenate with the
+                             round's last step size; Gaussian and mixture families) */
 } oasmc_run_out;
 
 /*

@@ -72,6 +72,7 @@ class _RunOut(C.Structure):
         ("T", C.c_void_p), ("beta", C.c_void_p), ("Lambda_hat", C.c_void_p),
         ("log_g", C.c_void_p), ("accept", C.c_void_p), ("eps", C.c_void_p),
         ("n_resample", C.c_void_p), ("rounds_done", C.c_int32),
+        ("rejuv_mean", C.c_void_p), ("rejuv_second", C.c_void_p),
     ]
 
 
@@ -111,12 +112,15 @@ def _load():
     L.oasmc_run_batch.argtypes = [vp, C.POINTER(_BatchProblem), C.c_int32, C.c_int32, C.c_int32,
                                   C.POINTER(_BatchOut), vp]
     L.oasmc_logreg_eval.argtypes = [vp, C.POINTER(_Problem), C.c_int64, vp, vp, vp, vp]
+    L.oasmc_rejuvenate.argtypes = [vp, C.POINTER(_Problem), C.POINTER(_Kernel), C.c_int64,
+                                   C.c_int32, C.c_double, C.c_uint64, C.c_uint32, C.c_uint32, vp,
+                                   vp, vp, vp, vp, vp, vp]
     L.oasmc_profile.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for f in ("oasmc_handle_create", "oasmc_handle_destroy", "oasmc_asmc", "oasmc_adapt_schedule",
               "oasmc_dar_times",
               "oasmc_run", "oasmc_resample", "oasmc_resample_noalloc", "oasmc_philox", "oasmc_logreg_eval",
-              "oasmc_profile", "oasmc_logZ_backward", "oasmc_run_batch"):
+              "oasmc_profile", "oasmc_logZ_backward", "oasmc_run_batch", "oasmc_rejuvenate"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -274,10 +278,11 @@ def run(problem: Problem, N1: int, rounds: int, seed: int, problem_id: int = 0, 
         budget="double_n", T1: int = 64, T_max: int = 0, N_max: int = 1 << 40,
         eps0: float = 0.1, eps_adapt: bool = False, eps_kappa: float = 0.0,
         accept_target: float = 0.574, interp: int = 0, Tcap: Optional[int] = None,
-        slots: int = 0, dar: bool = False) -> dict:
+        slots: int = 0, dar: bool = False, rejuvenate: bool = False) -> dict:
     """Alg. 2, OASMC: `rounds` rounds with Budget and OptimiseSchedule between them.
     ``dar`` (with ``resample_``): rounds after the first resample at the DAR times
-    predicted from the previous round."""
+    predicted from the previous round.  ``rejuvenate``: final-iteration rejuvenation
+    after every round (``rejuv_mean``, ``rejuv_second`` [rounds, d])."""
     dev = problem.device
     b = BUDGETS[budget] if isinstance(budget, str) else int(budget)
     if Tcap is None:
@@ -292,8 +297,11 @@ def run(problem: Problem, N1: int, rounds: int, seed: int, problem_id: int = 0, 
     acc = np.zeros((R, Tcap))
     eps = np.zeros((R, Tcap))
     nres = np.zeros(R, dtype=np.int32)
+    rj_m = np.zeros((R, problem.d)) if rejuvenate else None
+    rj_s = np.zeros((R, problem.d)) if rejuvenate else None
     out = _RunOut(R, Tcap, _np_ptr(logZ), _np_ptr(Ns), _np_ptr(Ts), _np_ptr(beta), _np_ptr(lam),
-                  _np_ptr(lg), _np_ptr(acc), _np_ptr(eps), _np_ptr(nres), 0)
+                  _np_ptr(lg), _np_ptr(acc), _np_ptr(eps), _np_ptr(nres), 0, _np_ptr(rj_m),
+                  _np_ptr(rj_s))
     ro = _RunOpts(b, int(T1), int(T_max), int(N_max), int(bool(eps_adapt)), float(eps0),
                   float(eps_kappa), float(accept_target), int(interp), int(bool(dar)))
     P = problem.c()
@@ -302,8 +310,39 @@ def run(problem: Problem, N1: int, rounds: int, seed: int, problem_id: int = 0, 
                              int(N1), int(seed) & (2 ** 64 - 1), int(problem_id), C.byref(out),
                              _stream(dev))
     _check(code)
-    return dict(logZ=logZ, N=Ns, T=Ts, beta=beta, Lambda=lam, log_g=lg, acc=acc, eps=eps,
-                n_resample=nres, rounds_done=out.rounds_done)
+    r = dict(logZ=logZ, N=Ns, T=Ts, beta=beta, Lambda=lam, log_g=lg, acc=acc, eps=eps,
+             n_resample=nres, rounds_done=out.rounds_done)
+    if rejuvenate:
+        r["rejuv_mean"], r["rejuv_second"] = rj_m, rj_s
+    return r
+
+
+def rejuvenate(problem: Problem, lw: torch.Tensor, x: torch.Tensor, T: int, eps_T: float,
+               seed: int, round_k: int = 1, problem_id: int = 0, move="rwmh", leapfrog: int = 5,
+               return_states: bool = False) -> dict:
+    """Final-iteration rejuvenation of a pass's final population (device lw [N],
+    x [N, d]): N chains of T steps at beta = 1; returns the averages of x and x^2
+    over the TN chain states and the accepted fraction (and the end states)."""
+    dev = problem.device
+    lw = lw.to(device=dev, dtype=torch.float64).contiguous()
+    x = x.to(device=dev, dtype=torch.float32).contiguous()
+    N = int(x.shape[0])
+    mean, second = np.zeros(problem.d), np.zeros(problem.d)
+    acc = C.c_double(0.0)
+    xo = torch.empty_like(x) if return_states else None
+    P = problem.c()
+    K = _kernel(move, leapfrog, False, "ess", 0.5)
+    _check(_load().oasmc_rejuvenate(_handle(dev.index or 0), C.byref(P), C.byref(K), N, int(T),
+                                    float(eps_T), int(seed) & (2 ** 64 - 1), int(round_k),
+                                    int(problem_id), C.c_void_p(lw.data_ptr()),
+                                    C.c_void_p(x.data_ptr()), _np_ptr(mean), _np_ptr(second),
+                                    C.c_void_p(C.addressof(acc)),
+                                    None if xo is None else C.c_void_p(xo.data_ptr()),
+                                    _stream(dev)))
+    out = dict(mean=mean, second=second, accept=acc.value)
+    if return_states:
+        out["x"] = xo
+    return out
 
 
 def dar_times(beta, log_g, beta_new, nu: float, interp: int = 0):

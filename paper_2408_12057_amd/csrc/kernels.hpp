@@ -141,6 +141,19 @@ struct AsmcState {
     uint64_t* btot;    // [nblocks] inclusive block totals after the scan
 };
 
+// Final-iteration rejuvenation (Sec. "Computing expectations"): N chains of
+// a.T steps at beta = 1 with step size eps, chain n starting from particle
+// anc[n] of the final population x_in; per-tile sums of x_i, x_i^2 over the
+// chain states and the accepted count in tsum [ntiles][2 d + 1].
+struct RejuvArgs {
+    SweepArgs a;          // target, move, leapfrog, N, T = chain length, key, ntiles
+    double eps;
+    const float* x_in;    // [N*d]
+    const int32_t* anc;   // [N]
+    double* tsum;         // [ntiles][2 d + 1]
+    float* x_out;         // [N*d] chain end states, or null
+};
+
 // Validated launch configuration of a VALU sweep.
 struct ValuShape {
     int lpp;  // lanes per particle
@@ -181,6 +194,16 @@ hipError_t launch_asmc_init(const SweepArgs& a, const ValuShape& s, const AsmcSt
 hipError_t launch_asmc_step(const SweepArgs& a, const ValuShape& s, const AsmcState& z, int t,
                             int trigger, double nu, hipStream_t st);
 hipError_t launch_resample_step(const SweepArgs& a, const AsmcState& z, int t, hipStream_t st);
+// Rejuvenation: chains and the per-tile sums, then the fixed-order reduction
+// of the tile sums into out [2 d + 1] (averages over N T samples, accepted fraction).
+hipError_t launch_rejuv(const RejuvArgs& R, const ValuShape& s, hipStream_t st);
+hipError_t launch_rejuv_reduce(const double* tsum, int64_t ntiles, int d, double samples,
+                               double* out, hipStream_t st);
+// Systematic resampling of lw[N] for the event word of step t (particle word
+// 0xFFFFFFFF, stream 3) of `key`: ancestors anc[N] (all -1 without a finite weight).
+hipError_t launch_resample_event(int64_t N, const double* lw, const RngKey& key, uint32_t t,
+                                 int32_t* anc, uint64_t* C, uint64_t* btot, double* scal,
+                                 hipStream_t st);
 // Merge of a segment's slot partials (steps t_begin+1 .. t_end and the segment's
 // final log-weights in entry T): moments, accepted counts, the log Z_hat factor
 // and, when t_end < T, the resampling event (flag, largest log w, uniform word).

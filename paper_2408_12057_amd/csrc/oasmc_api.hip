@@ -111,7 +111,8 @@ namespace {
 enum BufId {
     B_BETA, B_EPS, B_PART, B_LOGG, B_ACC, B_SCAL, B_X, B_X2, B_ELL, B_ELL2, B_LW, B_ACCW,
     B_TPART, B_NRES, B_ESS, B_RES, B_C, B_BTOT, B_LWO, B_XO, B_LOGREG, B_CKPT, B_SEG, B_ABITS,
-    B_GPART, B_GRAD, B_DEVRUN, B_DEVDESC, B_G, B_G2, B_BLK, B_COUNT
+    B_GPART, B_GRAD, B_DEVRUN, B_DEVDESC, B_G, B_G2, B_BLK, B_RJ_ANC, B_RJ_SUM, B_RJ_OUT,
+    B_RJ_LW, B_RJ_X, B_COUNT
 };
 
 template <typename T>
@@ -1022,6 +1023,76 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
     return OASMC_OK;
 }
 
+int oasmc_rejuvenate(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel* kernel,
+                     int64_t N, int32_t T, double eps_T, uint64_t seed, uint32_t round_k,
+                     uint32_t problem_id, const double* lw, const float* x, double* mean,
+                     double* second, double* accept, float* x_out, void* stream)
+{
+    if (!h) return fail(OASMC_EINVAL, "handle is NULL");
+    int s = check_problem(problem, kernel);
+    if (s) return s;
+    if (problem->family == OASMC_LOGREG)
+        return fail(OASMC_EUNSUPPORTED, "rejuvenation is built for the Gaussian and mixture families");
+    if (N < 1 || N > ((int64_t)1 << 30)) return fail(OASMC_EINVAL, "N must lie in [1, 2^30]");
+    if (T < 1) return fail(OASMC_EINVAL, "T must be >= 1");
+    if (!(eps_T > 0.0) || !std::isfinite(eps_T)) return fail(OASMC_EINVAL, "eps_T must be positive");
+    if (!lw || !x || !mean || !second) return fail(OASMC_EINVAL, "NULL argument");
+    HIP_TRY(hipSetDevice(h->device));
+    hipStream_t st = (hipStream_t)stream;
+    ValuShape shape{};
+    if (!valu_shape(problem->d, N, &shape))
+        return fail(OASMC_EUNSUPPORTED, "no kernel shape for d=%d", problem->d);
+    const int d = problem->d;
+    RejuvArgs R{};
+    R.a.tg = target_dev(problem);
+    R.a.move = kernel->move;
+    R.a.leapfrog = kernel->leapfrog;
+    R.a.N = N;
+    R.a.T = T;
+    R.a.key.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    R.a.key.k1 = (uint32_t)(seed >> 32);
+    R.a.key.c2 = (round_k & 0xFFFFu) | (problem_id << 16);
+    R.a.ntiles = valu_tiles(N, shape);
+    R.eps = eps_T;
+    R.x_in = x;
+    R.x_out = x_out;
+    int32_t* anc;
+    double *tsum, *res, *scal;
+    uint64_t *C, *btot;
+    HIP_TRY(wget(h, B_RJ_ANC, N, &anc));
+    HIP_TRY(wget(h, B_RJ_SUM, (size_t)R.a.ntiles * (2 * d + 1), &tsum));
+    HIP_TRY(wget(h, B_RJ_OUT, 2 * (size_t)d + 1, &res));
+    HIP_TRY(wget(h, B_SCAL, 8, &scal));
+    HIP_TRY(wget(h, B_C, N, &C));
+    HIP_TRY(wget(h, B_BTOT, resample_blocks(N), &btot));
+    R.anc = anc;
+    R.tsum = tsum;
+    HIP_TRY(launch_resample_event(N, lw, R.a.key, (uint32_t)T, anc, C, btot, scal, st));
+    double flag = 0.0;
+    HIP_TRY(hipMemcpyAsync(&flag, scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (flag == 0.0) return fail(OASMC_ENONFINITE, "no finite final weight to resample");
+    if (h->prof) HIP_TRY(hipEventRecord(h->ev0, st));
+    HIP_TRY(launch_rejuv(R, shape, st));
+    if (h->prof) HIP_TRY(hipEventRecord(h->ev1, st));
+    HIP_TRY(launch_rejuv_reduce(tsum, R.a.ntiles, d, (double)N * (double)T, res, st));
+    std::vector<double> hres(2 * (size_t)d + 1);
+    HIP_TRY(hipMemcpyAsync(hres.data(), res, sizeof(double) * hres.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h->prof) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+        h->prof_ms += ms;
+        h->prof_launches += 1;
+        h->prof_steps += (double)N * T;
+    }
+    std::copy(hres.begin(), hres.begin() + d, mean);
+    std::copy(hres.begin() + d, hres.begin() + 2 * d, second);
+    if (accept) *accept = hres[2 * d];
+    g_err.clear();
+    return OASMC_OK;
+}
+
 int oasmc_logreg_eval(oasmc_handle* h, const oasmc_problem* problem, int64_t N,
                       const float* theta, double* ell, float* grad, void* stream)
 {
@@ -1108,6 +1179,7 @@ int oasmc_logZ_backward(oasmc_handle* h, const oasmc_problem* problem, const oas
     a.ntiles = ntiles;
     // forward: the AIS pass with checkpoints and decisions recorded
     const int grid_waves = (int)std::min<int64_t>(S, (int64_t)h->cus * 8);
+    if (h->prof) HIP_TRY(hipEventRecord(h->ev0, st));
     HIP_TRY(launch_oais_valu(a, shape, grid_waves, st));
     HIP_TRY(launch_merge_slots(part, S, T, N, dlogg, dacc, dscal, st));
     // reverse
@@ -1122,10 +1194,19 @@ int oasmc_logZ_backward(oasmc_handle* h, const oasmc_problem* problem, const oas
     A.nwaves = ntiles;
     HIP_TRY(launch_adjoint(A, ashape, kb, st));
     HIP_TRY(launch_adjoint_reduce(gpart, ntiles, np, dgrad, st));
+    if (h->prof) HIP_TRY(hipEventRecord(h->ev1, st));
     double lz = 0.0;
     HIP_TRY(hipMemcpyAsync(&lz, dscal, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(grad, dgrad, sizeof(double) * np, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    if (h->prof) {
+        // forward pass, merge, reverse pass and reduction timed as one launch
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+        h->prof_ms += ms;
+        h->prof_launches += 1;
+        h->prof_steps += (double)N * T;
+    }
     *logZ = lz;
     if (!std::isfinite(lz)) return fail(OASMC_ENONFINITE, "log Z_hat is not finite");
     g_err.clear();
@@ -1246,7 +1327,10 @@ extern "C" int oasmc_run(oasmc_handle* h, const oasmc_problem* problem, const oa
         return fail(OASMC_EINVAL, "every oasmc_run_out array is required");
     const int Tcap = out->Tcap;
     out->rounds_done = 0;
-    if (!kernel->resample &&
+    const bool rejuv = out->rejuv_mean && out->rejuv_second;
+    if (rejuv && problem->family == OASMC_LOGREG)
+        return fail(OASMC_EUNSUPPORTED, "rejuvenation is built for the Gaussian and mixture families");
+    if (!kernel->resample && !rejuv &&
         (opts->budget == OASMC_BUDGET_FIXED || opts->budget == OASMC_BUDGET_DOUBLE_T)) {
         DevProblem q{};
         q.prob = *problem;
@@ -1331,10 +1415,22 @@ extern "C" int oasmc_run(oasmc_handle* h, const oasmc_problem* problem, const oa
         oasmc_round_out ro{};
         ro.log_g = lg.data();
         ro.accept = acc.data();
+        if (rejuv) {
+            HIP_TRY(wget(h, B_RJ_LW, N, &ro.lw));
+            HIP_TRY(wget(h, B_RJ_X, (size_t)N * problem->d, &ro.x));
+        }
         status = oasmc_asmc(h, problem, dar ? &kdar : kernel, N, T, beta.data(), eps.data(), seed,
                             (uint32_t)k, problem_id, &ro, stream);
         if (status != OASMC_OK && status != OASMC_ENONFINITE) break;
         const int r = k - 1;
+        if (rejuv) {
+            const int s4 = oasmc_rejuvenate(h, problem, kernel, N, T, eps[T - 1], seed, (uint32_t)k,
+                                            problem_id, ro.lw, ro.x,
+                                            out->rejuv_mean + (size_t)r * problem->d,
+                                            out->rejuv_second + (size_t)r * problem->d, nullptr,
+                                            nullptr, stream);
+            if (status == OASMC_OK && s4 != OASMC_OK) status = s4;
+        }
         out->logZ[r] = ro.logZ;
         out->N[r] = N;
         out->T[r] = T;

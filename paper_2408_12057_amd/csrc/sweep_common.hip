@@ -491,19 +491,72 @@ int64_t valu_tiles(int64_t N, const ValuShape& s)
 
 template <int FAM, int MOVE>
 hipError_t valu_dispatch(int what, const SweepArgs& a, const ValuShape& s, int gw,
-                         const AsmcState* z, int t, hipStream_t st, const ValuBatch* b);
+                         const AsmcState* z, int t, hipStream_t st, const ValuBatch* b,
+                         const RejuvArgs* rj);
 static hipError_t dispatch_all(int what, const SweepArgs& a, const ValuShape& s, int gw,
                                const AsmcState* z, int t, hipStream_t st,
-                               const ValuBatch* b = nullptr)
+                               const ValuBatch* b = nullptr, const RejuvArgs* rj = nullptr)
 {
     const int fam = a.tg.family, mv = a.move;
-    if (fam == kGauss && mv == kRwmh) return valu_dispatch<kGauss, kRwmh>(what, a, s, gw, z, t, st, b);
-    if (fam == kGauss && mv == kMala) return valu_dispatch<kGauss, kMala>(what, a, s, gw, z, t, st, b);
-    if (fam == kGauss && mv == kHmc) return valu_dispatch<kGauss, kHmc>(what, a, s, gw, z, t, st, b);
-    if (fam == kGmm && mv == kRwmh) return valu_dispatch<kGmm, kRwmh>(what, a, s, gw, z, t, st, b);
-    if (fam == kGmm && mv == kMala) return valu_dispatch<kGmm, kMala>(what, a, s, gw, z, t, st, b);
-    if (fam == kGmm && mv == kHmc) return valu_dispatch<kGmm, kHmc>(what, a, s, gw, z, t, st, b);
+#define OASMC_FM(F, M) \
+    if (fam == F && mv == M) return valu_dispatch<F, M>(what, a, s, gw, z, t, st, b, rj);
+    OASMC_FM(kGauss, kRwmh)
+    OASMC_FM(kGauss, kMala)
+    OASMC_FM(kGauss, kHmc)
+    OASMC_FM(kGmm, kRwmh)
+    OASMC_FM(kGmm, kMala)
+    OASMC_FM(kGmm, kHmc)
+#undef OASMC_FM
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_rejuv(const RejuvArgs& R, const ValuShape& s, hipStream_t st)
+{
+    return dispatch_all(4, R.a, s, 0, nullptr, 0, st, nullptr, &R);
+}
+
+// Column b of the tile sums over tiles in a fixed order (one wave per column).
+__global__ void __launch_bounds__(kWave) k_rejuv_reduce(const double* __restrict__ tsum,
+                                                         int64_t ntiles, int d, double samples,
+                                                         double* out)
+{
+    const int b = blockIdx.x;
+    const int w = 2 * d + 1;
+    double v = 0.0;
+    for (int64_t k = threadIdx.x; k < ntiles; k += kWave) v += tsum[(size_t)k * w + b];
+    v = wave_sum(v);
+    if (threadIdx.x == 0) out[b] = v / samples;
+}
+
+hipError_t launch_rejuv_reduce(const double* tsum, int64_t ntiles, int d, double samples,
+                               double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rejuv_reduce, dim3(2 * d + 1), dim3(kWave), 0, st, tsum, ntiles, d,
+                       samples, out);
+    return hipGetLastError();
+}
+
+// The uniform word of the resampling event at step t (particle word 0xFFFFFFFF).
+__global__ void k_event_word(RngKey key, uint32_t t, double* scal)
+{
+    const uint4 wd = draw_block(key, 0xFFFFFFFFu, t, kStreamResample, 0u, 0u);
+    scal[3] = (double)wd.x;
+}
+
+hipError_t launch_resample_event(int64_t N, const double* lw, const RngKey& key, uint32_t t,
+                                 int32_t* anc, uint64_t* C, uint64_t* btot, double* scal,
+                                 hipStream_t st)
+{
+    const int64_t nb = resample_blocks(N);
+    hipLaunchKernelGGL(k_rs_prepare, dim3(1), dim3(256), 0, st, N, lw, 0u, scal);
+    hipLaunchKernelGGL(k_event_word, dim3(1), dim3(1), 0, st, key, t, scal);
+    hipLaunchKernelGGL(k_rs_quant_scan, dim3((unsigned)nb), dim3(kScanThreads), 0, st, N, lw,
+                       (const double*)scal, C, btot, (unsigned*)nullptr);
+    hipLaunchKernelGGL(k_rs_scan_blocks, dim3(1), dim3(kScanThreads), 0, st, nb,
+                       (const double*)scal, btot);
+    hipLaunchKernelGGL(k_rs_ancestors, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N,
+                       (const double*)scal, (const uint64_t*)C, (const uint64_t*)btot, nb, anc);
+    return hipGetLastError();
 }
 
 hipError_t launch_oais_valu_batch(int family, int move, const ValuShape& s, const ValuBatch& b,

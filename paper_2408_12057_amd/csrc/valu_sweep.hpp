@@ -792,6 +792,92 @@ __global__ void __launch_bounds__(256, MinWaves<DPL>::value)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Final-iteration rejuvenation (Sec. "Computing expectations"): after the
+// last annealing step the population is resampled and N chains run T steps of
+// the forward kernel at beta = 1 (step size eps_T), chain n from particle
+// anc[n]; its states feed the expectations.  One wave per tile as in the
+// sweep; the chain draws with counters (n, T + s), s = 1..T.  Sums of x_i and
+// x_i^2 over the chain are kept per lane (in step order), summed over the
+// wave's particles by an xor butterfly and written per tile.
+// ---------------------------------------------------------------------------
+template <int FAM, int MOVE, int LPP, int DPL>
+__global__ void __launch_bounds__(256) k_rejuv(RejuvArgs R)
+{
+    constexpr int P = kWave / LPP;
+    extern __shared__ __align__(16) char sh_dyn[];
+    const SweepArgs& a = R.a;
+    const ParView pv = stage_params_lanes<LPP, DPL>(a.tg, sh_dyn);
+    const Consts c = make_consts(a.tg);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int r = lane % LPP, pl = lane / LPP;
+    const int64_t tile =
+        (int64_t)blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (tile >= a.ntiles) return;  // whole wave leaves together
+    const int64_t n64 = tile * P + pl;
+    const bool valid = n64 < a.N;
+    const int d = a.tg.d;
+    // the host checked the event, so every ancestor is a particle index
+    const int64_t src = R.anc[valid ? n64 : a.N - 1];
+    float x[DPL];
+    double g[DPL];
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+        const int i = r * DPL + j;
+        x[j] = (i < d) ? R.x_in[(size_t)src * d + i] : 0.f;
+        g[j] = 0.0;
+    }
+    double ell = (MOVE != kRwmh) ? Particle<FAM, LPP, DPL>::template eval<true>(a.tg, c, pv, r, x, g)
+                                 : Particle<FAM, LPP, DPL>::template eval<false>(a.tg, c, pv, r, x, g);
+    double s1[DPL], s2[DPL];
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) s1[j] = s2[j] = 0.0;
+    uint32_t na = 0;
+    for (int s = 1; s <= a.T; ++s) {
+        const bool acc = Particle<FAM, LPP, DPL>::template move<MOVE>(
+            a.tg, c, pv, a.key, (uint32_t)n64, (uint32_t)(a.T + s), r, a.leapfrog, 1.0, R.eps, x,
+            ell, g);
+        na += acc ? 1u : 0u;
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) {
+            const double v = (double)x[j];
+            s1[j] += v;
+            s2[j] += v * v;
+        }
+    }
+    if (valid && R.x_out) {
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) {
+            const int i = r * DPL + j;
+            if (i < d) R.x_out[(size_t)n64 * d + i] = x[j];
+        }
+    }
+    // sums over the wave's particles (lanes r, r + LPP, ... hold the same coordinates)
+    double cnt = (valid && r == 0) ? (double)na : 0.0;
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+        if (!valid) s1[j] = s2[j] = 0.0;
+#pragma unroll
+        for (int o = LPP; o < kWave; o <<= 1) {
+            s1[j] += __shfl_xor(s1[j], o, kWave);
+            s2[j] += __shfl_xor(s2[j], o, kWave);
+        }
+    }
+    cnt = wave_sum(cnt);
+    double* out = R.tsum + (size_t)tile * (2 * d + 1);
+    if (pl == 0) {
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) {
+            const int i = r * DPL + j;
+            if (i < d) {
+                out[i] = s1[j];
+                out[d + i] = s2[j];
+            }
+        }
+        if (r == 0) out[2 * d] = cnt;
+    }
+}
+
 template <int FAM, int MOVE, int LPP, int DPL>
 struct Launch {
     static hipError_t oais(const SweepArgs& a, int grid_waves, hipStream_t st)
@@ -816,6 +902,13 @@ struct Launch {
                            params_bytes_lanes(a.tg, LPP, DPL), st, a, z);
         return hipGetLastError();
     }
+    static hipError_t rejuv(const RejuvArgs& R, hipStream_t st)
+    {
+        const int64_t blocks = (R.a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+        hipLaunchKernelGGL((k_rejuv<FAM, MOVE, LPP, DPL>), dim3((unsigned)blocks), dim3(256),
+                           params_bytes_lanes(R.a.tg, LPP, DPL), st, R);
+        return hipGetLastError();
+    }
     static hipError_t step(const SweepArgs& a, const AsmcState& z, int t, hipStream_t st)
     {
         const int64_t blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -827,7 +920,8 @@ struct Launch {
 
 template <int FAM, int MOVE>
 hipError_t valu_dispatch(int what, const SweepArgs& a, const ValuShape& s, int gw,
-                           const AsmcState* z, int t, hipStream_t st, const ValuBatch* b)
+                           const AsmcState* z, int t, hipStream_t st, const ValuBatch* b,
+                           const RejuvArgs* rj)
 {
 #define OASMC_CASE(L, D)                                                     \
     if (s.lpp == L && s.dpl == D) {                                          \
@@ -836,6 +930,7 @@ hipError_t valu_dispatch(int what, const SweepArgs& a, const ValuShape& s, int g
         if (what == 3)                                                       \
             return Launch<FAM, MOVE, L, D>::batch(b->args, b->views, b->items, \
                                                   b->nitems, gw, st);        \
+        if (what == 4) return Launch<FAM, MOVE, L, D>::rejuv(*rj, st);       \
         return Launch<FAM, MOVE, L, D>::step(a, *z, t, st);                  \
     }
     OASMC_CASE(1, 4)
