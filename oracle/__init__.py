@@ -24,8 +24,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oasmc_oracle.c")
 _LIB = os.path.join(_HERE, "liboasmc_oracle.so")
 
-FAM_GAUSS, FAM_LOGREG, FAM_GMM = 1, 2, 3
-MOVE_RWMH, MOVE_MALA, MOVE_HMC, MOVE_EXACT, MOVE_IDENTITY = 1, 2, 3, 4, 5
+FAM_GAUSS, FAM_LOGREG, FAM_GMM, FAM_UNID = 1, 2, 3, 4
+MOVE_RWMH, MOVE_MALA, MOVE_HMC, MOVE_EXACT, MOVE_IDENTITY, MOVE_RWMH3 = 1, 2, 3, 4, 5, 6
 
 
 def build(force: bool = True) -> str:
@@ -59,6 +59,7 @@ class _Problem(C.Structure):
         ("X", C.c_void_p), ("y", C.c_void_p), ("n", C.c_int),
         ("K", C.c_int), ("means", C.c_void_p), ("log_scales", C.c_void_p),
         ("ref_mean", C.c_void_p), ("ref_sigma2", C.c_double),
+        ("binom_n", C.c_double), ("binom_k", C.c_double), ("box", C.c_double),
     ]
 
 
@@ -122,6 +123,10 @@ def _declare(L):
                                  C.c_double, C.c_uint64, C.c_uint32, C.c_uint32, _dp, _dp, _dp,
                                  _dp, _dp, _dp]
     L.orc_rejuvenate.restype = C.c_int
+    L.orc_zja.argtypes = [C.POINTER(_Problem), C.POINTER(_Opts), C.c_int64, C.c_double, C.c_int,
+                          C.c_int, C.c_double, C.c_uint64, C.c_uint32, C.c_uint32, _dp,
+                          C.POINTER(C.c_int), _dp, _dp, _dp, _dp]
+    L.orc_zja.restype = C.c_int
 
 
 def _f64(a) -> np.ndarray:
@@ -149,6 +154,9 @@ class Problem:
     log_scales: Optional[np.ndarray] = None
     ref_mean: Optional[np.ndarray] = None
     ref_sigma2: float = 1.0
+    binom_n: float = 0.0   # FAM_UNID: Binomial(k | n, x y) likelihood, uniform (0, box)^2 reference
+    binom_k: float = 0.0
+    box: float = 10.0
     _keep: list = field(default_factory=list, repr=False)
 
     def c(self) -> _Problem:
@@ -174,6 +182,7 @@ class Problem:
         P.log_scales = arr(self.log_scales)
         P.ref_mean = arr(self.ref_mean)
         P.ref_sigma2 = float(self.ref_sigma2)
+        P.binom_n, P.binom_k, P.box = float(self.binom_n), float(self.binom_k), float(self.box)
         self._keep = keep
         return P
 
@@ -298,6 +307,26 @@ def rejuvenate(problem: Problem, opts: Opts, lw, x, T: int, eps_T: float, seed: 
     if want_states:
         out["x"] = xo
     return out
+
+
+def zja(problem: Problem, opts: Opts, N: int, rho: float, Tmax: int, eps: float, seed: int,
+        iters: int = 40, round_k: int = 1, problem_id: int = 0) -> dict:
+    """ZJA online CESS-adaptive AIS: beta [T+1], T, log_g [3, T], logZ, lw [N], x [N, d]."""
+    d = problem.d
+    beta = np.zeros(Tmax + 1)
+    lg = np.zeros(3 * Tmax)
+    lw = np.zeros(N)
+    x = np.zeros(N * d)
+    T = C.c_int(0)
+    lz = C.c_double(0.0)
+    P = problem.c()
+    O = opts.c()
+    st = lib().orc_zja(C.byref(P), C.byref(O), N, float(rho), Tmax, iters, float(eps), seed,
+                       round_k, problem_id, _ptr(beta), C.byref(T), _ptr(lg), C.cast(C.byref(lz), _dp),
+                       _ptr(lw), _ptr(x))
+    Tv = T.value
+    return dict(status=st, T=Tv, beta=beta[:Tv + 1], log_g=lg.reshape(3, Tmax)[:, :Tv],
+                logZ=lz.value, lw=lw, x=x.reshape(N, d))
 
 
 def ell(problem: Problem, x) -> tuple:

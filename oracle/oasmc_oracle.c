@@ -166,8 +166,13 @@ double orc_uniform(uint64_t seed, uint32_t round_k, uint32_t problem, uint32_t n
 /* ------------------------------------------------------------------------ */
 /* Targets, reference, annealing path.                                       */
 /* ------------------------------------------------------------------------ */
-enum { FAM_GAUSS = 1, FAM_LOGREG = 2, FAM_GMM = 3 };
-enum { MOVE_RWMH = 1, MOVE_MALA = 2, MOVE_HMC = 3, MOVE_EXACT = 4, MOVE_IDENTITY = 5 };
+enum { FAM_GAUSS = 1, FAM_LOGREG = 2, FAM_GMM = 3, FAM_UNID = 4 };
+enum { MOVE_RWMH = 1, MOVE_MALA = 2, MOVE_HMC = 3, MOVE_EXACT = 4, MOVE_IDENTITY = 5,
+       MOVE_RWMH3 = 6 };
+/* MOVE_RWMH3: the alternation of three random-walk MH steps with proposal
+ * standard deviations eps * (0.1, 1, 10) that the paper's GPU experiments use
+ * (appendix "GPU implementation"), applied as one kernel per annealing step
+ * (substeps 0, 1, 2 of the counter layout). */
 /* MOVE_EXACT (Gaussian family only) draws X ~ pi_beta exactly, the idealised
  * kernel under which the efficient-local-exploration assumption holds;
  * MOVE_IDENTITY leaves X unchanged (AIS then reduces to importance sampling
@@ -191,6 +196,11 @@ typedef struct {
     /* reference eta = N(ref_mean, ref_sigma2 I), normalised (Z_0 = 1) */
     const double* ref_mean;   /* may be NULL: zero mean */
     double ref_sigma2;
+    /* FAM_UNID (unidentifiable product parameterisation, d = 2): eta uniform on
+     * (0, box)^2; likelihood Binomial(k | binom_n, x y), zero unless 0 < x y < 1;
+     * ell is the log-likelihood ratio against its maximum at x y = k / n:
+     *   ell = k log(u / p) + (n - k) log((1 - u) / (1 - p)),  u = x y, p = k / n */
+    double binom_n, binom_k, box;
 } orc_problem;
 
 static double ref_mean_at(const orc_problem* P, int i)
@@ -198,10 +208,18 @@ static double ref_mean_at(const orc_problem* P, int i)
     return P->ref_mean ? P->ref_mean[i] : 0.0;
 }
 
+static int in_box(const orc_problem* P, const double* x)
+{
+    for (int i = 0; i < P->d; ++i)
+        if (!(x[i] > 0.0 && x[i] < P->box)) return 0;
+    return 1;
+}
+
 /* log eta(x), the normalised reference density. */
 static double log_eta(const orc_problem* P, const double* x)
 {
     const double log_two_pi = 1.8378770664093454835606594728112;
+    if (P->family == FAM_UNID) return in_box(P, x) ? -P->d * log(P->box) : -INFINITY;
     double ss = 0.0;
     for (int i = 0; i < P->d; ++i) {
         double r = x[i] - ref_mean_at(P, i);
@@ -264,6 +282,14 @@ static double log_gamma_closed(const orc_problem* P, const double* x)
  */
 static double ell(const orc_problem* P, const double* x)
 {
+    if (P->family == FAM_UNID) {
+        double u = x[0] * x[1];
+        if (!in_box(P, x) || !(u > 0.0 && u < 1.0)) return -INFINITY;
+        double n = P->binom_n, k = P->binom_k, p = k / n;
+        /* log(u/p) and log((1-u)/(1-p)) as log1p of their small offsets near
+         * the maximum, where the two large terms cancel */
+        return k * log1p((u - p) / p) + (n - k) * log1p(-(u - p) / (1.0 - p));
+    }
     if (P->family == FAM_LOGREG) {
         double ll = 0.0;
         for (int i = 0; i < P->n; ++i) {
@@ -401,6 +427,27 @@ static int mh_step(const orc_problem* P, const orc_opts* O, const rng_key* K, ui
     double log_alpha;
     double ell_p = 0.0;
 
+    if (O->move == MOVE_RWMH3) {
+        static const double scale[3] = {0.1, 1.0, 10.0};
+        int any = 0;
+        double best = INFINITY;
+        for (int j = 0; j < 3; ++j) {
+            draw_normals(K, n, t, STREAM_MOVE, (uint32_t)j, d, xi);
+            for (int i = 0; i < d; ++i)
+                xp[i] = store(p->x[i] + eps * scale[j] * xi[i], O->state_f32);
+            double el = ell(P, xp);
+            double la = log_anneal(P, beta, xp, el) - log_anneal(P, beta, p->x, p->ell);
+            double lu = log(draw_uniform(K, n, t, STREAM_ACCEPT, (uint32_t)j));
+            if (fabs(la - lu) < fabs(best)) best = la - lu;
+            if (lu < la) {
+                for (int i = 0; i < d; ++i) p->x[i] = xp[i];
+                p->ell = el;
+                any = 1;
+            }
+        }
+        if (margin) *margin = best;
+        return any;
+    }
     if (O->move == MOVE_RWMH) {
         for (int i = 0; i < d; ++i) xp[i] = store(p->x[i] + eps * xi[i], O->state_f32);
         ell_p = ell(P, xp);
@@ -470,6 +517,14 @@ static void init_particle(const orc_problem* P, const orc_opts* O, const rng_key
                           uint32_t n, particle* p, double* work)
 {
     int d = P->d;
+    if (P->family == FAM_UNID) {
+        /* uniform reference: coordinate i from word i of block 0 */
+        uint32_t w[4];
+        draw_block(K, n, 0u, STREAM_INIT, 0, 0, w);
+        for (int i = 0; i < d; ++i) p->x[i] = store(P->box * word_to_uniform(w[i]), O->state_f32);
+        p->ell = ell(P, p->x);
+        return;
+    }
     draw_normals(K, n, 0u, STREAM_INIT, 0, d, work);
     double s = sqrt(P->ref_sigma2);
     for (int i = 0; i < d; ++i) p->x[i] = store(ref_mean_at(P, i) + s * work[i], O->state_f32);
@@ -769,6 +824,106 @@ int orc_asmc(const orc_problem* P, const orc_opts* O, int64_t N, int T, const do
     }
     free(X); free(G); free(L); free(LW); free(LG); free(A);
     return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Online CESS-adaptive AIS of Zhou, Johansen and Aston (ZJA).               */
+/* ------------------------------------------------------------------------ */
+/*
+ * The comparison method of Sec. "Connection to online conditional ESS
+ * optimisation" and Sec. "High-performance GPU implementation of adaptive
+ * schemes", applied to AIS (no resampling): with w_{t-1} and ell(X_{t-1}) in
+ * hand, beta_t is chosen so that the conditional ESS of the step,
+ *   CESS_t / N = g_1^2 / (g_0 g_2),  g_i = sum_n w_{t-1}^n exp(i (b - beta_{t-1}) ell_n)
+ * (eq. CESS), equals rho: beta_t = 1 when CESS(1) >= rho N, otherwise
+ * `iters` halvings of (beta_{t-1}, 1] on log CESS in binary64, keeping the
+ * upper part while CESS >= rho N (beta_t is the last point kept, or the first
+ * upper end if none was).  At t = Tmax beta_t is set to 1.  Then the step
+ * reweights, records the moments and moves every particle at beta_t (step
+ * size eps), as Alg. 1 does.
+ * Outputs: beta[Tmax + 1] (entries 0..T), *T, log_g[3 * Tmax] (layout
+ * i * Tmax + t - 1), *logZ, lw_out[N], x_out[N * d].
+ */
+static double lse_shift(int64_t N, const double* lw, const double* ell_v, double a, double* tmp)
+{
+    for (int64_t j = 0; j < N; ++j) tmp[j] = (a == 0.0) ? lw[j] : lw[j] + a * ell_v[j];
+    return logsumexp(tmp, N, 1);
+}
+
+int orc_zja(const orc_problem* P, const orc_opts* O, int64_t N, double rho, int Tmax, int iters,
+            double eps, uint64_t seed, uint32_t round_k, uint32_t problem_id, double* beta,
+            int* T_out, double* log_g, double* logZ, double* lw_out, double* x_out)
+{
+    if (!P || !O || N < 1 || Tmax < 1 || iters < 1 || !(rho > 0.0 && rho < 1.0) || !beta ||
+        !T_out || !log_g || !logZ)
+        return ORC_EINVAL;
+    int d = P->d;
+    rng_key K = {seed, round_k, problem_id};
+    if (O->nthreads > 0) omp_set_num_threads(O->nthreads);
+    double* X = (double*)malloc(sizeof(double) * (size_t)N * d);
+    double* G = (double*)malloc(sizeof(double) * (size_t)N * d);
+    double* L = (double*)malloc(sizeof(double) * (size_t)N);
+    double* lw = (double*)calloc((size_t)N, sizeof(double));
+    double* lg = (double*)malloc(sizeof(double) * (size_t)N);
+    double* tmp = (double*)malloc(sizeof(double) * (size_t)N);
+#pragma omp parallel
+    {
+        double* work = (double*)malloc(sizeof(double) * 6 * d);
+#pragma omp for schedule(static)
+        for (int64_t j = 0; j < N; ++j) {
+            particle p = {X + (size_t)j * d, 0.0, G + (size_t)j * d};
+            init_particle(P, O, &K, (uint32_t)j, &p, work);
+            L[j] = p.ell;
+        }
+        free(work);
+    }
+    const double log_rho = log(rho);
+    beta[0] = 0.0;
+    int T = 0;
+    for (int t = 1; t <= Tmax; ++t) {
+        double b0 = beta[t - 1];
+        double L0 = lse_shift(N, lw, L, 0.0, tmp);
+#define LOG_CESS(db) (2.0 * lse_shift(N, lw, L, (db), tmp) - lse_shift(N, lw, L, 2.0 * (db), tmp) - L0)
+        double bt;
+        if (LOG_CESS(1.0 - b0) >= log_rho) {
+            bt = 1.0;
+        } else {
+            double lo = b0, hi = 1.0;
+            for (int it = 0; it < iters; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (LOG_CESS(mid - b0) >= log_rho) lo = mid;
+                else hi = mid;
+            }
+            bt = (lo > b0) ? lo : hi;
+        }
+#undef LOG_CESS
+        if (t == Tmax) bt = 1.0;
+        beta[t] = bt;
+        for (int64_t j = 0; j < N; ++j) lg[j] = (bt - b0) * L[j];
+        double m3[3];
+        moments(N, lw, lg, m3, tmp);
+        for (int i = 0; i < 3; ++i) log_g[(size_t)i * Tmax + (t - 1)] = m3[i];
+        for (int64_t j = 0; j < N; ++j) lw[j] += lg[j];
+#pragma omp parallel
+        {
+            double* work = (double*)malloc(sizeof(double) * 6 * d);
+#pragma omp for schedule(static)
+            for (int64_t j = 0; j < N; ++j) {
+                particle p = {X + (size_t)j * d, L[j], G + (size_t)j * d};
+                mh_step(P, O, &K, (uint32_t)j, (uint32_t)t, bt, eps, &p, work, NULL, -1);
+                L[j] = p.ell;
+            }
+            free(work);
+        }
+        T = t;
+        if (bt >= 1.0) break;
+    }
+    *T_out = T;
+    *logZ = logsumexp(lw, N, 1) - log((double)N);
+    if (lw_out) memcpy(lw_out, lw, sizeof(double) * (size_t)N);
+    if (x_out) memcpy(x_out, X, sizeof(double) * (size_t)N * d);
+    free(X); free(G); free(L); free(lw); free(lg); free(tmp);
+    return isfinite(*logZ) ? ORC_OK : ORC_ENONFINITE;
 }
 
 /* ------------------------------------------------------------------------ */
