@@ -196,6 +196,11 @@ def logz_error(oa, spec, args, last_logz, res) -> dict:
 #    (700 at d = 10, the sweep's model).
 GRAD_WORK = 3.9e3
 REJUV_WORK = 620.0
+# Unid (d = 2) with the three-scale RWMH kernel: per substep one Philox block of
+# normals (140), one Box-Muller pair (22), one accept block (140), the binomial
+# log-likelihood ratio (two log1p, about 10) and the proposal/MH arithmetic
+# (about 20); three substeps plus the moment statistics (100)
+UNID_WORK = 3 * (140 + 22 + 140 + 10 + 20) + 100.0
 
 
 def gauss_work(d: int) -> float:
@@ -213,6 +218,89 @@ def oracle_rate(fn, n_lo: int, cap: int, budget_s: float = 12.0):
     t0 = time.perf_counter()
     fn(n1)
     return n1, time.perf_counter() - t0
+
+
+def zja_workload(args, oa, torch) -> int:
+    """The paper's GPU comparison (Sec. "High-performance GPU implementation of
+    adaptive schemes") on the Unid model with its GPU parameters (n = 1e11,
+    k = 1e10, Uniform(0, 10)^2 reference), N = 2^14 particles, the three-scale
+    RWMH kernel (0.1, 1, 10): one step = one OAIS run (T = 1, 2, ..., doubling
+    over the rounds); ZJA runs beside it with the CESS threshold matched through
+    D ~ Lambda^2 / T^2 (Lambda_hat and T of OAIS's last round).  Both are timed
+    over the same seeds, with the relative variance of Z_hat against the Laplace
+    form of the evidence, so the line reports OAIS's speed-up over ZJA at equal
+    variance (time x variance, since the variance falls as 1/cost)."""
+    n, k, box, N, R = 1e11, 1e10, 10.0, 1 << 14, args.zja_rounds
+    p = k / n
+    logZ_ref = (np.log(np.log(box * box / p)) - 2 * np.log(box) +
+                0.5 * np.log(2 * np.pi * p * (1 - p) / n))
+    prob = oa.Problem.unid(n, k, box)
+    kw = dict(move="rwmh3", budget="double_t", T1=1, T_max=1 << (R - 1), eps0=1.0)
+    S = max(args.steps, 2)
+    for i in range(args.warmup):
+        oa.run(prob, N, R, seed=args.seed + i, **kw)
+    torch.cuda.synchronize()
+    oa.profile(True)
+    t0 = time.perf_counter()
+    runs = [oa.run(prob, N, R, seed=args.seed + 1000 + i, **kw) for i in range(S)]
+    torch.cuda.synchronize()
+    t_oais = (time.perf_counter() - t0) / S
+    prof = oa.profile(False)
+    TR = int(runs[0]["T"][-1])
+    lam = float(np.mean([r["Lambda"][-1][TR] for r in runs]))
+    rho = float(np.exp(-(lam / TR) ** 2))
+    for i in range(args.warmup):
+        oa.zja(prob, N, rho, 1 << 16, 1.0, args.seed + i, return_state=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    zr = [oa.zja(prob, N, rho, 1 << 16, 1.0, args.seed + 1000 + i, return_state=False)
+          for i in range(S)]
+    torch.cuda.synchronize()
+    t_zja = (time.perf_counter() - t0) / S
+    z_o = np.exp(np.array([r["logZ"][-1] for r in runs]) - logZ_ref)
+    z_z = np.exp(np.array([r["logZ"] for r in zr]) - logZ_ref)
+    v_o, v_z = float(np.var(z_o, ddof=1)), float(np.var(z_z, ddof=1))
+    steps_run = float(np.sum(runs[0]["N"].astype(np.float64) * runs[0]["T"]))
+    rate = prof["particle_steps"] / (prof["kernel_ms"] * 1e-3) if prof["kernel_ms"] else None
+    peak = PEAK_LANE_CYCLES / UNID_WORK
+    line = {"metric": METRIC, "value": steps_run / t_oais, "unit": "particle-steps/s",
+            "n_gpus": 1, "steps": S, "warmup": args.warmup, "ms_per_step": t_oais * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32 state / f64 arithmetic and weights", "data": "synthetic",
+            "config": {"workload": "unid_n1e11_k1e10_rwmh3_oais_vs_zja", "N": N, "rounds": R,
+                       "T_last": TR},
+            "logZ_error": {"seeds": S, "reference": float(logZ_ref),
+                           "reference_kind": "Laplace form of the evidence",
+                           "rmse": float(np.sqrt(np.mean(np.log(z_o) ** 2))),
+                           "rel_var_Z_oais": v_o, "rel_var_Z_zja": v_z},
+            "comparison": {"zja_rho": rho, "zja_T_mean": float(np.mean([r["T"] for r in zr])),
+                           "oais_ms_per_run": t_oais * 1e3, "zja_ms_per_run": t_zja * 1e3,
+                           "zja_over_oais_time": t_zja / t_oais,
+                           "zja_over_oais_time_x_variance": (t_zja * v_z) / (t_oais * v_o)
+                           if v_o > 0 else None},
+            "roofline": {"bound": "alu", "achieved": rate, "peak": peak,
+                         "unit": "particle-steps/s", "frac": rate / peak if rate else None,
+                         "traffic": None, "kernel": "k_oais_valu (OAIS sweeps)",
+                         "work_lane_cycles_per_particle_step": UNID_WORK,
+                         "avg_launch_ms": prof["kernel_ms"] / max(prof["launches"], 1),
+                         "launches": prof["launches"]},
+            "cpu_baseline": None}
+    if not args.no_cpu_baseline:
+        import oracle as orc
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        P = orc.Problem(family=orc.FAM_UNID, d=2, binom_n=n, binom_k=k, box=box)
+        bt = runs[0]["beta"][R - 1][:TR + 1]
+        ep = runs[0]["eps"][R - 1][:TR]
+
+        def go(m):
+            orc.asmc(P, orc.Opts(move=orc.MOVE_RWMH3, state_f32=1, nthreads=cores), N, bt, ep,
+                     args.seed, round_k=R, subset=np.arange(m))
+        m, dt = oracle_rate(go, cores, N)
+        line["cpu_baseline"] = {"value": m * TR / dt, "unit": "particle-steps/s", "cores": cores,
+                                "kind": "oracle",
+                                "sample": f"{m} particles x T={TR} (last OAIS round), {dt:.1f} s"}
+    print(json.dumps(line), flush=True)
+    return 0
 
 
 def extra_workload(args, oa, wl, torch) -> int:
@@ -370,7 +458,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="logreg",
-                    choices=sorted(WORKLOADS) + ["grad", "rejuv", "batch", "batch_seq"])
+                    choices=sorted(WORKLOADS) + ["grad", "rejuv", "batch", "batch_seq", "zja"])
+    ap.add_argument("--zja-rounds", type=int, default=10,
+                    help="OAIS rounds of the zja workload (T doubles from 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rmse-seeds", type=int, default=-1,
                     help="seeds for the log Z error (default per workload; 0 skips it)")
@@ -401,6 +491,8 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": nbytes, "repeats": 3}), flush=True)
         return 0
+    if args.workload == "zja":
+        return zja_workload(args, oa, torch)
     if args.workload in ("grad", "rejuv", "batch", "batch_seq"):
         return extra_workload(args, oa, wl, torch)
     spec = WORKLOADS[args.workload](oa, wl)

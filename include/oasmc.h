@@ -44,8 +44,12 @@ typedef enum {
     OASMC_EUNSUPPORTED = -5  /* (family, move, d) combination not built */
 } oasmc_status;
 
-typedef enum { OASMC_GAUSS = 1, OASMC_LOGREG = 2, OASMC_GMM = 3 } oasmc_family;
-typedef enum { OASMC_RWMH = 1, OASMC_MALA = 2, OASMC_HMC = 3 } oasmc_move;
+typedef enum { OASMC_GAUSS = 1, OASMC_LOGREG = 2, OASMC_GMM = 3, OASMC_UNID = 4 } oasmc_family;
+/* OASMC_RWMH3: the alternation of three random-walk MH steps with proposal
+ * standard deviations eps (0.1, 1, 10), one kernel per annealing step, used by
+ * the paper's GPU experiments (appendix "GPU implementation"); the step's
+ * accept bit is set when any of the three was accepted. */
+typedef enum { OASMC_RWMH = 1, OASMC_MALA = 2, OASMC_HMC = 3, OASMC_RWMH3 = 4 } oasmc_move;
 
 /*
  * Target gamma and reference eta.  All array pointers are DEVICE pointers to
@@ -57,7 +61,14 @@ typedef enum { OASMC_RWMH = 1, OASMC_MALA = 2, OASMC_HMC = 3 } oasmc_move;
  *                 as 1).  ell is the log-likelihood.
  *   OASMC_GMM   : gamma(x) = (1/K) sum_k exp(-|x - means[k]|^2 / (2 exp(2 log_scales[k])))
  *                 means[K][d], log_scales[K].
- *   eta         : N(ref_mean, ref_sigma2 I); ref_mean may be NULL (zero mean).
+ *   OASMC_UNID  : the unidentifiable product parameterisation (appendix on the
+ *                 models): d = 2, eta = Uniform(0, box)^2, gamma = eta times the
+ *                 likelihood Binomial(binom_k | binom_n, x y) divided by its
+ *                 maximum (at x y = k / n), zero unless 0 < x y < 1; so
+ *                 log Z_hat estimates log Z - log Binomial(k | n, k / n).
+ *                 Moves RWMH and RWMH3 only.
+ *   eta         : N(ref_mean, ref_sigma2 I) (all families but OASMC_UNID);
+ *                 ref_mean may be NULL (zero mean).
  */
 typedef struct {
     int32_t family;
@@ -72,6 +83,7 @@ typedef struct {
     const float* log_scales;
     const float* ref_mean;
     double ref_sigma2;
+    double binom_n, binom_k, box; /* OASMC_UNID */
 } oasmc_problem;
 
 /*
@@ -146,6 +158,27 @@ const char* oasmc_last_error(void);
 int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel* kernel,
                int64_t N, int32_t T, const double* beta, const double* eps, uint64_t seed,
                uint32_t round_k, uint32_t problem_id, oasmc_round_out* out, void* stream);
+
+/*
+ * The online CESS-adaptive AIS of Zhou, Johansen and Aston (ZJA), the
+ * comparison method of Sec. "Connection to online conditional ESS
+ * optimisation" and of the GPU comparison: after each step the next annealing
+ * parameter is chosen from the current weighted particles so that
+ * CESS_t / N = g_1^2 / (g_0 g_2) (eq. CESS) equals rho: beta_t = 1 when CESS at
+ * 1 is already >= rho N, else `iters` bisection halvings of (beta_{t-1}, 1]
+ * keeping the upper part while CESS >= rho N; at t = Tmax beta_t is set to 1.
+ * The selection runs on the device (one workgroup over all particles), then the
+ * step reweights and moves every particle as oasmc_asmc does (AIS: kernel's
+ * resample must be 0; constant step size eps).  Random streams as oasmc_asmc.
+ * Outputs: beta[0..T] (host, capacity Tmax + 1), *T_out, log_g (host [3*Tmax],
+ * layout i * Tmax + t - 1, may be NULL), *logZ, final lw[N] and x[N*d]
+ * (device, may be NULL).  Gaussian, mixture and Unid families.  Synchronises
+ * `stream` once per 32 steps.
+ */
+int oasmc_zja(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel* kernel, int64_t N,
+              double rho, int32_t Tmax, int32_t iters, double eps, uint64_t seed, uint32_t round_k,
+              uint32_t problem_id, double* beta, int32_t* T_out, double* log_g, double* logZ,
+              double* lw, float* x, void* stream);
 
 /*
  * Final-iteration rejuvenation (Sec. "Computing expectations"): after a pass,

@@ -557,7 +557,8 @@ static double logsumexp(const double* v, int64_t m, int64_t stride)
 static void moments(int64_t N, const double* lw_prev, const double* lg, double* out3, double* tmp)
 {
     for (int i = 0; i < 3; ++i) {
-        for (int64_t n = 0; n < N; ++n) tmp[n] = lw_prev[n] + (double)i * lg[n];
+        /* (g^n_t)^0 = 1 also where g^n_t = 0 (log g = -inf, a zero likelihood) */
+        for (int64_t n = 0; n < N; ++n) tmp[n] = (i == 0) ? lw_prev[n] : lw_prev[n] + (double)i * lg[n];
         out3[i] = logsumexp(tmp, N, 1);
     }
 }

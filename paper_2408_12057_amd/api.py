@@ -13,8 +13,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboasmc.so")
 
 OK, EINVAL, EHIP, ENOMEM, ENONFINITE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-GAUSS, LOGREG, GMM = 1, 2, 3
-MOVES = {"rwmh": 1, "mala": 2, "hmc": 3}
+GAUSS, LOGREG, GMM, UNID = 1, 2, 3, 4
+MOVES = {"rwmh": 1, "mala": 2, "hmc": 3, "rwmh3": 4}
 TRIGGERS = {"ess": 0, "cess": 1, "sir": 2, "fixed": 3}
 BUDGETS = {"fixed": 0, "double_n": 1, "double_t": 2, "sqrt2": 3}
 
@@ -30,7 +30,8 @@ class _Problem(C.Structure):
         ("family", C.c_int32), ("d", C.c_int32), ("mu", C.c_void_p), ("sigma2", C.c_double),
         ("X", C.c_void_p), ("y", C.c_void_p), ("n", C.c_int32), ("K", C.c_int32),
         ("means", C.c_void_p), ("log_scales", C.c_void_p), ("ref_mean", C.c_void_p),
-        ("ref_sigma2", C.c_double),
+        ("ref_sigma2", C.c_double), ("binom_n", C.c_double), ("binom_k", C.c_double),
+        ("box", C.c_double),
     ]
 
 
@@ -112,6 +113,9 @@ def _load():
     L.oasmc_run_batch.argtypes = [vp, C.POINTER(_BatchProblem), C.c_int32, C.c_int32, C.c_int32,
                                   C.POINTER(_BatchOut), vp]
     L.oasmc_logreg_eval.argtypes = [vp, C.POINTER(_Problem), C.c_int64, vp, vp, vp, vp]
+    L.oasmc_zja.argtypes = [vp, C.POINTER(_Problem), C.POINTER(_Kernel), C.c_int64, C.c_double,
+                            C.c_int32, C.c_int32, C.c_double, C.c_uint64, C.c_uint32, C.c_uint32,
+                            vp, vp, vp, vp, vp, vp, vp]
     L.oasmc_rejuvenate.argtypes = [vp, C.POINTER(_Problem), C.POINTER(_Kernel), C.c_int64,
                                    C.c_int32, C.c_double, C.c_uint64, C.c_uint32, C.c_uint32, vp,
                                    vp, vp, vp, vp, vp, vp]
@@ -120,7 +124,8 @@ def _load():
     for f in ("oasmc_handle_create", "oasmc_handle_destroy", "oasmc_asmc", "oasmc_adapt_schedule",
               "oasmc_dar_times",
               "oasmc_run", "oasmc_resample", "oasmc_resample_noalloc", "oasmc_philox", "oasmc_logreg_eval",
-              "oasmc_profile", "oasmc_logZ_backward", "oasmc_run_batch", "oasmc_rejuvenate"):
+              "oasmc_profile", "oasmc_logZ_backward", "oasmc_run_batch", "oasmc_rejuvenate",
+              "oasmc_zja"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -174,6 +179,16 @@ class Problem:
     log_scales: Optional[torch.Tensor] = None
     ref_mean: Optional[torch.Tensor] = None
     ref_sigma2: float = 1.0
+    binom_n: float = 0.0
+    binom_k: float = 0.0
+    box: float = 10.0
+
+    @staticmethod
+    def unid(n: float, k: float, box: float = 10.0, device="cuda"):
+        """The unidentifiable product parameterisation: Uniform(0, box)^2 reference,
+        Binomial(k | n, x y) likelihood divided by its maximum."""
+        return Problem(UNID, 2, torch.device(device), binom_n=float(n), binom_k=float(k),
+                       box=float(box))
 
     @staticmethod
     def gauss(mu, sigma2: float, ref_sigma2: float = 1.0, ref_mean=None, device="cuda"):
@@ -203,7 +218,8 @@ class Problem:
         return _Problem(self.family, self.d, p(self.mu), self.sigma2, p(self.X), p(self.y),
                         0 if self.X is None else int(self.X.shape[0]),
                         0 if self.means is None else int(self.means.shape[0]),
-                        p(self.means), p(self.log_scales), p(self.ref_mean), self.ref_sigma2)
+                        p(self.means), p(self.log_scales), p(self.ref_mean), self.ref_sigma2,
+                        self.binom_n, self.binom_k, self.box)
 
 
 def _kernel(move, leapfrog, resample_, trigger, nu, slots=0, resample_at=None) -> _Kernel:
@@ -314,6 +330,34 @@ def run(problem: Problem, N1: int, rounds: int, seed: int, problem_id: int = 0, 
              n_resample=nres, rounds_done=out.rounds_done)
     if rejuvenate:
         r["rejuv_mean"], r["rejuv_second"] = rj_m, rj_s
+    return r
+
+
+def zja(problem: Problem, N: int, rho: float, Tmax: int, eps: float, seed: int, move="rwmh3",
+        leapfrog: int = 5, iters: int = 40, round_k: int = 1, problem_id: int = 0,
+        return_state: bool = True) -> dict:
+    """ZJA online CESS-adaptive AIS: beta [T+1], T, log_g [3, T], logZ (and final lw, x)."""
+    dev = problem.device
+    beta = np.zeros(Tmax + 1)
+    lg = np.zeros(3 * Tmax)
+    T = C.c_int32(0)
+    lz = C.c_double(0.0)
+    lw = x = None
+    if return_state:
+        lw = torch.empty(N, dtype=torch.float64, device=dev)
+        x = torch.empty((N, problem.d), dtype=torch.float32, device=dev)
+    P = problem.c()
+    K = _kernel(move, leapfrog, False, "ess", 0.5)
+    _check(_load().oasmc_zja(_handle(dev.index or 0), C.byref(P), C.byref(K), int(N), float(rho),
+                             int(Tmax), int(iters), float(eps), int(seed) & (2 ** 64 - 1),
+                             int(round_k), int(problem_id), _np_ptr(beta),
+                             C.c_void_p(C.addressof(T)), _np_ptr(lg), C.c_void_p(C.addressof(lz)),
+                             None if lw is None else C.c_void_p(lw.data_ptr()),
+                             None if x is None else C.c_void_p(x.data_ptr()), _stream(dev)))
+    Tv = T.value
+    r = dict(T=Tv, beta=beta[:Tv + 1], log_g=lg.reshape(3, Tmax)[:, :Tv], logZ=lz.value)
+    if return_state:
+        r["lw"], r["x"] = lw, x
     return r
 
 

@@ -78,12 +78,13 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& zc,
     zs = r * s;
 }
 
-// Normals 4b .. 4b+3 of a (particle, step, stream) sequence.
+// Normals 4b .. 4b+3 of a (particle, step, stream, substep) sequence.
 template <bool FUSED = true>
 __device__ __forceinline__ void normals4(const RngKey& key, uint32_t n, uint32_t t,
-                                        uint32_t stream, uint32_t block, double z[4])
+                                        uint32_t stream, uint32_t block, double z[4],
+                                        uint32_t substep = 0u)
 {
-    const uint4 w = draw_block<FUSED>(key, n, t, stream, 0u, block);
+    const uint4 w = draw_block<FUSED>(key, n, t, stream, substep, block);
     box_muller(w.x, w.y, z[0], z[1]);
     box_muller(w.z, w.w, z[2], z[3]);
 }

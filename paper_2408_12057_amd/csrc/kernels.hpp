@@ -9,8 +9,12 @@
 
 namespace oasmc {
 
-enum Family { kGauss = 1, kLogreg = 2, kGmm = 3 };
-enum Move { kRwmh = 1, kMala = 2, kHmc = 3 };
+enum Family { kGauss = 1, kLogreg = 2, kGmm = 3, kUnid = 4 };
+// kRwmh3: the alternation of three random-walk MH substeps with standard
+// deviations eps (0.1, 1, 10) per step (the paper's GPU experiments).
+enum Move { kRwmh = 1, kMala = 2, kHmc = 3, kRwmh3 = 4 };
+// Moves that use grad ell (and keep it with the state).
+__host__ __device__ constexpr bool uses_grad(int move) { return move == kMala || move == kHmc; }
 
 constexpr int kMaxK = 16;      // mixture components handled by the VALU kernels
 constexpr int kMaxDValu = 256; // dimension handled by the VALU kernels
@@ -27,6 +31,9 @@ struct TargetDev {
     const float* log_scales;
     const float* ref_mean;  // may be null
     double ref_sigma2;
+    // kUnid (d = 2): uniform reference on (0, box)^2; ell = log Binomial(k | n, x y)
+    // minus its maximum (at x y = k / n), -inf unless 0 < x y < 1 inside the box
+    double binom_n, binom_k, box;
 };
 
 // Pointers to a problem's target parameters as the particle code reads them:
@@ -92,6 +99,9 @@ struct SweepArgs {
     double* sell;
     double* slw;
     uint32_t* saccw;
+    // Online schedules (ZJA): the per-step kernel of the resampling variant
+    // does nothing for steps t > *t_stop (device; null = never stops early).
+    const int* t_stop;
 };
 
 // Element e of the lane layout of (reference mean, target means) for a shape
@@ -107,6 +117,7 @@ __device__ __forceinline__ double lane_param(const TargetDev& tg, int lpp, int d
     if (i >= tg.d) return 0.0;
     if (k == 0) return tg.ref_mean ? (double)tg.ref_mean[i] : 0.0;
     if (tg.family == kGmm && k > tg.K) return 0.0;  // padding of the last block
+    if (tg.family == kUnid) return 0.0;              // no target means
     const float* src = (tg.family == kGmm) ? tg.means : tg.mu;
     return (double)src[(size_t)(k - 1) * tg.d + i];
 }
@@ -208,6 +219,15 @@ hipError_t launch_resample_event(int64_t N, const double* lw, const RngKey& key,
 // final log-weights in entry T): moments, accepted counts, the log Z_hat factor
 // and, when t_end < T, the resampling event (flag, largest log w, uniform word).
 hipError_t launch_segment_merge(const SweepArgs& a, const AsmcState& z, hipStream_t st);
+// ZJA (online CESS-adaptive AIS): beta_t by bisection of log CESS on the
+// device (one workgroup), then the step's reweight and move without a merge;
+// log Z_hat from the final log-weights into logZ[0].
+hipError_t launch_zja_select(int64_t N, const double* lw, const double* ell, double* beta, int t,
+                             int Tmax, double log_rho, int iters, int* stop, double* log_g,
+                             hipStream_t st);
+hipError_t launch_asmc_move(const SweepArgs& a, const ValuShape& s, const AsmcState& z, int t,
+                            hipStream_t st);
+hipError_t launch_zja_final(int64_t N, const double* lw, double* logZ, hipStream_t st);
 hipError_t launch_merge_slots(const double* part, int64_t S, int T, int64_t N, double* log_g,
                               double* acc, double* logZ, hipStream_t st);
 hipError_t launch_resample_plain(int64_t N, const double* lw, uint32_t u, int32_t* anc,

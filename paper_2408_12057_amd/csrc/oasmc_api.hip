@@ -112,7 +112,7 @@ enum BufId {
     B_BETA, B_EPS, B_PART, B_LOGG, B_ACC, B_SCAL, B_X, B_X2, B_ELL, B_ELL2, B_LW, B_ACCW,
     B_TPART, B_NRES, B_ESS, B_RES, B_C, B_BTOT, B_LWO, B_XO, B_LOGREG, B_CKPT, B_SEG, B_ABITS,
     B_GPART, B_GRAD, B_DEVRUN, B_DEVDESC, B_G, B_G2, B_BLK, B_RJ_ANC, B_RJ_SUM, B_RJ_OUT,
-    B_RJ_LW, B_RJ_X, B_COUNT
+    B_RJ_LW, B_RJ_X, B_ZSTOP, B_COUNT
 };
 
 template <typename T>
@@ -147,9 +147,9 @@ int check_schedule(int T, const double* beta)
 int check_problem(const oasmc_problem* p, const oasmc_kernel* k)
 {
     if (!p || !k) return fail(OASMC_EINVAL, "problem or kernel is NULL");
-    if (!(p->ref_sigma2 > 0.0) || !std::isfinite(p->ref_sigma2))
+    if (p->family != OASMC_UNID && (!(p->ref_sigma2 > 0.0) || !std::isfinite(p->ref_sigma2)))
         return fail(OASMC_EINVAL, "ref_sigma2 must be positive and finite");
-    if (k->move < OASMC_RWMH || k->move > OASMC_HMC)
+    if (k->move < OASMC_RWMH || k->move > OASMC_RWMH3)
         return fail(OASMC_EINVAL, "unknown move %d", k->move);
     if (k->move == OASMC_HMC && k->leapfrog < 1)
         return fail(OASMC_EINVAL, "HMC needs leapfrog >= 1");
@@ -171,6 +171,15 @@ int check_problem(const oasmc_problem* p, const oasmc_kernel* k)
         if (p->K < 1 || p->K > kMaxK) return fail(OASMC_EUNSUPPORTED, "mixture supports 1 <= K <= %d", kMaxK);
         if (p->d < 1 || p->d > kMaxDValu)
             return fail(OASMC_EUNSUPPORTED, "mixture supports 1 <= d <= %d", kMaxDValu);
+        break;
+    case OASMC_UNID:
+        if (p->d != 2) return fail(OASMC_EUNSUPPORTED, "the Unid target has d = 2");
+        if (!(p->binom_n > 0.0) || !(p->binom_k > 0.0) || !(p->binom_k < p->binom_n) ||
+            !std::isfinite(p->binom_n))
+            return fail(OASMC_EINVAL, "Unid needs 0 < binom_k < binom_n");
+        if (!(p->box > 0.0) || !std::isfinite(p->box)) return fail(OASMC_EINVAL, "box must be positive");
+        if (k->move != OASMC_RWMH && k->move != OASMC_RWMH3)
+            return fail(OASMC_EUNSUPPORTED, "the Unid target is built for RWMH and RWMH3");
         break;
     case OASMC_LOGREG:
         if (!p->X || !p->y) return fail(OASMC_EINVAL, "logistic regression needs X and y");
@@ -201,6 +210,9 @@ TargetDev target_dev(const oasmc_problem* p)
     t.log_scales = p->log_scales;
     t.ref_mean = p->ref_mean;
     t.ref_sigma2 = p->ref_sigma2;
+    t.binom_n = p->binom_n;
+    t.binom_k = p->binom_k;
+    t.box = p->box;
     return t;
 }
 
@@ -932,7 +944,7 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
         HIP_TRY(wget(h, B_X2, (size_t)N * d, &z.X2));
         HIP_TRY(wget(h, B_ELL, N, &z.ell));
         HIP_TRY(wget(h, B_ELL2, N, &z.ell2));
-        if (kernel->move != OASMC_RWMH) {
+        if (uses_grad(kernel->move)) {
             HIP_TRY(wget(h, B_G, (size_t)N * d, &z.G));
             HIP_TRY(wget(h, B_G2, (size_t)N * d, &z.G2));
         }
@@ -1019,6 +1031,104 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
     out->logZ = scal[0];
     out->n_resample = nres;
     if (!std::isfinite(out->logZ)) return fail(OASMC_ENONFINITE, "log Z_hat is not finite");
+    g_err.clear();
+    return OASMC_OK;
+}
+
+int oasmc_zja(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel* kernel, int64_t N,
+              double rho, int32_t Tmax, int32_t iters, double eps, uint64_t seed, uint32_t round_k,
+              uint32_t problem_id, double* beta, int32_t* T_out, double* log_g, double* logZ,
+              double* lw, float* x, void* stream)
+{
+    if (!h || !beta || !T_out || !logZ) return fail(OASMC_EINVAL, "NULL argument");
+    int s = check_problem(problem, kernel);
+    if (s) return s;
+    if (problem->family == OASMC_LOGREG || kernel->resample)
+        return fail(OASMC_EUNSUPPORTED, "ZJA is built for AIS on the Gaussian, mixture and Unid families");
+    if (N < 1 || N > ((int64_t)1 << 30)) return fail(OASMC_EINVAL, "N must lie in [1, 2^30]");
+    if (!(rho > 0.0 && rho < 1.0)) return fail(OASMC_EINVAL, "rho must lie in (0, 1)");
+    if (Tmax < 1) return fail(OASMC_EINVAL, "Tmax must be >= 1");
+    if (iters < 1 || iters > 60) return fail(OASMC_EINVAL, "iters must lie in [1, 60]");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(OASMC_EINVAL, "eps must be positive");
+    HIP_TRY(hipSetDevice(h->device));
+    hipStream_t st = (hipStream_t)stream;
+    ValuShape shape{};
+    if (!valu_shape(problem->d, N, &shape))
+        return fail(OASMC_EUNSUPPORTED, "no kernel shape for d=%d", problem->d);
+    const int d = problem->d;
+    SweepArgs a{};
+    a.tg = target_dev(problem);
+    a.move = kernel->move;
+    a.leapfrog = kernel->leapfrog;
+    a.N = N;
+    a.T = Tmax;
+    a.key.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    a.key.k1 = (uint32_t)(seed >> 32);
+    a.key.c2 = (round_k & 0xFFFFu) | (problem_id << 16);
+    a.ntiles = valu_tiles(N, shape);
+    a.acc_words = (Tmax + 31) / 32;
+    double *dbeta, *deps, *dlogg, *dscal;
+    int* dstop;
+    HIP_TRY(wget(h, B_BETA, (size_t)Tmax + 1, &dbeta));
+    HIP_TRY(wget(h, B_EPS, Tmax, &deps));
+    HIP_TRY(wget(h, B_LOGG, 3 * (size_t)Tmax, &dlogg));
+    HIP_TRY(wget(h, B_SCAL, 8, &dscal));
+    HIP_TRY(wget(h, B_ZSTOP, 1, &dstop));
+    std::vector<double> eps_h(Tmax, eps), beta0(1, 0.0);
+    HIP_TRY(hipMemcpyAsync(deps, eps_h.data(), sizeof(double) * Tmax, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(dbeta, beta0.data(), sizeof(double), hipMemcpyHostToDevice, st));
+    const int stop0 = Tmax;
+    HIP_TRY(hipMemcpyAsync(dstop, &stop0, sizeof(int), hipMemcpyHostToDevice, st));
+    a.beta = dbeta;
+    a.eps = deps;
+    a.t_stop = dstop;
+    AsmcState z{};
+    HIP_TRY(wget(h, B_X, (size_t)N * d, &z.X));
+    HIP_TRY(wget(h, B_ELL, N, &z.ell));
+    if (uses_grad(kernel->move)) HIP_TRY(wget(h, B_G, (size_t)N * d, &z.G));
+    HIP_TRY(wget(h, B_LW, N, &z.lw));
+    HIP_TRY(wget(h, B_ACCW, N, &z.accw));
+    HIP_TRY(wget(h, B_TPART, (size_t)a.ntiles * 8, &z.tile_part));
+    const double log_rho = std::log(rho);
+    if (h->prof) HIP_TRY(hipEventRecord(h->ev0, st));
+    HIP_TRY(launch_asmc_init(a, shape, z, st));
+    // steps in chunks; the host looks at the device's stop step after each
+    // chunk (steps past it are no-ops on the device)
+    constexpr int kChunk = 32;
+    int T = Tmax;
+    for (int t0 = 1; t0 <= Tmax; t0 += kChunk) {
+        const int t1 = std::min(Tmax, t0 + kChunk - 1);
+        for (int t = t0; t <= t1; ++t) {
+            HIP_TRY(launch_zja_select(N, z.lw, z.ell, dbeta, t, Tmax, log_rho, iters, dstop, dlogg, st));
+            HIP_TRY(launch_asmc_move(a, shape, z, t, st));
+        }
+        int stop = 0;
+        HIP_TRY(hipMemcpyAsync(&stop, dstop, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (stop <= t1) {
+            T = stop;
+            break;
+        }
+    }
+    HIP_TRY(launch_zja_final(N, z.lw, dscal, st));
+    if (h->prof) HIP_TRY(hipEventRecord(h->ev1, st));
+    double lz = 0.0;
+    HIP_TRY(hipMemcpyAsync(beta, dbeta, sizeof(double) * (T + 1), hipMemcpyDeviceToHost, st));
+    if (log_g) HIP_TRY(hipMemcpyAsync(log_g, dlogg, sizeof(double) * 3 * Tmax, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&lz, dscal, sizeof(double), hipMemcpyDeviceToHost, st));
+    if (lw) HIP_TRY(hipMemcpyAsync(lw, z.lw, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+    if (x) HIP_TRY(hipMemcpyAsync(x, z.X, sizeof(float) * N * d, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h->prof) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+        h->prof_ms += ms;
+        h->prof_launches += T;
+        h->prof_steps += (double)N * T;
+    }
+    *T_out = T;
+    *logZ = lz;
+    if (!std::isfinite(lz)) return fail(OASMC_ENONFINITE, "log Z_hat is not finite");
     g_err.clear();
     return OASMC_OK;
 }

@@ -506,8 +506,144 @@ static hipError_t dispatch_all(int what, const SweepArgs& a, const ValuShape& s,
     OASMC_FM(kGmm, kRwmh)
     OASMC_FM(kGmm, kMala)
     OASMC_FM(kGmm, kHmc)
+    OASMC_FM(kGauss, kRwmh3)
+    OASMC_FM(kGmm, kRwmh3)
+    OASMC_FM(kUnid, kRwmh)
+    OASMC_FM(kUnid, kRwmh3)
 #undef OASMC_FM
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_asmc_move(const SweepArgs& a, const ValuShape& s, const AsmcState& z, int t,
+                            hipStream_t st)
+{
+    return dispatch_all(2, a, s, 0, &z, t, st);
+}
+
+// ---------------------------------------------------------------------------
+// ZJA: the online CESS-adaptive schedule of Zhou, Johansen and Aston applied
+// to AIS (Sec. "Connection to online conditional ESS optimisation").  One
+// workgroup chooses beta_t from log w_{t-1} and ell(X_{t-1}) of every particle:
+// CESS(b) / N = g_1^2 / (g_0 g_2), g_i = sum_n w_n exp(i (b - beta_{t-1}) ell_n)
+// (eq. CESS); beta_t = 1 if CESS(1) >= rho N, else `iters` halvings of
+// (beta_{t-1}, 1] keeping the upper part while CESS >= rho N.  This is the
+// per-step communication across all particles that the loop-swapped OAIS pass
+// avoids.
+// ---------------------------------------------------------------------------
+constexpr int kZjaThreads = 1024;
+
+// Log-sum-exps L_i over the particles of log w + i a ell for i = I0 .. 2, in
+// two passes (a block maximum, then a block sum of exp(x - max): one
+// exponential per term, no data-dependent branch around it); per-thread
+// partials in particle order, then the wave's xor butterfly, then the waves in
+// order, so every thread ends with the same bits.
+template <int I0>
+__device__ __forceinline__ void zja_lse(int64_t N, const double* __restrict__ lw,
+                                        const double* __restrict__ ell, double a, double (&L)[3],
+                                        double* shm)
+{
+    constexpr int NW = kZjaThreads / kWave;
+    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    auto term = [&](int64_t j, int i) {
+        const double v = lw[j];
+        return (i == 0) ? v : v + (double)i * a * ell[j];
+    };
+    double m[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t j = threadIdx.x; j < N; j += kZjaThreads)
+#pragma unroll
+        for (int i = I0; i < 3; ++i) m[i] = fmax(m[i], term(j, i));
+#pragma unroll
+    for (int i = I0; i < 3; ++i) {
+        m[i] = wave_max(m[i]);
+        if (lane == 0) shm[w * 3 + i] = m[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = I0; i < 3; ++i) {
+        double mm = -INFINITY;
+        for (int ww = 0; ww < NW; ++ww) mm = fmax(mm, shm[ww * 3 + i]);
+        m[i] = mm;
+    }
+    __syncthreads();
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t j = threadIdx.x; j < N; j += kZjaThreads)
+#pragma unroll
+        for (int i = I0; i < 3; ++i) {
+            const double x = term(j, i);
+            s[i] += (x > -INFINITY) ? exp(x - m[i]) : 0.0;
+        }
+#pragma unroll
+    for (int i = I0; i < 3; ++i) {
+        s[i] = wave_sum(s[i]);
+        if (lane == 0) shm[w * 3 + i] = s[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = I0; i < 3; ++i) {
+        double ss = 0.0;
+        for (int ww = 0; ww < NW; ++ww) ss += shm[ww * 3 + i];
+        L[i] = (m[i] > -INFINITY) ? lse_value(m[i], ss) : -INFINITY;
+    }
+    __syncthreads();  // shm is reused by the next call
+}
+
+__global__ void __launch_bounds__(kZjaThreads)
+    k_zja_select(int64_t N, const double* __restrict__ lw, const double* __restrict__ ell,
+                 double* beta, int t, int Tmax, double log_rho, int iters, int* stop,
+                 double* log_g)
+{
+    if (t > *stop) return;
+    __shared__ double shm[(kZjaThreads / kWave) * 3];
+    const double b0 = beta[t - 1];
+    double L[3];
+    zja_lse<0>(N, lw, ell, 1.0 - b0, L, shm);  // L_0 (log of sum w_{t-1}) is fixed for the step
+    const double L0 = L[0];
+    double bt;
+    if (2.0 * L[1] - L[2] - L0 >= log_rho) {
+        bt = 1.0;
+    } else {
+        double lo = b0, hi = 1.0;
+        for (int it = 0; it < iters; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            zja_lse<1>(N, lw, ell, mid - b0, L, shm);
+            if (2.0 * L[1] - L[2] - L0 >= log_rho) lo = mid;
+            else hi = mid;
+        }
+        bt = (lo > b0) ? lo : hi;
+    }
+    if (t == Tmax) bt = 1.0;
+    zja_lse<1>(N, lw, ell, bt - b0, L, shm);  // the step's moments at the chosen beta_t
+    L[0] = L0;
+    if (threadIdx.x == 0) {
+        beta[t] = bt;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) log_g[(size_t)i * Tmax + (t - 1)] = L[i];
+        if (bt >= 1.0) *stop = t;
+    }
+}
+
+__global__ void __launch_bounds__(kZjaThreads) k_zja_final(int64_t N, const double* lw,
+                                                           double* logZ)
+{
+    __shared__ double shm[(kZjaThreads / kWave) * 3];
+    double L[3];
+    zja_lse<0>(N, lw, lw, 0.0, L, shm);
+    if (threadIdx.x == 0) logZ[0] = L[0] - log((double)N);
+}
+
+hipError_t launch_zja_select(int64_t N, const double* lw, const double* ell, double* beta, int t,
+                             int Tmax, double log_rho, int iters, int* stop, double* log_g,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zja_select, dim3(1), dim3(kZjaThreads), 0, st, N, lw, ell, beta, t, Tmax,
+                       log_rho, iters, stop, log_g);
+    return hipGetLastError();
+}
+
+hipError_t launch_zja_final(int64_t N, const double* lw, double* logZ, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zja_final, dim3(1), dim3(kZjaThreads), 0, st, N, lw, logZ);
+    return hipGetLastError();
 }
 
 hipError_t launch_rejuv(const RejuvArgs& R, const ValuShape& s, hipStream_t st)

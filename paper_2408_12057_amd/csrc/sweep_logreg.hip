@@ -442,7 +442,7 @@ __device__ __forceinline__ void logreg_slot(LogregShared& sh, const LogregArgs& 
                     const int i = __builtin_amdgcn_readfirstlane(tid / kWave), q = tid % kWave;
                     const bool vq = (tile * kLP + q) < a.N;
                     const double lg = (beta - beta_prev) * sh.ll[q];
-                    const double x = vq ? sh.lw[q] + (double)i * lg : -INFINITY;
+                    const double x = vq ? (i == 0 ? sh.lw[q] : sh.lw[q] + (double)i * lg) : -INFINITY;
                     double m = x;
 #pragma unroll
                     for (int o = 1; o < kWave; o <<= 1) m = fmax(m, __shfl_xor(m, o, kWave));

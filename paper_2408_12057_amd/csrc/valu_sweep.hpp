@@ -69,7 +69,8 @@ __device__ __forceinline__ ParView stage_params(const TargetDev& tg, char* sh)
     float* mu = m + d;
     for (int i = threadIdx.x; i < d; i += blockDim.x) m[i] = tg.ref_mean ? tg.ref_mean[i] : 0.f;
     const float* src = (tg.family == kGmm) ? tg.means : tg.mu;
-    for (int i = threadIdx.x; i < nmu; i += blockDim.x) mu[i] = src[i];
+    if (src)
+        for (int i = threadIdx.x; i < nmu; i += blockDim.x) mu[i] = src[i];
     // 1/(2 v_k), 1/v_k; zero beyond K (padded components of a block)
     for (int k = threadIdx.x; k < kMaxK; k += blockDim.x) {
         const bool on = tg.family == kGmm && k < tg.K;
@@ -144,6 +145,12 @@ struct Particle {
         return v;
     }
 
+    // Inside the support (0, box)^2 of the uniform reference (kUnid).
+    static __device__ __forceinline__ bool unid_inside(const TargetDev& tg, const float (&x)[DPL])
+    {
+        return x[0] > 0.f && (double)x[0] < tg.box && x[1] > 0.f && (double)x[1] < tg.box;
+    }
+
     // ell(x) = log gamma(x) - log eta(x); with GRAD also its gradient on this
     // lane's coordinates.  r = lane index inside the group.
     template <bool GRAD>
@@ -152,7 +159,21 @@ struct Particle {
                                                   double (&g)[DPL])
     {
         const ParView pv = fresh(pv0);
-        if constexpr (FAM == kGauss) {
+        if constexpr (FAM == kUnid) {
+            // d = 2 on one lane: the log-likelihood ratio of Binomial(k | n, x y)
+            // against its maximum, log1p forms near the ridge x y = k / n
+            (void)r;
+            (void)c;
+            const double x0 = (double)x[0], x1 = (double)x[1];
+            const double u = x0 * x1;
+            if (GRAD) {
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) g[j] = 0.0;
+            }
+            if (!unid_inside(tg, x) || !(u > 0.0 && u < 1.0)) return -INFINITY;
+            const double n = tg.binom_n, k = tg.binom_k, p = k / n;
+            return k * log1p((u - p) / p) + (n - k) * log1p(-(u - p) / (1.0 - p));
+        } else if constexpr (FAM == kGauss) {
             double ssg = 0.0, sse = 0.0;
 #pragma unroll
             for (int j = 0; j < DPL; ++j) {
@@ -299,7 +320,8 @@ struct Particle {
     // one (particle, step, stream) sequence: block r DPL / 4 + bb of it.
     static __device__ __forceinline__ void normals_block(const RngKey& key, uint32_t n,
                                                          uint32_t t, uint32_t stream, int r,
-                                                         int d, int bb, double (&q)[4])
+                                                         int d, int bb, double (&q)[4],
+                                                         uint32_t substep = 0u)
     {
         static_assert(DPL % 4 == 0, "lane slices are whole blocks of 4 coordinates");
         const int b = r * (DPL / 4) + bb;
@@ -307,7 +329,7 @@ struct Particle {
         for (int u = 0; u < 4; ++u) q[u] = 0.0;
         if (4 * b < d) {
             double w[4];
-            normals4(key, n, t, stream, (uint32_t)b, w);
+            normals4(key, n, t, stream, (uint32_t)b, w, substep);
 #pragma unroll
             for (int u = 0; u < 4; ++u) q[u] = (4 * b + u < d) ? w[u] : 0.0;
         }
@@ -332,6 +354,18 @@ struct Particle {
                                                   int r, float (&x)[DPL], double (&g)[DPL],
                                                   bool grad)
     {
+        if constexpr (FAM == kUnid) {
+            // uniform reference: coordinate i from word i of block 0
+            const uint4 w = draw_block(key, n, 0u, kStreamInit, 0u, 0u);
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) {
+                x[j] = 0.f;
+                g[j] = 0.0;
+            }
+            x[0] = (float)(tg.box * word_uniform(w.x));
+            x[1] = (float)(tg.box * word_uniform(w.y));
+            return eval<false>(tg, c, pv, r, x, g);
+        }
         double z[DPL];
         normals(key, n, 0u, kStreamInit, r, tg.d, z);
 #pragma unroll
@@ -353,8 +387,54 @@ struct Particle {
     {
         // RWMH draws its normals block by block inside the proposal loop
         // (shorter live ranges); MALA and HMC draw them all first
+        if constexpr (MOVE == kRwmh3 || FAM == kUnid) {
+            // random-walk substeps (one for kRwmh, three with standard
+            // deviations eps (0.1, 1, 10) for kRwmh3), each with its own
+            // normals and accept uniform (counter substep j); the decision
+            // reported is whether any substep was accepted
+            constexpr int NS = (MOVE == kRwmh3) ? 3 : 1;
+            bool any = false;
+#pragma unroll
+            for (int sub = 0; sub < NS; ++sub) {
+                const double sd = (MOVE == kRwmh3) ? eps * (sub == 0 ? 0.1 : (sub == 1 ? 1.0 : 10.0))
+                                                   : eps;
+                float xq[DPL];
+                double gq[DPL];
+                double dle = 0.0;
+#pragma unroll
+                for (int bb = 0; bb < DPL / 4; ++bb) {
+                    double q[4];
+                    normals_block(key, n, t, kStreamMove, r, tg.d, bb, q, (uint32_t)sub);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int j = 4 * bb + u;
+                        xq[j] = (float)((double)x[j] + sd * q[u]);
+                        if constexpr (FAM != kUnid) {
+                            const double a = (double)x[j] - ref(pv, r, j);
+                            const double b = (double)xq[j] - ref(pv, r, j);
+                            dle += a * a - b * b;
+                        }
+                    }
+                }
+                const double ellq = eval<false>(tg, c, pv, r, xq, gq);
+                double la;
+                if constexpr (FAM == kUnid)
+                    la = unid_inside(tg, xq) ? beta * (ellq - ell) : -INFINITY;
+                else
+                    la = group_sum<LPP>(dle) * c.half_inv_s2r + beta * (ellq - ell);
+                const uint4 w = draw_block(key, n, t, kStreamAccept, (uint32_t)sub, 0u);
+                const bool acc = (forced >= 0) ? (forced != 0) : (log(word_uniform(w.x)) < la);
+                if (acc) {
+#pragma unroll
+                    for (int j = 0; j < DPL; ++j) x[j] = xq[j];
+                    ell = ellq;
+                }
+                any = any || acc;
+            }
+            return any;
+        }
         double z[DPL];
-        if constexpr (MOVE != kRwmh) normals(key, n, t, kStreamMove, r, tg.d, z);
+        if constexpr (uses_grad(MOVE)) normals(key, n, t, kStreamMove, r, tg.d, z);
         float xp[DPL];
         double gp[DPL];
         double ellp;
@@ -444,7 +524,7 @@ struct Particle {
 #pragma unroll
             for (int j = 0; j < DPL; ++j) {
                 x[j] = xp[j];
-                if (MOVE != kRwmh) g[j] = gp[j];
+                if (uses_grad(MOVE)) g[j] = gp[j];
             }
             ell = ellp;
         }
@@ -470,6 +550,13 @@ struct MinWaves {
     static constexpr int value = DPL <= 8 ? 4 : 1;
 };
 
+// log of w_{t-1} (g_t)^i for a record v = (log w_{t-1}, log g_t): g^0 = 1 also
+// where g = 0 (log g = -inf, a zero likelihood), so i = 0 takes log w alone.
+__device__ __forceinline__ double mom_term(double2 v, int i)
+{
+    return (i == 0) ? v.x : v.x + (double)i * v.y;
+}
+
 // All tiles of one slot of one problem, in tile order (one wave).  The
 // moments of a slot therefore accumulate in the same order whichever wave,
 // kernel or launch processes the slot.
@@ -485,7 +572,7 @@ __device__ __forceinline__ void oais_slot(const SweepArgs& a, const ParView& pv,
     const int pl = lane / LPP;
     const int T = a.T;
     const int d = a.tg.d;
-    const bool grad = (MOVE != kRwmh);
+    const bool grad = uses_grad(MOVE);
 
     // Fold TC buffered steps of this tile into the slot's accumulators.  For
     // the final entry (fin) the fourth field keeps the largest log w instead
@@ -503,7 +590,7 @@ __device__ __forceinline__ void oais_slot(const SweepArgs& a, const ParView& pv,
                 if (p < P) {
                     const double2 v = rec[tcl][p];
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) m[i] = fmax(m[i], v.x + (double)i * v.y);
+                    for (int i = 0; i < 3; ++i) m[i] = fmax(m[i], mom_term(v, i));
                 }
             }
 #pragma unroll
@@ -513,7 +600,7 @@ __device__ __forceinline__ void oais_slot(const SweepArgs& a, const ParView& pv,
                     const double2 v = rec[tcl][p];
 #pragma unroll
                     for (int i = 0; i < 3; ++i)
-                        if (m[i] > -INFINITY) s[i] += exp(v.x + (double)i * v.y - m[i]);
+                        if (m[i] > -INFINITY) s[i] += exp(mom_term(v, i) - m[i]);
                 }
             }
         }
@@ -694,13 +781,13 @@ __global__ void __launch_bounds__(256) k_asmc_init(SweepArgs a, AsmcState z)
     float x[DPL];
     double g[DPL];
     const double ell = Particle<FAM, LPP, DPL>::init(a.tg, c, pv, a.key, (uint32_t)n64, r, x, g,
-                                                     MOVE != kRwmh);
+                                                     uses_grad(MOVE));
 #pragma unroll
     for (int j = 0; j < DPL; ++j) {
         const int i = r * DPL + j;
         if (i < a.tg.d) {
             z.X[(size_t)n64 * a.tg.d + i] = x[j];
-            if (MOVE != kRwmh) z.G[(size_t)n64 * a.tg.d + i] = g[j];
+            if (uses_grad(MOVE)) z.G[(size_t)n64 * a.tg.d + i] = g[j];
         }
     }
     if (r == 0) {
@@ -714,6 +801,7 @@ template <int FAM, int MOVE, int LPP, int DPL>
 __global__ void __launch_bounds__(256, MinWaves<DPL>::value)
     k_asmc_step(SweepArgs a, AsmcState z, int t)
 {
+    if (a.t_stop && t > *a.t_stop) return;  // an online schedule already reached beta = 1
     constexpr int P = kWave / LPP;
     extern __shared__ __align__(16) char sh_dyn[];
     const ParView pv = stage_params_lanes<LPP, DPL>(a.tg, sh_dyn);
@@ -734,7 +822,7 @@ __global__ void __launch_bounds__(256, MinWaves<DPL>::value)
     for (int j = 0; j < DPL; ++j) {
         const int i = r * DPL + j;
         x[j] = (i < d) ? z.X[(size_t)nl * d + i] : 0.f;
-        g[j] = (MOVE != kRwmh && i < d) ? z.G[(size_t)nl * d + i] : 0.0;
+        g[j] = (uses_grad(MOVE) && i < d) ? z.G[(size_t)nl * d + i] : 0.0;
     }
     double ell = z.ell[nl];
     double lw = z.lw[nl];
@@ -776,7 +864,7 @@ __global__ void __launch_bounds__(256, MinWaves<DPL>::value)
             const int i = r * DPL + j;
             if (i < d) {
                 z.X[(size_t)n64 * d + i] = x[j];
-                if (MOVE != kRwmh) z.G[(size_t)n64 * d + i] = g[j];
+                if (uses_grad(MOVE)) z.G[(size_t)n64 * d + i] = g[j];
             }
         }
         if (r == 0) {
@@ -827,7 +915,7 @@ __global__ void __launch_bounds__(256) k_rejuv(RejuvArgs R)
         x[j] = (i < d) ? R.x_in[(size_t)src * d + i] : 0.f;
         g[j] = 0.0;
     }
-    double ell = (MOVE != kRwmh) ? Particle<FAM, LPP, DPL>::template eval<true>(a.tg, c, pv, r, x, g)
+    double ell = uses_grad(MOVE) ? Particle<FAM, LPP, DPL>::template eval<true>(a.tg, c, pv, r, x, g)
                                  : Particle<FAM, LPP, DPL>::template eval<false>(a.tg, c, pv, r, x, g);
     double s1[DPL], s2[DPL];
 #pragma unroll
@@ -934,6 +1022,7 @@ hipError_t valu_dispatch(int what, const SweepArgs& a, const ValuShape& s, int g
         return Launch<FAM, MOVE, L, D>::step(a, *z, t, st);                  \
     }
     OASMC_CASE(1, 4)
+    if constexpr (FAM == kUnid) return hipErrorInvalidValue;  // d = 2: one lane of 4 only
     OASMC_CASE(1, 8)
     OASMC_CASE(1, 12)
     OASMC_CASE(1, 16)
