@@ -409,10 +409,15 @@ def extra_workload(args, oa, wl, torch) -> int:
         cpu_what = ("the last round of problems {g0} (Gaussian) and {l0} (logistic regression) "
                     "on the first {n} particles each")
         cpu_steps = lambda n: n * (specs[g0]["T"] + specs[l0]["T"])
+    if args.autotune:
+        oa.autotune(1)
+        cfg["autotune"] = True
     oa.profile(True)
     for i in range(args.warmup):
         run(i)
     torch.cuda.synchronize()
+    if args.autotune:
+        cfg["autotuned_classes"] = oa.autotune(1)
     oa.profile(True)  # totals cleared: the timed region only
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -459,6 +464,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="logreg",
                     choices=sorted(WORKLOADS) + ["grad", "rejuv", "batch", "batch_seq", "zja"])
+    ap.add_argument("--autotune", action="store_true",
+                    help="measure the VALU sweeps' launch shapes per problem class first (batch)")
     ap.add_argument("--zja-rounds", type=int, default=10,
                     help="OAIS rounds of the zja workload (T doubles from 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

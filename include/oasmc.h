@@ -215,6 +215,27 @@ int oasmc_adapt_schedule(int32_t T, const double* beta, const double* log_g, int
                          int32_t interp, double* beta_new, double* Lambda_hat);
 
 /*
+ * Launch-shape autotuning of the loop-swapped sweeps of the Gaussian and
+ * mixture families (AIS passes of oasmc_asmc, oasmc_run and oasmc_run_batch):
+ * a particle spans LPP lanes of DPL coordinates.  enable = 1: the first pass of
+ * a problem class (family, move, d, N rounded up to a power of two, HMC's
+ * leapfrog steps, K) times every built shape that holds d on a 4-step pass of the problem
+ * itself (two runs each, HIP events) and keeps the fastest (the fixed rule's
+ * shape unless another is 2% faster) in the handle; later passes of the class
+ * reuse it.  enable = 0: the fixed rule.  enable = -1: the fixed rule and the
+ * measured shapes are forgotten.  *n_classes (may be NULL) gets the number of
+ * classes measured.  Results depend on the shape only through the binary64
+ * summation order of a particle's lanes.  Not for use under graph capture (the
+ * measurement synchronises its stream).
+ */
+int oasmc_autotune(oasmc_handle* h, int32_t enable, int32_t* n_classes);
+
+/* The shape (lanes per particle, coordinates per lane) the next AIS pass of
+ * this problem would use, measuring it first when autotuning is on. */
+int oasmc_shape(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel* kernel,
+                int64_t N, int32_t* lpp, int32_t* dpl, void* stream);
+
+/*
  * Deterministic adaptive resampling (DAR) times for a new schedule, predicted
  * from a previous round (Sec. "Effective resample size for deterministic
  * adaptive resampling", eq. (DAR-times); AR converges to DAR as N grows, by the

@@ -113,6 +113,8 @@ def _load():
     L.oasmc_run_batch.argtypes = [vp, C.POINTER(_BatchProblem), C.c_int32, C.c_int32, C.c_int32,
                                   C.POINTER(_BatchOut), vp]
     L.oasmc_logreg_eval.argtypes = [vp, C.POINTER(_Problem), C.c_int64, vp, vp, vp, vp]
+    L.oasmc_autotune.argtypes = [vp, C.c_int32, vp]
+    L.oasmc_shape.argtypes = [vp, C.POINTER(_Problem), C.POINTER(_Kernel), C.c_int64, vp, vp, vp]
     L.oasmc_zja.argtypes = [vp, C.POINTER(_Problem), C.POINTER(_Kernel), C.c_int64, C.c_double,
                             C.c_int32, C.c_int32, C.c_double, C.c_uint64, C.c_uint32, C.c_uint32,
                             vp, vp, vp, vp, vp, vp, vp]
@@ -125,7 +127,7 @@ def _load():
               "oasmc_dar_times",
               "oasmc_run", "oasmc_resample", "oasmc_resample_noalloc", "oasmc_philox", "oasmc_logreg_eval",
               "oasmc_profile", "oasmc_logZ_backward", "oasmc_run_batch", "oasmc_rejuvenate",
-              "oasmc_zja"):
+              "oasmc_zja", "oasmc_autotune", "oasmc_shape"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -331,6 +333,26 @@ def run(problem: Problem, N1: int, rounds: int, seed: int, problem_id: int = 0, 
     if rejuvenate:
         r["rejuv_mean"], r["rejuv_second"] = rj_m, rj_s
     return r
+
+
+def autotune(enable: int, device: int = 0) -> int:
+    """Launch-shape autotuning of the VALU sweeps on (1) or off (0); -1 also
+    forgets the measured shapes.  Returns the number of classes measured."""
+    n = C.c_int32(0)
+    _check(_load().oasmc_autotune(_handle(device), int(enable), C.c_void_p(C.addressof(n))))
+    return n.value
+
+
+def shape(problem: Problem, N: int, move="rwmh", leapfrog: int = 5) -> tuple:
+    """(lanes per particle, coordinates per lane) of the next AIS pass of ``problem``."""
+    dev = problem.device
+    lpp, dpl = C.c_int32(0), C.c_int32(0)
+    P = problem.c()
+    K = _kernel(move, leapfrog, False, "ess", 0.5)
+    _check(_load().oasmc_shape(_handle(dev.index or 0), C.byref(P), C.byref(K), int(N),
+                               C.c_void_p(C.addressof(lpp)), C.c_void_p(C.addressof(dpl)),
+                               _stream(dev)))
+    return lpp.value, dpl.value
 
 
 def zja(problem: Problem, N: int, rho: float, Tmax: int, eps: float, seed: int, move="rwmh3",

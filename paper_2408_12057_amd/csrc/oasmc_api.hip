@@ -6,7 +6,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <map>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -83,6 +85,10 @@ struct oasmc_handle_s {
     std::vector<hipEvent_t> evpool;  // event pairs around the sweeps of each round
     double prof_ms = 0.0, prof_steps = 0.0, prof_flops = 0.0;
     int64_t prof_launches = 0;
+    // measured launch shapes of the loop-swapped VALU sweep, per problem class
+    // (family, move, d, N rounded up to a power of two, leapfrog, K)
+    bool autotune = false;
+    std::map<std::array<int64_t, 6>, ValuShape> tuned;
 
     // Returns a device buffer of at least `bytes` in slot `id` (grow-only).
     hipError_t get(int id, size_t bytes, void** out)
@@ -371,6 +377,89 @@ int dar_times_impl(int T, const double* beta, const double* log_g, int Tn,
             sum = 0.0;
         }
     }
+    return OASMC_OK;
+}
+
+// Shapes (lanes per particle, coordinates per lane) the VALU sweeps are built
+// for; a shape holds d when LPP DPL >= d.
+const ValuShape kShapes[] = {{1, 4}, {1, 8}, {1, 12}, {1, 16}, {1, 20}, {1, 24}, {2, 16},
+                             {4, 8}, {4, 16}, {8, 8}, {8, 16}, {16, 8}, {16, 16}};
+
+// The launch shape of a loop-swapped VALU sweep.  Without autotuning the
+// fixed rule of valu_shape; with it, the shape measured fastest for the
+// problem's class: every shape that holds d runs the same short pass (4 steps,
+// uniform schedule, all N particles up to 2^20) on the problem itself, twice,
+// timed with HIP events; the fastest per particle-step is kept in the handle.
+// Results do not depend on the shape except through binary64 summation order
+// across a particle's lanes.
+int pick_shape(oasmc_handle* h, const oasmc_problem* p, const oasmc_kernel* k, int64_t N,
+               ValuShape* s, hipStream_t st)
+{
+    if (!valu_shape(p->d, N, s)) return fail(OASMC_EUNSUPPORTED, "no kernel shape for d=%d", p->d);
+    if (!h->autotune || p->family == OASMC_UNID) return OASMC_OK;
+    int64_t nb = 1;
+    while (nb < N) nb <<= 1;
+    // leapfrog steps matter only to HMC
+    const std::array<int64_t, 6> key{p->family, k->move, p->d, nb,
+                                     k->move == OASMC_HMC ? k->leapfrog : 0, p->K};
+    auto it = h->tuned.find(key);
+    if (it != h->tuned.end()) {
+        *s = it->second;
+        return OASMC_OK;
+    }
+    const int T = 4;
+    const int64_t Nt = std::min<int64_t>(N, (int64_t)1 << 20);
+    std::vector<double> bh(T + 1), eh(T, 0.1);
+    for (int t = 0; t <= T; ++t) bh[t] = (double)t / T;
+    double *db, *de;
+    HIP_TRY(wget(h, B_BETA, T + 1, &db));
+    HIP_TRY(wget(h, B_EPS, T, &de));
+    HIP_TRY(hipMemcpyAsync(db, bh.data(), sizeof(double) * (T + 1), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(de, eh.data(), sizeof(double) * T, hipMemcpyHostToDevice, st));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const ValuShape rule = *s;
+    ValuShape best = rule;
+    float best_ms = 1e30f;
+    std::vector<ValuShape> cands{rule};  // the rule's shape first: it wins near ties
+    for (const ValuShape& c : kShapes)
+        if (c.lpp * c.dpl >= p->d && !(c.lpp == rule.lpp && c.dpl == rule.dpl)) cands.push_back(c);
+    for (const ValuShape& c : cands) {
+        SweepArgs a{};
+        a.tg = target_dev(p);
+        a.move = k->move;
+        a.leapfrog = k->leapfrog;
+        a.N = Nt;
+        a.T = T;
+        a.beta = db;
+        a.eps = de;
+        a.key.k0 = 0x7E57u;
+        a.ntiles = valu_tiles(Nt, c);
+        a.S = slot_count(a.ntiles, 0);
+        double* part;
+        HIP_TRY(wget(h, B_PART, (size_t)a.S * (T + 1) * 4, &part));
+        a.part = part;
+        const int gw = (int)std::min<int64_t>(a.S, (int64_t)h->cus * 8);
+        float ms = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+            HIP_TRY(hipEventRecord(e0, st));
+            HIP_TRY(launch_oais_valu(a, c, gw, st));
+            HIP_TRY(hipEventRecord(e1, st));
+            HIP_TRY(hipEventSynchronize(e1));
+            float m = 0.f;
+            HIP_TRY(hipEventElapsedTime(&m, e0, e1));
+            ms = std::min(ms, m);
+        }
+        if (ms < best_ms * 0.98f) {  // a candidate must beat the best so far by 2%
+            best_ms = ms;
+            best = c;
+        }
+    }
+    HIP_TRY(hipEventDestroy(e0));
+    HIP_TRY(hipEventDestroy(e1));
+    h->tuned[key] = best;
+    *s = best;
     return OASMC_OK;
 }
 
@@ -740,7 +829,7 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
 }
 
 // Fills the derived fields of a problem; returns a status.
-int prepare_dev_problem(oasmc_handle* h, DevProblem& q)
+int prepare_dev_problem(oasmc_handle* h, DevProblem& q, hipStream_t st)
 {
     int s = check_problem(&q.prob, &q.kern);
     if (s) return s;
@@ -757,7 +846,8 @@ int prepare_dev_problem(oasmc_handle* h, DevProblem& q)
         q.shape = ValuShape{0, 0};
         q.ntiles = logreg_tiles(q.N);
     } else {
-        if (!valu_shape(q.prob.d, q.N, &q.shape)) return fail(OASMC_EUNSUPPORTED, "no kernel for d=%d", q.prob.d);
+        const int ps = pick_shape(h, &q.prob, &q.kern, q.N, &q.shape, st);
+        if (ps) return ps;
         q.kh = 0;
         q.ntiles = valu_tiles(q.N, q.shape);
     }
@@ -804,6 +894,34 @@ int oasmc_handle_destroy(oasmc_handle* h)
     for (auto& b : h->bufs)
         if (b.p) hipFree(b.p);
     delete h;
+    return OASMC_OK;
+}
+
+int oasmc_autotune(oasmc_handle* h, int32_t enable, int32_t* n_classes)
+{
+    if (!h) return fail(OASMC_EINVAL, "handle is NULL");
+    h->autotune = enable > 0;
+    if (enable < 0) h->tuned.clear();
+    if (n_classes) *n_classes = (int32_t)h->tuned.size();
+    g_err.clear();
+    return OASMC_OK;
+}
+
+int oasmc_shape(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel* kernel,
+                int64_t N, int32_t* lpp, int32_t* dpl, void* stream)
+{
+    if (!h || !lpp || !dpl) return fail(OASMC_EINVAL, "NULL argument");
+    int s = check_problem(problem, kernel);
+    if (s) return s;
+    if (problem->family == OASMC_LOGREG) return fail(OASMC_EUNSUPPORTED, "no VALU shape for logistic regression");
+    if (N < 1) return fail(OASMC_EINVAL, "N must be >= 1");
+    HIP_TRY(hipSetDevice(h->device));
+    ValuShape sh{};
+    s = pick_shape(h, problem, kernel, N, &sh, (hipStream_t)stream);
+    if (s) return s;
+    *lpp = sh.lpp;
+    *dpl = sh.dpl;
+    g_err.clear();
     return OASMC_OK;
 }
 
@@ -889,8 +1007,8 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
                             h->lds_per_block, logreg_shared_bytes());
             ntiles = logreg_tiles(N);
         } else {
-            if (!valu_shape(problem->d, N, &shape))
-                return fail(OASMC_EUNSUPPORTED, "no kernel shape for d=%d", problem->d);
+            const int ps = pick_shape(h, problem, kernel, N, &shape, st);
+            if (ps) return ps;
             ntiles = valu_tiles(N, shape);
         }
         const int64_t S = slot_count(ntiles, kernel->slots);
@@ -1460,7 +1578,7 @@ extern "C" int oasmc_run(oasmc_handle* h, const oasmc_problem* problem, const oa
         q.accept_target = opts->accept_target;
         q.seed = seed;
         q.problem_id = problem_id;
-        int st = prepare_dev_problem(h, q);
+        int st = prepare_dev_problem(h, q, (hipStream_t)stream);
         if (st) return st;
         HIP_TRY(hipSetDevice(h->device));
         std::vector<DevProblem> ps{q};
@@ -1618,7 +1736,7 @@ extern "C" int oasmc_run_batch(oasmc_handle* h, const oasmc_batch_problem* probs
         q.accept_target = b.accept_target;
         q.seed = b.seed;
         q.problem_id = b.problem_id;
-        const int st = prepare_dev_problem(h, q);
+        const int st = prepare_dev_problem(h, q, (hipStream_t)stream);
         if (st) {
             std::string m = g_err;
             return fail(st, "problem %d: %s", p, m.c_str());
