@@ -127,6 +127,10 @@ def _declare(L):
                           C.c_int, C.c_double, C.c_uint64, C.c_uint32, C.c_uint32, _dp,
                           C.POINTER(C.c_int), _dp, _dp, _dp, _dp]
     L.orc_zja.restype = C.c_int
+    L.orc_pt.argtypes = [C.POINTER(_Problem), C.POINTER(_Opts), C.c_int, C.c_int, C.c_int, _dp,
+                         _dp, C.c_uint64, C.c_uint32, C.c_uint32, _dp, _dp, _dp,
+                         C.POINTER(C.c_int64), _dp, _dp]
+    L.orc_pt.restype = C.c_int
 
 
 def _f64(a) -> np.ndarray:
@@ -327,6 +331,28 @@ def zja(problem: Problem, opts: Opts, N: int, rho: float, Tmax: int, eps: float,
     Tv = T.value
     return dict(status=st, T=Tv, beta=beta[:Tv + 1], log_g=lg.reshape(3, Tmax)[:, :Tv],
                 logZ=lz.value, lw=lw, x=x.reshape(N, d))
+
+
+def pt(problem: Problem, opts: Opts, K: int, beta, eps, Tp: int, seed: int, round_k: int = 1,
+       problem_id: int = 0) -> dict:
+    """Parallel tempering (K copies of N'+1 chains, T' iterations, even/odd swaps):
+    logZ (stepping stone), ss [N'], rej [N'] (swap rejection per pair), Lambda_PT,
+    round trips, tmean / tsecond [d] (target chain)."""
+    beta = _f64(beta)
+    Np = beta.shape[0] - 1
+    eps = _f64(np.broadcast_to(np.asarray(eps, dtype=np.float64), (Np + 1,)))
+    d = problem.d
+    ss, rej = np.zeros(Np), np.zeros(Np)
+    tm, ts = np.zeros(d), np.zeros(d)
+    lz = C.c_double(0.0)
+    trips = C.c_int64(0)
+    P = problem.c()
+    O = opts.c()
+    st = lib().orc_pt(C.byref(P), C.byref(O), K, Np, Tp, _ptr(beta), _ptr(eps), seed, round_k,
+                      problem_id, C.cast(C.byref(lz), _dp), _ptr(ss), _ptr(rej), C.byref(trips),
+                      _ptr(tm), _ptr(ts))
+    return dict(status=st, logZ=lz.value, ss=ss, rej=rej, Lambda_PT=float(np.sum(rej)),
+                trips=trips.value, tmean=tm, tsecond=ts)
 
 
 def ell(problem: Problem, x) -> tuple:

@@ -928,6 +928,148 @@ int orc_zja(const orc_problem* P, const orc_opts* O, int64_t N, double rho, int 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Parallel tempering through computational duality.                         */
+/* ------------------------------------------------------------------------ */
+/*
+ * PT (Sec. "Computational duality with parallel tempering"): K independent
+ * copies, each of N' + 1 chains jointly targeting pi_{beta_0} x ... x
+ * pi_{beta_N'}, run for T' iterations.  Reading (the section gives the
+ * estimators; the swap scheme is that of non-reversible PT, deterministic even
+ * and odd swaps): every chain (a replica r of copy k, global index
+ * k (N' + 1) + r) starts from eta; iteration t applies the forward kernel at the
+ * replica's current temperature (counters (replica, t), step size eps[n] of
+ * temperature n), then proposes swaps of the replicas at temperatures
+ * (n, n + 1) for every n of the parity of t (even t: n = 0, 2, ...), accepted
+ * iff log u < (beta_{n+1} - beta_n)(ell(y at n) - ell(y at n+1)), u from
+ * stream 4 with counter (k (N' + 1) + n, t).  Swaps exchange temperatures, not
+ * states.  After iteration t:
+ *   - the stepping stone terms (beta_n - beta_{n-1}) ell(Y^{n-1}_t), n = 1..N',
+ *     pooled over copies: log Z_PT = sum_n [logsumexp_{k,t}(...) - log(K T')]
+ *     (eq. (Z_PT) with the K T' samples of each temperature);
+ *   - the swap rejection 1 - min(1, alpha) of each proposed pair, averaged per
+ *     pair into r_n (Lambda_PT estimate = sum_n r_n);
+ *   - round trips: a replica that reached temperature N' after its last visit
+ *     to 0 completes one when it returns to 0;
+ *   - x_i and x_i^2 of the replica at temperature N' (the target chain).
+ * Outputs: *logZ, ss[N'] (the per-temperature log-means), rej[N'], trips (total
+ * over copies), tmean[d], tsecond[d] (averages over K T' target-chain states).
+ */
+#define STREAM_SWAP 4u
+int orc_pt(const orc_problem* P, const orc_opts* O, int K, int Np, int Tp, const double* beta,
+           const double* eps, uint64_t seed, uint32_t round_k, uint32_t problem_id, double* logZ,
+           double* ss, double* rej, int64_t* trips, double* tmean, double* tsecond)
+{
+    if (!P || !O || K < 1 || Np < 1 || Tp < 1 || !beta || !eps || !logZ || !ss || !rej)
+        return ORC_EINVAL;
+    if (beta[0] != 0.0 || beta[Np] != 1.0) return ORC_EINVAL;
+    for (int n = 1; n <= Np; ++n)
+        if (!(beta[n] > beta[n - 1])) return ORC_EINVAL;
+    int d = P->d, R = Np + 1;
+    rng_key Kk = {seed, round_k, problem_id};
+    if (O->nthreads > 0) omp_set_num_threads(O->nthreads);
+    /* per copy: stepping-stone terms [Np][Tp], rejection sums [Np], counts [Np],
+     * round trips, target sums [d] x 2 */
+    double* terms = (double*)malloc(sizeof(double) * (size_t)K * Np * Tp);
+    double* rsum = (double*)calloc((size_t)K * Np, sizeof(double));
+    int64_t* rcnt = (int64_t*)calloc((size_t)K * Np, sizeof(int64_t));
+    int64_t* rt = (int64_t*)calloc((size_t)K, sizeof(int64_t));
+    double* f1 = (double*)calloc((size_t)K * d, sizeof(double));
+    double* f2 = (double*)calloc((size_t)K * d, sizeof(double));
+    int status = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < K; ++k) {
+        double* X = (double*)malloc(sizeof(double) * (size_t)R * d);
+        double* G = (double*)malloc(sizeof(double) * (size_t)R * d);
+        double* L = (double*)malloc(sizeof(double) * R);
+        double* work = (double*)malloc(sizeof(double) * 6 * d);
+        int* tau = (int*)malloc(sizeof(int) * R);   /* temperature of replica r */
+        int* rep = (int*)malloc(sizeof(int) * R);   /* replica at temperature n */
+        int* side = (int*)malloc(sizeof(int) * R);  /* 0: last extreme 0, 1: reached N' since */
+        for (int r = 0; r < R; ++r) {
+            particle p = {X + (size_t)r * d, 0.0, G + (size_t)r * d};
+            init_particle(P, O, &Kk, (uint32_t)(k * R + r), &p, work);
+            L[r] = p.ell;
+            tau[r] = r;
+            rep[r] = r;
+            side[r] = (r == 0) ? 0 : -1;
+        }
+        for (int t = 1; t <= Tp; ++t) {
+            for (int r = 0; r < R; ++r) {
+                particle p = {X + (size_t)r * d, L[r], G + (size_t)r * d};
+                int n = tau[r];
+                mh_step(P, O, &Kk, (uint32_t)(k * R + r), (uint32_t)t, beta[n], eps[n], &p, work,
+                        NULL, -1);
+                L[r] = p.ell;
+            }
+            for (int n = (t % 2 == 0) ? 0 : 1; n + 1 < R; n += 2) {
+                int a = rep[n], b = rep[n + 1];
+                double la = (beta[n + 1] - beta[n]) * (L[a] - L[b]);
+                double u = draw_uniform(&Kk, (uint32_t)(k * R + n), (uint32_t)t, STREAM_SWAP, 0);
+                double acc = (la >= 0.0) ? 1.0 : exp(la);
+                if (la != la) acc = 0.0;
+                rsum[(size_t)k * Np + n] += 1.0 - acc;
+                rcnt[(size_t)k * Np + n] += 1;
+                if (log(u) < la) {
+                    rep[n] = b;
+                    rep[n + 1] = a;
+                    tau[a] = n + 1;
+                    tau[b] = n;
+                }
+            }
+            for (int r = 0; r < R; ++r) {
+                if (tau[r] == Np && side[r] == 0) side[r] = 1;
+                if (tau[r] == 0) {
+                    if (side[r] == 1) rt[k] += 1;
+                    side[r] = 0;
+                }
+            }
+            for (int n = 1; n <= Np; ++n)
+                terms[((size_t)k * Np + (n - 1)) * Tp + (t - 1)] =
+                    (beta[n] - beta[n - 1]) * L[rep[n - 1]];
+            const double* y = X + (size_t)rep[Np] * d;
+            for (int i = 0; i < d; ++i) {
+                f1[(size_t)k * d + i] += y[i];
+                f2[(size_t)k * d + i] += y[i] * y[i];
+            }
+        }
+        free(X); free(G); free(L); free(work); free(tau); free(rep); free(side);
+    }
+    double lz = 0.0;
+    double* col = (double*)malloc(sizeof(double) * (size_t)K * Tp);
+    for (int n = 0; n < Np; ++n) {
+        for (int k = 0; k < K; ++k)
+            memcpy(col + (size_t)k * Tp, terms + ((size_t)k * Np + n) * Tp, sizeof(double) * Tp);
+        ss[n] = logsumexp(col, (int64_t)K * Tp, 1) - log((double)K * Tp);
+        lz += ss[n];
+        double a = 0.0;
+        int64_t c = 0;
+        for (int k = 0; k < K; ++k) {
+            a += rsum[(size_t)k * Np + n];
+            c += rcnt[(size_t)k * Np + n];
+        }
+        rej[n] = c > 0 ? a / (double)c : NAN;
+    }
+    *logZ = lz;
+    if (trips) {
+        int64_t tot = 0;
+        for (int k = 0; k < K; ++k) tot += rt[k];
+        *trips = tot;
+    }
+    for (int i = 0; tmean && tsecond && i < d; ++i) {
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < K; ++k) {
+            a += f1[(size_t)k * d + i];
+            b += f2[(size_t)k * d + i];
+        }
+        tmean[i] = a / ((double)K * Tp);
+        tsecond[i] = b / ((double)K * Tp);
+    }
+    if (!isfinite(lz)) status = ORC_ENONFINITE;
+    free(col); free(terms); free(rsum); free(rcnt); free(rt); free(f1); free(f2);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Final-iteration rejuvenation (Sec. "Computing expectations").             */
 /* ------------------------------------------------------------------------ */
 /*
