@@ -303,6 +303,72 @@ def zja_workload(args, oa, torch) -> int:
     return 0
 
 
+def pt_workload(args, oa, wl, torch) -> int:
+    """Parallel tempering through the duality (Sec. "Computational duality with
+    parallel tempering") on the d = 10 Gaussian target: K = 2048 copies of
+    N' + 1 = 64 chains (one wave per copy) on the schedule Alg. 3 builds from an
+    OAIS round, T' = 64 iterations of RWMH plus even/odd swaps.  One step = one
+    PT run; value = chain-steps/s; the stepping-stone log Z error over seeds
+    against the closed form, Lambda_PT and the round-trip rate beside it."""
+    import oracle as orc
+
+    w = wl.gaussian_d10()
+    prob = oa.Problem.gauss(w.params["mu"], w.params["sigma2"], w.ref_sigma2)
+    K, Np, Tp = 2048, 63, 64
+    r0 = oa.run(prob, 1024, 2, seed=args.seed, move="rwmh", budget="fixed", T1=64, eps0=w.eps0)
+    beta, _ = oa.adapt_schedule(r0["beta"][1], r0["log_g"][1], Np)
+    eps = np.full(Np + 1, w.eps0)
+    for i in range(args.warmup):
+        oa.pt(prob, K, beta, eps, Tp, args.seed + i)
+    torch.cuda.synchronize()
+    oa.profile(True)
+    t0 = time.perf_counter()
+    outs = [oa.pt(prob, K, beta, eps, Tp, args.seed + 100 + i) for i in range(args.steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = oa.profile(False)
+    steps = float(K * (Np + 1) * Tp)
+    ref = 5 * np.log(np.pi / 2)
+    lz = np.array([o["logZ"] for o in outs])
+    rej = outs[0]["rej"]
+    rate = prof["particle_steps"] / (prof["kernel_ms"] * 1e-3)
+    peak = PEAK_LANE_CYCLES / ALU_WORK["gauss"]
+    line = {"metric": METRIC, "value": steps * args.steps / el, "unit": "particle-steps/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32 state / f64 arithmetic and weights",
+            "data": "synthetic",
+            "config": {"workload": "gauss_d10_rwmh_parallel_tempering", "copies": K,
+                       "chains_per_copy": Np + 1, "iterations": Tp},
+            "logZ_error": {"seeds": int(len(lz)), "reference": float(ref),
+                           "reference_kind": "closed form",
+                           "rmse": float(np.sqrt(np.mean((lz - ref) ** 2))),
+                           "mean_error": float(np.mean(lz - ref))},
+            "pt": {"Lambda_PT": float(np.sum(rej)),
+                   "round_trips_per_copy_iteration": outs[0]["trips"] / (K * Tp),
+                   "nrpt_rate_from_rejections": float(1 / (2 + 2 * np.sum(rej / (1 - rej))))},
+            "roofline": {"bound": "alu", "achieved": rate, "peak": peak, "unit": "particle-steps/s",
+                         "frac": rate / peak, "traffic": None, "kernel": "k_pt",
+                         "work_lane_cycles_per_particle_step": ALU_WORK["gauss"],
+                         "avg_launch_ms": prof["kernel_ms"] / max(prof["launches"], 1),
+                         "launches": prof["launches"]},
+            "cpu_baseline": None}
+    if not args.no_cpu_baseline:
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        P = orc.Problem(family=orc.FAM_GAUSS, d=w.d, mu=w.params["mu"], sigma2=w.params["sigma2"],
+                        ref_sigma2=w.ref_sigma2)
+
+        def go(m):
+            orc.pt(P, orc.Opts(move=orc.MOVE_RWMH, state_f32=1, nthreads=cores), m, beta, eps, Tp,
+                   args.seed)
+        m, dt = oracle_rate(go, cores, K)
+        line["cpu_baseline"] = {"value": m * (Np + 1) * Tp / dt, "unit": "particle-steps/s",
+                                "cores": cores, "kind": "oracle",
+                                "sample": f"{m} copies x {Np + 1} chains x {Tp} iterations, {dt:.1f} s"}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def extra_workload(args, oa, wl, torch) -> int:
     """The gradient (mixture d = 20, K = 4, N = 8192, T = 256 MALA, checkpoints
     every 16), final-iteration rejuvenation (N = 2^20 chains of 64 RWMH steps on
@@ -463,7 +529,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="logreg",
-                    choices=sorted(WORKLOADS) + ["grad", "rejuv", "batch", "batch_seq", "zja"])
+                    choices=sorted(WORKLOADS) + ["grad", "rejuv", "batch", "batch_seq", "zja",
+                                                 "pt"])
     ap.add_argument("--autotune", action="store_true",
                     help="measure the VALU sweeps' launch shapes per problem class first (batch)")
     ap.add_argument("--zja-rounds", type=int, default=10,
@@ -500,6 +567,8 @@ def main() -> int:
         return 0
     if args.workload == "zja":
         return zja_workload(args, oa, torch)
+    if args.workload == "pt":
+        return pt_workload(args, oa, wl, torch)
     if args.workload in ("grad", "rejuv", "batch", "batch_seq"):
         return extra_workload(args, oa, wl, torch)
     spec = WORKLOADS[args.workload](oa, wl)

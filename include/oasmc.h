@@ -181,6 +181,31 @@ int oasmc_zja(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel*
               double* lw, float* x, void* stream);
 
 /*
+ * Parallel tempering (Sec. "Computational duality with parallel tempering"):
+ * K independent copies of Np + 1 chains at the temperatures beta[0..Np] (host,
+ * 0 = beta_0 < ... < beta_Np = 1) with step sizes eps[0..Np] (host), run for
+ * Tp iterations.  Every chain starts from eta; iteration t applies the kernel's
+ * move at each chain's temperature (counters (copy (Np + 1) + replica, t)) and
+ * then proposes the swaps of temperatures (n, n + 1) for the n of the parity of
+ * t (non-reversible, deterministic even/odd), accepted iff
+ * log u < (beta_{n+1} - beta_n)(ell(y at n) - ell(y at n + 1)) with u from stream
+ * 4, counter (copy (Np + 1) + n, t).  One workgroup per copy; a copy holds at
+ * most 16 waves of chains.  Outputs (host; each but logZ may be NULL):
+ * *logZ = sum_n ss[n], ss[n] the log of the mean of
+ * exp((beta_{n+1} - beta_n) ell) over the K Tp states at temperature n (the
+ * stepping-stone estimator eq. (Z_PT), pooled over copies); rej[n] the mean
+ * swap rejection 1 - min(1, alpha) of pair (n, n + 1), whose sum estimates the
+ * communication barrier Lambda_PT; *trips the round trips (temperature 0 to Np
+ * and back) of all replicas; tmean[d], tsecond[d] the averages of x_i and x_i^2
+ * over the K Tp states at temperature Np.  Gaussian, mixture and Unid families.
+ * Synchronises `stream`.
+ */
+int oasmc_pt(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel* kernel, int32_t K,
+             int32_t Np, int32_t Tp, const double* beta, const double* eps, uint64_t seed,
+             uint32_t round_k, uint32_t problem_id, double* logZ, double* ss, double* rej,
+             int64_t* trips, double* tmean, double* tsecond, void* stream);
+
+/*
  * Final-iteration rejuvenation (Sec. "Computing expectations"): after a pass,
  * resample its final population (log-weights lw[N], states x[N*d], both
  * device, e.g. oasmc_round_out.lw / .x) with the systematic resampler and the

@@ -113,6 +113,9 @@ def _load():
     L.oasmc_run_batch.argtypes = [vp, C.POINTER(_BatchProblem), C.c_int32, C.c_int32, C.c_int32,
                                   C.POINTER(_BatchOut), vp]
     L.oasmc_logreg_eval.argtypes = [vp, C.POINTER(_Problem), C.c_int64, vp, vp, vp, vp]
+    L.oasmc_pt.argtypes = [vp, C.POINTER(_Problem), C.POINTER(_Kernel), C.c_int32, C.c_int32,
+                           C.c_int32, vp, vp, C.c_uint64, C.c_uint32, C.c_uint32, vp, vp, vp, vp,
+                           vp, vp, vp]
     L.oasmc_autotune.argtypes = [vp, C.c_int32, vp]
     L.oasmc_shape.argtypes = [vp, C.POINTER(_Problem), C.POINTER(_Kernel), C.c_int64, vp, vp, vp]
     L.oasmc_zja.argtypes = [vp, C.POINTER(_Problem), C.POINTER(_Kernel), C.c_int64, C.c_double,
@@ -127,7 +130,7 @@ def _load():
               "oasmc_dar_times",
               "oasmc_run", "oasmc_resample", "oasmc_resample_noalloc", "oasmc_philox", "oasmc_logreg_eval",
               "oasmc_profile", "oasmc_logZ_backward", "oasmc_run_batch", "oasmc_rejuvenate",
-              "oasmc_zja", "oasmc_autotune", "oasmc_shape"):
+              "oasmc_zja", "oasmc_autotune", "oasmc_shape", "oasmc_pt"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -333,6 +336,29 @@ def run(problem: Problem, N1: int, rounds: int, seed: int, problem_id: int = 0, 
     if rejuvenate:
         r["rejuv_mean"], r["rejuv_second"] = rj_m, rj_s
     return r
+
+
+def pt(problem: Problem, K: int, beta, eps, Tp: int, seed: int, move="rwmh", leapfrog: int = 5,
+       round_k: int = 1, problem_id: int = 0) -> dict:
+    """Parallel tempering: K copies of len(beta) chains, Tp iterations, even/odd swaps.
+    Returns logZ (stepping stone), ss [N'], rej [N'], Lambda_PT, trips, tmean, tsecond."""
+    dev = problem.device
+    beta = _host_f64(beta)
+    Np = beta.shape[0] - 1
+    eps = _host_f64(np.broadcast_to(np.asarray(eps, dtype=np.float64), (Np + 1,)))
+    ss, rej = np.zeros(Np), np.zeros(Np)
+    tm, ts = np.zeros(problem.d), np.zeros(problem.d)
+    lz = C.c_double(0.0)
+    trips = C.c_int64(0)
+    P = problem.c()
+    Kn = _kernel(move, leapfrog, False, "ess", 0.5)
+    _check(_load().oasmc_pt(_handle(dev.index or 0), C.byref(P), C.byref(Kn), int(K), Np, int(Tp),
+                            _np_ptr(beta), _np_ptr(eps), int(seed) & (2 ** 64 - 1), int(round_k),
+                            int(problem_id), C.c_void_p(C.addressof(lz)), _np_ptr(ss), _np_ptr(rej),
+                            C.c_void_p(C.addressof(trips)), _np_ptr(tm), _np_ptr(ts),
+                            _stream(dev)))
+    return dict(logZ=lz.value, ss=ss, rej=rej, Lambda_PT=float(np.sum(rej)), trips=trips.value,
+                tmean=tm, tsecond=ts)
 
 
 def autotune(enable: int, device: int = 0) -> int:

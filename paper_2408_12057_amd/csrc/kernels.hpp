@@ -68,6 +68,19 @@ __host__ __device__ inline size_t lane_param_doubles(const TargetDev& tg, int lp
     return (size_t)(1 + lane_means(tg)) * lpp * dpl;
 }
 
+// Offset of the lane-layout arrays behind the staged parameters (8-aligned):
+// reference and target means as floats after 1/(2 v_k), 1/v_k.
+__host__ __device__ inline size_t lane_params_offset(const TargetDev& tg)
+{
+    const int nmu = (tg.family == kGmm) ? tg.K * tg.d : tg.d;
+    return (2 * kMaxK * sizeof(double) + (size_t)(tg.d + nmu) * sizeof(float) + 7) & ~(size_t)7;
+}
+// Dynamic LDS of a VALU kernel with the lane-layout parameters of a shape.
+__host__ __device__ inline size_t params_bytes_lanes(const TargetDev& tg, int lpp, int dpl)
+{
+    return lane_params_offset(tg) + lane_param_doubles(tg, lpp, dpl) * sizeof(double);
+}
+
 // Arguments of one annealing pass.
 struct SweepArgs {
     TargetDev tg;
@@ -165,6 +178,21 @@ struct RejuvArgs {
     float* x_out;         // [N*d] chain end states, or null
 };
 
+// Parallel tempering: K copies (one workgroup each) of Np + 1 chains at the
+// temperatures beta[0..Np] (step sizes eps[0..Np]), a.T iterations; per copy
+// out[k * stride ..]: stepping-stone (max, scaled sum) pairs [Np][2], summed
+// swap rejections [Np], round trips, the number of waves; fpart [K][16][2d]:
+// target-chain sums of x_i, x_i^2 per wave.
+struct PtArgs {
+    SweepArgs a;          // target, move, leapfrog, key, T = iterations
+    int K, Np;
+    const double* beta;   // device [Np+1]
+    const double* eps;    // device [Np+1]
+    double* out;          // device [K][stride]
+    int64_t stride;       // >= 3 Np + 2
+    double* fpart;        // device [K][16][2d]
+};
+
 // Validated launch configuration of a VALU sweep.
 struct ValuShape {
     int lpp;  // lanes per particle
@@ -208,6 +236,17 @@ hipError_t launch_resample_step(const SweepArgs& a, const AsmcState& z, int t, h
 // Rejuvenation: chains and the per-tile sums, then the fixed-order reduction
 // of the tile sums into out [2 d + 1] (averages over N T samples, accepted fraction).
 hipError_t launch_rejuv(const RejuvArgs& R, const ValuShape& s, hipStream_t st);
+hipError_t launch_pt(const PtArgs& A, const ValuShape& s, hipStream_t st);
+// Dynamic LDS of one PT workgroup (staged target parameters, then the
+// replicas' ell, rejection sums, temperature maps and a reduction buffer).
+__host__ __device__ inline size_t pt_shared_bytes(const PtArgs& A, int lpp, int dpl)
+{
+    const size_t R = (size_t)A.Np + 1;
+    size_t off = params_bytes_lanes(A.a.tg, lpp, dpl);
+    off = (off + 15) & ~(size_t)15;
+    return off + R * sizeof(double) + (size_t)A.Np * sizeof(double) + 3 * R * sizeof(int) +
+           16 * sizeof(double);
+}
 hipError_t launch_rejuv_reduce(const double* tsum, int64_t ntiles, int d, double samples,
                                double* out, hipStream_t st);
 // Systematic resampling of lw[N] for the event word of step t (particle word

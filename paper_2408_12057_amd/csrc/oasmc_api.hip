@@ -118,7 +118,7 @@ enum BufId {
     B_BETA, B_EPS, B_PART, B_LOGG, B_ACC, B_SCAL, B_X, B_X2, B_ELL, B_ELL2, B_LW, B_ACCW,
     B_TPART, B_NRES, B_ESS, B_RES, B_C, B_BTOT, B_LWO, B_XO, B_LOGREG, B_CKPT, B_SEG, B_ABITS,
     B_GPART, B_GRAD, B_DEVRUN, B_DEVDESC, B_G, B_G2, B_BLK, B_RJ_ANC, B_RJ_SUM, B_RJ_OUT,
-    B_RJ_LW, B_RJ_X, B_ZSTOP, B_COUNT
+    B_RJ_LW, B_RJ_X, B_ZSTOP, B_PT_OUT, B_PT_F, B_COUNT
 };
 
 template <typename T>
@@ -1247,6 +1247,121 @@ int oasmc_zja(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel*
     *T_out = T;
     *logZ = lz;
     if (!std::isfinite(lz)) return fail(OASMC_ENONFINITE, "log Z_hat is not finite");
+    g_err.clear();
+    return OASMC_OK;
+}
+
+int oasmc_pt(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel* kernel, int32_t K,
+             int32_t Np, int32_t Tp, const double* beta, const double* eps, uint64_t seed,
+             uint32_t round_k, uint32_t problem_id, double* logZ, double* ss, double* rej,
+             int64_t* trips, double* tmean, double* tsecond, void* stream)
+{
+    if (!h || !logZ) return fail(OASMC_EINVAL, "NULL argument");
+    int s = check_problem(problem, kernel);
+    if (s) return s;
+    if (problem->family == OASMC_LOGREG)
+        return fail(OASMC_EUNSUPPORTED, "parallel tempering is built for the Gaussian, mixture and Unid families");
+    if (K < 1 || Np < 1 || Tp < 1) return fail(OASMC_EINVAL, "need K, Np, Tp >= 1");
+    s = check_schedule(Np, beta);
+    if (s) return s;
+    if (!eps) return fail(OASMC_EINVAL, "eps is NULL");
+    for (int n = 0; n <= Np; ++n)
+        if (!(eps[n] > 0.0) || !std::isfinite(eps[n]))
+            return fail(OASMC_EINVAL, "eps[%d] must be positive and finite", n);
+    const int R = Np + 1;
+    ValuShape shape{};
+    if (!valu_shape(problem->d, (int64_t)K * R, &shape))
+        return fail(OASMC_EUNSUPPORTED, "no kernel shape for d=%d", problem->d);
+    const int P = kWave / shape.lpp;
+    if (R > 16 * P)
+        return fail(OASMC_EUNSUPPORTED, "a copy holds at most %d chains at d=%d", 16 * P, problem->d);
+    HIP_TRY(hipSetDevice(h->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int d = problem->d;
+    PtArgs A{};
+    A.a.tg = target_dev(problem);
+    A.a.move = kernel->move;
+    A.a.leapfrog = kernel->leapfrog;
+    A.a.N = (int64_t)K * R;
+    A.a.T = Tp;
+    A.a.key.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    A.a.key.k1 = (uint32_t)(seed >> 32);
+    A.a.key.c2 = (round_k & 0xFFFFu) | (problem_id << 16);
+    A.K = K;
+    A.Np = Np;
+    A.stride = 3 * (int64_t)Np + 2;
+    if (pt_shared_bytes(A, shape.lpp, shape.dpl) > h->lds_per_block)
+        return fail(OASMC_EUNSUPPORTED, "too many chains for the LDS of one workgroup");
+    double *dbeta, *deps, *out, *fpart;
+    HIP_TRY(wget(h, B_BETA, (size_t)R, &dbeta));
+    HIP_TRY(wget(h, B_EPS, (size_t)R, &deps));
+    HIP_TRY(wget(h, B_PT_OUT, (size_t)K * A.stride, &out));
+    HIP_TRY(wget(h, B_PT_F, (size_t)K * 16 * 2 * d, &fpart));
+    HIP_TRY(hipMemcpyAsync(dbeta, beta, sizeof(double) * R, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(deps, eps, sizeof(double) * R, hipMemcpyHostToDevice, st));
+    A.beta = dbeta;
+    A.eps = deps;
+    A.out = out;
+    A.fpart = fpart;
+    if (h->prof) HIP_TRY(hipEventRecord(h->ev0, st));
+    HIP_TRY(launch_pt(A, shape, st));
+    if (h->prof) HIP_TRY(hipEventRecord(h->ev1, st));
+    std::vector<double> ho((size_t)K * A.stride), hf((size_t)K * 16 * 2 * d);
+    HIP_TRY(hipMemcpyAsync(ho.data(), out, sizeof(double) * ho.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hf.data(), fpart, sizeof(double) * hf.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h->prof) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+        h->prof_ms += ms;
+        h->prof_launches += 1;
+        h->prof_steps += (double)K * R * Tp;
+    }
+    // the copies' outputs in copy order: stepping stones pooled over the K T'
+    // terms of each temperature, rejections averaged over the proposals
+    double lz = 0.0;
+    const double lkt = std::log((double)K * Tp);
+    for (int n = 0; n < Np; ++n) {
+        double m = -INFINITY, sum = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double mk = ho[(size_t)k * A.stride + 2 * n], sk = ho[(size_t)k * A.stride + 2 * n + 1];
+            if (!(mk > -INFINITY) || !(sk > 0.0)) continue;
+            if (mk > m) {
+                sum = sum * std::exp(m - mk) + sk;
+                m = mk;
+            } else {
+                sum += sk * std::exp(mk - m);
+            }
+        }
+        const double v = (sum > 0.0) ? m + std::log(sum) - lkt : -INFINITY;
+        if (ss) ss[n] = v;
+        lz += v;
+        // pair n is proposed at the iterations t of its parity
+        const double cnt = (double)K * ((n % 2 == 0) ? (Tp / 2) : ((Tp + 1) / 2));
+        double rs = 0.0;
+        for (int k = 0; k < K; ++k) rs += ho[(size_t)k * A.stride + 2 * Np + n];
+        if (rej) rej[n] = cnt > 0 ? rs / cnt : NAN;
+    }
+    if (trips) {
+        double tr = 0.0;
+        for (int k = 0; k < K; ++k) tr += ho[(size_t)k * A.stride + 3 * Np];
+        *trips = (int64_t)std::llround(tr);
+    }
+    if (tmean && tsecond) {
+        const int waves = (R + P - 1) / P;
+        for (int i = 0; i < d; ++i) {
+            double a1 = 0.0, a2 = 0.0;
+            for (int k = 0; k < K; ++k)
+                for (int w = 0; w < waves; ++w) {
+                    a1 += hf[((size_t)k * 16 + w) * 2 * d + i];
+                    a2 += hf[((size_t)k * 16 + w) * 2 * d + d + i];
+                }
+            tmean[i] = a1 / ((double)K * Tp);
+            tsecond[i] = a2 / ((double)K * Tp);
+        }
+    }
+    *logZ = lz;
+    if (!std::isfinite(lz)) return fail(OASMC_ENONFINITE, "log Z_PT is not finite");
     g_err.clear();
     return OASMC_OK;
 }

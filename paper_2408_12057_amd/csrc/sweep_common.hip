@@ -492,10 +492,10 @@ int64_t valu_tiles(int64_t N, const ValuShape& s)
 template <int FAM, int MOVE>
 hipError_t valu_dispatch(int what, const SweepArgs& a, const ValuShape& s, int gw,
                          const AsmcState* z, int t, hipStream_t st, const ValuBatch* b,
-                         const RejuvArgs* rj);
+                         const void* ext);
 static hipError_t dispatch_all(int what, const SweepArgs& a, const ValuShape& s, int gw,
                                const AsmcState* z, int t, hipStream_t st,
-                               const ValuBatch* b = nullptr, const RejuvArgs* rj = nullptr)
+                               const ValuBatch* b = nullptr, const void* rj = nullptr)
 {
     const int fam = a.tg.family, mv = a.move;
 #define OASMC_FM(F, M) \
@@ -644,6 +644,11 @@ hipError_t launch_zja_final(int64_t N, const double* lw, double* logZ, hipStream
 {
     hipLaunchKernelGGL(k_zja_final, dim3(1), dim3(kZjaThreads), 0, st, N, lw, logZ);
     return hipGetLastError();
+}
+
+hipError_t launch_pt(const PtArgs& A, const ValuShape& s, hipStream_t st)
+{
+    return dispatch_all(5, A.a, s, 0, nullptr, 0, st, nullptr, &A);
 }
 
 hipError_t launch_rejuv(const RejuvArgs& R, const ValuShape& s, hipStream_t st)

@@ -88,12 +88,6 @@ inline size_t params_bytes(const TargetDev& tg)
     return 2 * kMaxK * sizeof(double) + (size_t)(tg.d + nmu) * sizeof(float);
 }
 
-// Offset of the lane-layout arrays behind the staged parameters (8-aligned).
-__host__ __device__ inline size_t lane_params_offset(const TargetDev& tg)
-{
-    const int nmu = (tg.family == kGmm) ? tg.K * tg.d : tg.d;
-    return (2 * kMaxK * sizeof(double) + (size_t)(tg.d + nmu) * sizeof(float) + 7) & ~(size_t)7;
-}
 
 // The same staging followed by the binary64 lane-layout means lm, lmu of the
 // shape (LPP, DPL).
@@ -108,10 +102,6 @@ __device__ __forceinline__ ParView stage_params_lanes(const TargetDev& tg, char*
     return ParView{base.m, base.mu, base.hiv, base.iv, lane, lane + LPP * DPL};
 }
 
-inline size_t params_bytes_lanes(const TargetDev& tg, int lpp, int dpl)
-{
-    return lane_params_offset(tg) + lane_param_doubles(tg, lpp, dpl) * sizeof(double);
-}
 
 // ---------------------------------------------------------------------------
 // Particle arithmetic for one lane group.
@@ -966,6 +956,153 @@ __global__ void __launch_bounds__(256) k_rejuv(RejuvArgs R)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Parallel tempering (Sec. "Computational duality with parallel tempering"):
+// one workgroup per PT copy, replica r of the copy on particle slot r of the
+// workgroup (LPP lanes), at temperature tau[r].  Iteration t: every replica
+// takes one step of the forward kernel at its temperature (counters (replica,
+// t)); then one thread per proposed pair (n, n + 1) of the parity of t decides
+// the swap of temperatures (stream 4, counter (copy (N' + 1) + n, t)); then
+// the stepping-stone terms (one thread per temperature, a running maximum and
+// scaled sum), round trips (one thread per replica) and the target chain's
+// sums (the replica at N') are taken.  Swaps exchange temperatures, not states.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kStreamSwap = 4;
+
+template <int FAM, int MOVE, int LPP, int DPL>
+__global__ void __launch_bounds__(1024) k_pt(PtArgs A)
+{
+    constexpr int P = kWave / LPP;
+    extern __shared__ __align__(16) char sh_dyn[];
+    const SweepArgs& a = A.a;
+    const ParView pv = stage_params_lanes<LPP, DPL>(a.tg, sh_dyn);
+    const Consts c = make_consts(a.tg);
+    const int R = A.Np + 1;
+    const int Np = A.Np;
+    size_t off = (params_bytes_lanes(a.tg, LPP, DPL) + 15) & ~(size_t)15;
+    double* Lsh = reinterpret_cast<double*>(sh_dyn + off);   // [R] ell of replica r
+    double* rsum = Lsh + R;                                   // [Np] summed rejections
+    int* tau = reinterpret_cast<int*>(rsum + Np);             // [R] temperature of replica r
+    int* rep = tau + R;                                       // [R] replica at temperature n
+    int* side = rep + R;                                      // [R] round-trip state
+    double* red = reinterpret_cast<double*>(side + R + ((R & 1) ? 1 : 0));  // [16]
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = tid / kWave;
+    const int r = lane % LPP;
+    const int slot = wv * P + lane / LPP;   // replica of this lane group
+    const bool live = slot < R;
+    const int k = blockIdx.x;
+    const uint32_t gid = (uint32_t)(k * R + (live ? slot : 0));
+    const int d = a.tg.d;
+    for (int i = tid; i < R; i += blockDim.x) {
+        tau[i] = i;
+        rep[i] = i;
+        side[i] = (i == 0) ? 0 : -1;
+    }
+    for (int i = tid; i < Np; i += blockDim.x) rsum[i] = 0.0;
+    float x[DPL];
+    double g[DPL];
+    double ell = Particle<FAM, LPP, DPL>::init(a.tg, c, pv, a.key, gid, r, x, g, uses_grad(MOVE));
+    double f1[DPL], f2[DPL];
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) f1[j] = f2[j] = 0.0;
+    double sm = -INFINITY, ss = 0.0;  // stepping stone of temperature tid (tid < Np)
+    double trips = 0.0;               // round trips of replica tid (tid < R)
+    __syncthreads();
+    for (int t = 1; t <= a.T; ++t) {
+        const int n = live ? tau[slot] : 0;
+        Particle<FAM, LPP, DPL>::template move<MOVE>(a.tg, c, pv, a.key, gid, (uint32_t)t, r,
+                                                     a.leapfrog, A.beta[n], A.eps[n], x, ell, g);
+        if (live && r == 0) Lsh[slot] = ell;
+        __syncthreads();
+        // swaps of the pairs (n, n + 1), n of the parity of t
+        {
+            const int np = ((t & 1) ? 1 : 0) + 2 * tid;
+            if (np + 1 < R) {
+                const int ra = rep[np], rb = rep[np + 1];
+                const double la = (A.beta[np + 1] - A.beta[np]) * (Lsh[ra] - Lsh[rb]);
+                const uint4 w = draw_block(a.key, (uint32_t)(k * R + np), (uint32_t)t, kStreamSwap,
+                                           0u, 0u);
+                const double acc = (la >= 0.0) ? 1.0 : ((la == la) ? exp(la) : 0.0);
+                rsum[np] += 1.0 - acc;
+                if (log(word_uniform(w.x)) < la) {
+                    rep[np] = rb;
+                    rep[np + 1] = ra;
+                    tau[ra] = np + 1;
+                    tau[rb] = np;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < R) {
+            const int tr = tau[tid];
+            if (tr == Np && side[tid] == 0) side[tid] = 1;
+            if (tr == 0) {
+                if (side[tid] == 1) trips += 1.0;
+                side[tid] = 0;
+            }
+        }
+        if (tid < Np) {
+            const double v = (A.beta[tid + 1] - A.beta[tid]) * Lsh[rep[tid]];
+            if (v > -INFINITY) {
+                if (v > sm) {
+                    ss = ss * exp(sm - v) + 1.0;
+                    sm = v;
+                } else {
+                    ss += exp(v - sm);
+                }
+            }
+        }
+        if (live && tau[slot] == Np) {
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) {
+                const double v = (double)x[j];
+                f1[j] += v;
+                f2[j] += v * v;
+            }
+        }
+        __syncthreads();
+    }
+    // per-copy outputs: stepping stone (max, scaled sum), rejections, round
+    // trips, target-chain sums over the copy's replicas (fixed order)
+    double* o = A.out + (size_t)k * A.stride;
+    if (tid < Np) {
+        o[2 * tid] = sm;
+        o[2 * tid + 1] = ss;
+        o[2 * Np + tid] = rsum[tid];
+    }
+    double tr = wave_sum(trips);
+    if (lane == 0) red[wv] = tr;
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+        if (!live) f1[j] = f2[j] = 0.0;
+#pragma unroll
+        for (int q = LPP; q < kWave; q <<= 1) {
+            f1[j] += __shfl_xor(f1[j], q, kWave);
+            f2[j] += __shfl_xor(f2[j], q, kWave);
+        }
+    }
+    double* fo = A.fpart + ((size_t)k * 16 + wv) * 2 * d;
+    if (lane < LPP) {
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) {
+            const int i = r * DPL + j;
+            if (i < d) {
+                fo[i] = f1[j];
+                fo[d + i] = f2[j];
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double s = 0.0;
+        for (int i = 0; i < (int)(blockDim.x / kWave); ++i) s += red[i];
+        o[3 * Np] = s;
+        o[3 * Np + 1] = (double)(blockDim.x / kWave);
+    }
+}
+
 template <int FAM, int MOVE, int LPP, int DPL>
 struct Launch {
     static hipError_t oais(const SweepArgs& a, int grid_waves, hipStream_t st)
@@ -997,6 +1134,15 @@ struct Launch {
                            params_bytes_lanes(R.a.tg, LPP, DPL), st, R);
         return hipGetLastError();
     }
+    static hipError_t pt(const PtArgs& A, hipStream_t st)
+    {
+        constexpr int P = kWave / LPP;
+        const int waves = (A.Np + 1 + P - 1) / P;
+        const size_t shb = pt_shared_bytes(A, LPP, DPL);
+        hipLaunchKernelGGL((k_pt<FAM, MOVE, LPP, DPL>), dim3((unsigned)A.K), dim3(waves * kWave),
+                           shb, st, A);
+        return hipGetLastError();
+    }
     static hipError_t step(const SweepArgs& a, const AsmcState& z, int t, hipStream_t st)
     {
         const int64_t blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -1009,8 +1155,10 @@ struct Launch {
 template <int FAM, int MOVE>
 hipError_t valu_dispatch(int what, const SweepArgs& a, const ValuShape& s, int gw,
                            const AsmcState* z, int t, hipStream_t st, const ValuBatch* b,
-                           const RejuvArgs* rj)
+                           const void* ext)
 {
+    const RejuvArgs* rj = static_cast<const RejuvArgs*>(ext);
+    const PtArgs* pt = static_cast<const PtArgs*>(ext);
 #define OASMC_CASE(L, D)                                                     \
     if (s.lpp == L && s.dpl == D) {                                          \
         if (what == 0) return Launch<FAM, MOVE, L, D>::oais(a, gw, st);      \
@@ -1019,6 +1167,7 @@ hipError_t valu_dispatch(int what, const SweepArgs& a, const ValuShape& s, int g
             return Launch<FAM, MOVE, L, D>::batch(b->args, b->views, b->items, \
                                                   b->nitems, gw, st);        \
         if (what == 4) return Launch<FAM, MOVE, L, D>::rejuv(*rj, st);       \
+        if (what == 5) return Launch<FAM, MOVE, L, D>::pt(*pt, st);          \
         return Launch<FAM, MOVE, L, D>::step(a, *z, t, st);                  \
     }
     OASMC_CASE(1, 4)

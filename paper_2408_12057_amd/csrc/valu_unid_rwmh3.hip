@@ -5,5 +5,5 @@
 namespace oasmc {
 template hipError_t valu_dispatch<kUnid, kRwmh3>(int, const SweepArgs&, const ValuShape&, int,
                                                   const AsmcState*, int, hipStream_t,
-                                                  const ValuBatch*, const RejuvArgs*);
+                                                  const ValuBatch*, const void*);
 }  // namespace oasmc
