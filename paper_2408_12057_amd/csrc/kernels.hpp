@@ -18,7 +18,7 @@ __host__ __device__ constexpr bool uses_grad(int move) { return move == kMala ||
 
 constexpr int kMaxK = 16;      // mixture components handled by the VALU kernels
 constexpr int kMaxDValu = 256; // dimension handled by the VALU kernels
-constexpr int kMaxDLogreg = 64;
+constexpr int kMaxDLogreg = 256;
 
 // Device description of the target and reference (all pointers device, fp32).
 struct TargetDev {
@@ -316,21 +316,27 @@ hipError_t launch_oais_logreg(const SweepArgs& a, int cus, void* ws, size_t ws_b
 // One logistic-regression problem as its sweep kernel sees it.
 struct LogregArgs {
     SweepArgs a;
-    const float* Xp;   // packed [n_pad][64], rows signed by 2 y - 1, padding rows zero
+    const float* Xp;   // packed [n_pad][cols], rows signed by 2 y - 1, padding rows zero
     int n_pad;
+    float* gl;         // d > 64: cached gradients at the states, [tiles 32][cols]
+    float* glp;        // d > 64: gradients at the proposals, [tiles 32][cols]
 };
-int logreg_kh(int d);      // column half-width class of d (-1 if unsupported)
+int logreg_kh(int d);      // column class of d (half-width, or 1000 + panels; -1 if unsupported)
 int logreg_npad(int n);    // padded row count
+int logreg_cols(int d);    // packed columns (64, or 64 per panel above 64 features)
+// Points A's data and gradient buffers into a workspace of
+// logreg_workspace_bytes(tg, N) bytes.
+void logreg_layout(const TargetDev& tg, int64_t N, void* ws, LogregArgs* A);
 hipError_t logreg_pack_into(const TargetDev& tg, float* Xp, hipStream_t st);
 hipError_t launch_oais_logreg_batch(int kh, const LogregArgs* args, const int2* items,
                                    int64_t nitems, int grid, hipStream_t st);
 hipError_t launch_logreg_eval(const TargetDev& tg, const float* theta, int64_t N, double* ell,
                               float* grad, void* ws, hipStream_t st);
 size_t logreg_workspace_bytes(const TargetDev& tg, int64_t N);
-size_t logreg_shared_bytes();
+size_t logreg_shared_bytes(int d);
 // Packs X and y into the kernel's padded, column-permuted layout in ws.
 hipError_t logreg_prepare(const TargetDev& tg, void* ws, hipStream_t st);
-int64_t logreg_tiles(int64_t N);
+int64_t logreg_tiles(int64_t N, int d);
 // Sets / clears the message oasmc_last_error() returns on this thread.
 int record_error(int code, const char* fmt, ...);
 void clear_error();

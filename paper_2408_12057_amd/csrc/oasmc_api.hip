@@ -549,10 +549,7 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
                    align256(sizeof(double) * lane_param_doubles(tg, q.shape.lpp, q.shape.dpl));
         }
         q.off_data = off;
-        if (q.logreg) {
-            const int np = logreg_npad(q.prob.n);
-            off += align256(sizeof(float) * (size_t)np * 64);
-        }
+        if (q.logreg) off += align256(logreg_workspace_bytes(target_dev(&q.prob), q.N));
     }
     char* ws;
     {
@@ -662,11 +659,7 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
             reinterpret_cast<SweepArgs*>(blob.data() + d_sweep)[(size_t)k * P + p] = a;
             LogregArgs la{};
             la.a = a;
-            if (q.logreg) {
-                const int np = logreg_npad(q.prob.n);
-                la.Xp = at<float>(ws, q.off_data);
-                la.n_pad = np;
-            }
+            if (q.logreg) logreg_layout(a.tg, q.N, ws + q.off_data, &la);
             reinterpret_cast<LogregArgs*>(blob.data() + d_lr)[(size_t)k * P + p] = la;
             RoundDev rd{};
             rd.T = T;
@@ -838,13 +831,13 @@ int prepare_dev_problem(oasmc_handle* h, DevProblem& q, hipStream_t st)
     if (!(q.eps0 > 0.0)) return fail(OASMC_EINVAL, "eps0 must be positive");
     q.logreg = (q.prob.family == OASMC_LOGREG);
     if (q.logreg) {
-        if (h->lds_per_block < logreg_shared_bytes())
+        if (h->lds_per_block < logreg_shared_bytes(q.prob.d))
             return fail(OASMC_EUNSUPPORTED, "device offers %zu bytes of LDS per workgroup, need %zu",
-                        h->lds_per_block, logreg_shared_bytes());
+                        h->lds_per_block, logreg_shared_bytes(q.prob.d));
         q.kh = logreg_kh(q.prob.d);
         if (q.kh < 0) return fail(OASMC_EUNSUPPORTED, "no kernel for d=%d", q.prob.d);
         q.shape = ValuShape{0, 0};
-        q.ntiles = logreg_tiles(q.N);
+        q.ntiles = logreg_tiles(q.N, q.prob.d);
     } else {
         const int ps = pick_shape(h, &q.prob, &q.kern, q.N, &q.shape, st);
         if (ps) return ps;
@@ -1002,10 +995,10 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
         int64_t ntiles;
         ValuShape shape{};
         if (problem->family == OASMC_LOGREG) {
-            if (h->lds_per_block < logreg_shared_bytes())
+            if (h->lds_per_block < logreg_shared_bytes(problem->d))
                 return fail(OASMC_EUNSUPPORTED, "device offers %zu bytes of LDS per workgroup, need %zu",
-                            h->lds_per_block, logreg_shared_bytes());
-            ntiles = logreg_tiles(N);
+                            h->lds_per_block, logreg_shared_bytes(problem->d));
+            ntiles = logreg_tiles(N, problem->d);
         } else {
             const int ps = pick_shape(h, problem, kernel, N, &shape, st);
             if (ps) return ps;
@@ -1445,9 +1438,9 @@ int oasmc_logreg_eval(oasmc_handle* h, const oasmc_problem* problem, int64_t N,
     if (problem->d < 1 || problem->d > kMaxDLogreg)
         return fail(OASMC_EUNSUPPORTED, "logistic regression supports 1 <= d <= %d", kMaxDLogreg);
     if (N < 1 || N > ((int64_t)1 << 30)) return fail(OASMC_EINVAL, "N must lie in [1, 2^30]");
-    if (h->lds_per_block < logreg_shared_bytes())
+    if (h->lds_per_block < logreg_shared_bytes(problem->d))
         return fail(OASMC_EUNSUPPORTED, "device offers %zu bytes of LDS per workgroup, need %zu",
-                    h->lds_per_block, logreg_shared_bytes());
+                    h->lds_per_block, logreg_shared_bytes(problem->d));
     HIP_TRY(hipSetDevice(h->device));
     const TargetDev tg = target_dev(problem);
     void* ws;

@@ -651,17 +651,495 @@ __global__ void __launch_bounds__(LCfg::threads) k_logreg_eval(const float* __re
 }
 
 // ---------------------------------------------------------------------------
-int64_t logreg_tiles(int64_t N) { return (N + kLP - 1) / kLP; }
+// Wide variant, 64 < d <= 256: the features sit in NP panels of 64 packed
+// columns (panel p holds features p F .. p F + F - 1, F = ceil(d / NP), with the
+// same split of each panel into two halves of width KHW = ceil(F / 2) as the
+// 64-column layout), so the logits' K loop runs over the panels.  A tile has
+// 32 particles (one 32-particle group of the MFMA products), so a wave keeps
+// the gradient tiles of every panel (NP x 2 x 16 accumulators) and LDS holds
+// the states, proposals and one staged panel per wave; the cached gradients
+// (at the state and at the proposal) live in HBM, [N][NP 64] in packed column
+// order.  Per 32-row chunk a wave stages each panel twice: once for the
+// logits, once after the epilogue for the gradient (the second pass re-reads
+// the panels from L2), with the global load of the next panel issued one stage
+// ahead.  The eight waves' gradient tiles are summed panel by panel in wave
+// order through the staging area.
+// ---------------------------------------------------------------------------
+constexpr int kLPW = 32;  // particles per tile, wide variant
+
+struct LCfgW {
+    static constexpr int waves = 8;
+    static constexpr int threads = waves * kWave;
+    static constexpr int tpp = threads / kLPW;  // threads per particle, scalar phases
+};
+
+template <int NP>
+struct LogregSharedW {
+    float theta[kLPW][NP * 64 + 4];
+    float prop[kLPW][NP * 64 + 4];
+    float stage[LCfgW::waves][kRows][kSt];
+    double ll[kLPW], llp[kLPW], lw[kLPW];
+    double llpart[LCfgW::waves][kLPW];
+    double fwd[kLPW], dle[kLPW], logu[kLPW];
+    float m[NP * 64];
+    uint32_t cnt;
+};
+
+static_assert(sizeof(LogregSharedW<4>::stage) >= 16 * 8 * LCfgW::waves * kWave,
+              "the wide gradient reduction fits in the staging buffers");
+static_assert(sizeof(LogregSharedW<4>) <= 160 * 1024, "the wide tile fits in LDS");
+
+// Panel widths of the wide layout.
+__host__ __device__ inline int wide_np(int d) { return (d + 63) / 64; }
+__host__ __device__ inline int wide_f(int d) { return (d + wide_np(d) - 1) / wide_np(d); }
+__host__ __device__ inline int wide_khw(int d) { return (wide_f(d) + 1) / 2; }
+__host__ __device__ inline int col_of_wide(int f, int F, int KHW)
+{
+    const int p = f / F, l = f - p * F;
+    return 64 * p + (l < KHW ? l : 32 + l - KHW);
+}
+
+__global__ void k_logreg_pack_wide(const float* __restrict__ X, const float* __restrict__ y,
+                                   int n, int d, int cols, int n_pad, float* __restrict__ Xp)
+{
+    const int F = wide_f(d), KHW = wide_khw(d);
+    const int64_t total = (int64_t)n_pad * cols;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / cols), c = (int)(e % cols);
+        const int p = c / 64, cc = c % 64;
+        int l = -1;
+        if (cc < 32) {
+            if (cc < KHW) l = cc;
+        } else if (cc - 32 + KHW < F) {
+            l = KHW + cc - 32;
+        }
+        const int f = p * F + l;
+        const bool in = i < n && l >= 0 && f < d;
+        const float v = in ? X[(int64_t)i * d + f] : 0.f;
+        Xp[e] = (in && y[i] == 0.f) ? -v : v;
+    }
+}
+
+// The chunk slice of panel p: row l / 2, columns 64 p + 32 (l % 2) .. + 31.
+__device__ __forceinline__ Slice fetch_slice_w(const float* Xp, int n_pad, int cols, int c, int p)
+{
+    const int l = threadIdx.x % kWave;
+    const int r0 = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave) * wave_rows(n_pad);
+    gmem_f* const Xg = (gmem_f*)Xp;
+    const gmem_f4* src =
+        (const gmem_f4*)(Xg + (size_t)(r0 + c * kRows + l / 2) * cols + 64 * p + (l % 2) * 32);
+    Slice t;
+    t.v0 = src[0]; t.v1 = src[1]; t.v2 = src[2]; t.v3 = src[3];
+    t.v4 = src[4]; t.v5 = src[5]; t.v6 = src[6]; t.v7 = src[7];
+    return t;
+}
+
+// ell and grad ell at sh.prop for the tile's 32 particles: ell into sh.llp,
+// the gradient into glp (HBM, packed columns) of particles pbase .. pbase + 31
+// (rows past N are written too: the buffers cover whole tiles).
+template <int NP>
+__device__ __forceinline__ void contraction_w(LogregSharedW<NP>& sh, const float* __restrict__ Xp,
+                                              int n, int n_pad, int khw, float* glp, int64_t pbase)
+{
+    constexpr int kW = LCfgW::waves;
+    constexpr int cols = NP * 64;
+    constexpr double kLn2 = 0.693147180559945309;
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int l = tid % kWave;
+    const int h = l / 32;
+    const int j = l % 32;
+    floatx16 G[NP][2];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int ft = 0; ft < 2; ++ft)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) G[p][ft][q] = 0.f;
+    double llacc = 0.0;
+    const int nchunks = wave_rows(n_pad) / kRows;
+    const int r0 = w * wave_rows(n_pad);
+    float(*stc)[kSt] = sh.stage[w];
+    // 2 NP stages per chunk (the panels for the logits, then again for the
+    // gradient); `ahead` holds the next stage's slice, loaded while the
+    // current one is consumed from the wave's staging buffer
+    Slice ahead = fetch_slice_w(Xp, n_pad, cols, 0, 0);
+    for (int c = 0; c < nchunks; ++c) {
+        // signed logits of the chunk, transposed, accumulated over the panels
+        floatx16 acc;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = 0.f;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            put_slice(stc, ahead);
+            wsync();
+            ahead = fetch_slice_w(Xp, n_pad, cols, c, (p + 1) % NP);
+#pragma unroll 4
+            for (int s = 0; s < khw; ++s)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(stc[j][32 * h + s],
+                                                           sh.prop[j][64 * p + 32 * h + s], acc,
+                                                           0, 0, 0);
+            wsync();
+        }
+        // the epilogue (see epi_a, epi_b): acc becomes sigma(-u)
+        {
+            float llc = 0.f, prod = 1.f;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                EpiTmp tq;
+                epi_a(acc[q], tq);
+                acc[q] = epi_b(acc[q], tq, llc, prod);
+            }
+            const int npad_rows = padding_rows(n - (r0 + c * kRows), h);
+            const float lp = __builtin_amdgcn_logf(__builtin_amdgcn_ldexpf(prod, -npad_rows));
+            llacc += (double)llc - kLn2 * (double)lp;
+        }
+        // gradient, panel by panel: G[p][ft] += sigma(-u)^T X'_{p, ft}
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            put_slice(stc, ahead);
+            wsync();
+            if (p + 1 < NP)
+                ahead = fetch_slice_w(Xp, n_pad, cols, c, p + 1);
+            else
+                ahead = fetch_slice_w(Xp, n_pad, cols, min(c + 1, nchunks - 1), 0);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int row = slot_row(q, h);
+                G[p][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[q], stc[row][j], G[p][0], 0, 0, 0);
+                G[p][1] =
+                    __builtin_amdgcn_mfma_f32_32x32x2f32(acc[q], stc[row][32 + j], G[p][1], 0, 0, 0);
+            }
+            wsync();
+        }
+    }
+    // per-particle log-likelihood: halves of the wave, then the waves in order
+    llacc += __shfl_xor(llacc, 32, kWave);
+    if (h == 0) sh.llpart[w][j] = llacc;
+    lsync();  // every wave is done with its staging buffer
+    if (tid < kLPW) {
+        double sacc = 0.0;
+        for (int ww = 0; ww < kW; ++ww) sacc += sh.llpart[ww][tid];
+        sh.llp[tid] = sacc;
+    }
+    // gradient, panel by panel: every wave stores its 2 tiles (8 float4 per
+    // lane, lane-interleaved), then wave w sums float4 w of every lane over the
+    // waves in order and writes those entries
+    floatx4* red = reinterpret_cast<floatx4*>(&sh.stage[0][0][0]);
+    constexpr int kSlot = 8 * kWave;  // float4 per wave slot
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const floatx16& v = G[p][k / 4];
+            const int q = 4 * (k % 4);
+            red[w * kSlot + k * kWave + l] = floatx4{v[q], v[q + 1], v[q + 2], v[q + 3]};
+        }
+        lsync();
+        {
+            const int k = w;  // float4 k holds G[p][k / 4][q .. q + 3], q = 4 (k % 4)
+            floatx4 v = red[k * kWave + l];
+            for (int ww = 1; ww < kW; ++ww) {
+                const floatx4 u = red[ww * kSlot + k * kWave + l];
+                v[0] += u[0];
+                v[1] += u[1];
+                v[2] += u[2];
+                v[3] += u[3];
+            }
+            const int ft = k / 4, q0 = 4 * (k % 4);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                glp[(size_t)(pbase + slot_row(q0 + i, h)) * cols + 64 * p + 32 * ft + j] = v[i];
+        }
+        // the stores complete before the barrier: after it, other waves of
+        // the tile read these entries (through the CU's shared L1)
+        __threadfence_block();
+        lsync();
+    }
+}
+
+template <int NP>
+__device__ __forceinline__ void logreg_setup_w(LogregSharedW<NP>& sh, const SweepArgs& a)
+{
+    const int tid = threadIdx.x;
+    const int d = a.tg.d, F = wide_f(d), KHW = wide_khw(d);
+    for (int e = tid; e < kLPW * (NP * 64 + 4); e += LCfgW::threads) {
+        (&sh.theta[0][0])[e] = 0.f;
+        (&sh.prop[0][0])[e] = 0.f;
+    }
+    for (int c = tid; c < NP * 64; c += LCfgW::threads) sh.m[c] = 0.f;
+    lsync();
+    for (int f = tid; f < d; f += LCfgW::threads)
+        sh.m[col_of_wide(f, F, KHW)] = a.tg.ref_mean ? a.tg.ref_mean[f] : 0.f;
+    lsync();
+}
+
+// All tiles of one slot of one problem (the wide counterpart of logreg_slot:
+// the same steps, moments, proposals and correction, in the same order).
+template <int NP>
+__device__ __forceinline__ void logreg_slot_w(LogregSharedW<NP>& sh, const LogregArgs& A,
+                                              int64_t slot)
+{
+    constexpr int kTPP = LCfgW::tpp;
+    constexpr int cols = NP * 64;
+    const SweepArgs& a = A.a;
+    const int tid = threadIdx.x;
+    const int p = tid / kTPP, r = tid % kTPP;
+    const int d = a.tg.d, F = wide_f(d), KHW = wide_khw(d);
+    const int T = a.T;
+    const double s2r = a.tg.ref_sigma2;
+    const double inv_s2r = 1.0 / s2r, half_inv_s2r = 0.5 / s2r, sref = sqrt(s2r);
+    typedef __attribute__((address_space(1))) const double gmem_d;
+    gmem_d* const beta_g = (gmem_d*)a.beta;
+    gmem_d* const eps_g = (gmem_d*)a.eps;
+    const int nblocks = (d + 3) / 4;
+    for (int64_t tile = slot; tile < a.ntiles; tile += a.S) {
+        const bool first = (tile == slot);
+        const int64_t pbase = tile * kLPW;
+        const int64_t n64 = pbase + p;
+        const bool valid = n64 < a.N;
+        const uint32_t n = (uint32_t)n64;
+        float* gl = A.gl + (size_t)n64 * cols;     // cached gradient at the state
+        float* glpp = A.glp + (size_t)n64 * cols;  // gradient at the proposal
+        uint32_t accw = 0;
+        double beta_prev = 0.0;
+        for (int t = 0; t <= T; ++t) {
+            const double beta = (t > 0) ? beta_g[t] : 0.0;
+            const double eps = (t > 0) ? eps_g[t - 1] : 1.0;
+            const double hh = 0.5 * eps * eps;
+            if (t > 0 && tid < 3 * kWave) {
+                const int i = __builtin_amdgcn_readfirstlane(tid / kWave), q = tid % kWave;
+                const bool vq = q < kLPW && (pbase + q) < a.N;
+                const double lg = vq ? (beta - beta_prev) * sh.ll[q] : 0.0;
+                const double x = vq ? (i == 0 ? sh.lw[q] : sh.lw[q] + (double)i * lg) : -INFINITY;
+                double mm = x;
+#pragma unroll
+                for (int o = 1; o < kWave; o <<= 1) mm = fmax(mm, __shfl_xor(mm, o, kWave));
+                double sum = (mm > -INFINITY && vq) ? exp(x - mm) : 0.0;
+#pragma unroll
+                for (int o = 1; o < kWave; o <<= 1) sum += __shfl_xor(sum, o, kWave);
+                if (q == 0) {
+                    double* e = a.part + ((size_t)slot * (T + 1) + (t - 1)) * 4;
+                    const double L = lse_value(mm, sum);
+                    e[i] = first ? L : log_add(e[i], L);
+                }
+            }
+            if (tid == 0) sh.cnt = 0u;
+            {
+                double fwd = 0.0, dle = 0.0;
+                for (int b = r; b < nblocks; b += kTPP) {
+                    double zz[4];
+                    normals4<false>(a.key, n, (uint32_t)t, t > 0 ? kStreamMove : kStreamInit,
+                                    (uint32_t)b, zz);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int f = 4 * b + u;
+                        if (f < d) {
+                            const int c = col_of_wide(f, F, KHW);
+                            const double mv = (double)sh.m[c];
+                            if (t == 0) {
+                                sh.prop[p][c] = (float)(mv + sref * zz[u]);
+                            } else {
+                                const double xv = (double)sh.theta[p][c];
+                                const double ga = -(xv - mv) * inv_s2r + beta * (double)gl[c];
+                                const float xp = (float)(xv + hh * ga + eps * zz[u]);
+                                sh.prop[p][c] = xp;
+                                const double rr = (double)xp - xv - hh * ga;
+                                fwd = fma(rr, rr, fwd);
+                                const double d0 = xv - mv, d1 = (double)xp - mv;
+                                dle += d0 * d0 - d1 * d1;
+                            }
+                        }
+                    }
+                }
+                fwd = group_sum<kTPP>(fwd);
+                dle = group_sum<kTPP>(dle);
+                if (r == 0) {
+                    sh.fwd[p] = fwd;
+                    sh.dle[p] = dle;
+                    const uint4 wd = draw_block<false>(a.key, n, (uint32_t)t, kStreamAccept, 0u, 0u);
+                    sh.logu[p] = (t > 0) ? log(word_uniform(wd.x)) : -INFINITY;
+                }
+            }
+            lsync();
+            contraction_w<NP>(sh, A.Xp, a.tg.n, A.n_pad, KHW, A.glp, pbase);
+            {
+                double bwd = 0.0;
+                for (int f = r; f < d; f += kTPP) {
+                    const int c = col_of_wide(f, F, KHW);
+                    const double xv = (double)sh.theta[p][c];
+                    const double xpv = (double)sh.prop[p][c];
+                    const double gap = -(xpv - (double)sh.m[c]) * inv_s2r + beta * (double)glpp[c];
+                    const double rr = xv - xpv - hh * gap;
+                    bwd = fma(rr, rr, bwd);
+                }
+                bwd = group_sum<kTPP>(bwd);
+                const double inv2e2 = 1.0 / (2.0 * eps * eps);
+                const double log_alpha = sh.dle[p] * half_inv_s2r + beta * (sh.llp[p] - sh.ll[p]) -
+                                         bwd * inv2e2 + sh.fwd[p] * inv2e2;
+                const bool acc = (t == 0) || (sh.logu[p] < log_alpha);
+                if (acc) {
+                    for (int f = r; f < d; f += kTPP) {
+                        const int c = col_of_wide(f, F, KHW);
+                        sh.theta[p][c] = sh.prop[p][c];
+                        gl[c] = glpp[c];
+                    }
+                }
+                const uint64_t bal = __ballot(acc && valid && r == 0);
+                if ((tid % kWave) == 0) atomicAdd(&sh.cnt, (uint32_t)__popcll(bal));
+                if (r == 0) {
+                    sh.lw[p] = (t == 0) ? 0.0 : sh.lw[p] + (beta - beta_prev) * sh.ll[p];
+                    if (acc) sh.ll[p] = sh.llp[p];
+                    if (t > 0) {
+                        accw |= (acc ? 1u : 0u) << ((t - 1) & 31);
+                        if (((t - 1) & 31) == 31 || t == T) {
+                            if (a.acc_bits && valid)
+                                a.acc_bits[(size_t)n64 * a.acc_words + (t - 1) / 32] = accw;
+                            accw = 0;
+                        }
+                    }
+                }
+            }
+            // the cached-gradient stores complete before the barrier (the next
+            // proposals read them from other lanes)
+            __threadfence_block();
+            lsync();
+            if (t > 0 && tid == 0) {
+                double* e = a.part + ((size_t)slot * (T + 1) + (t - 1)) * 4;
+                e[3] = (first ? 0.0 : e[3]) + (double)sh.cnt;
+            }
+            beta_prev = beta;
+        }
+        if (tid < kWave) {
+            const bool vq = tid < kLPW && (pbase + tid) < a.N;
+            double mm = vq ? sh.lw[tid] : -INFINITY, ss = vq ? 1.0 : 0.0;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const double m2 = __shfl_xor(mm, o, kWave);
+                const double s2 = __shfl_xor(ss, o, kWave);
+                lse_merge(mm, ss, m2, s2);
+            }
+            if (tid == 0) {
+                double* e = a.part + ((size_t)slot * (T + 1) + T) * 4;
+                const double L = lse_value(mm, ss);
+                e[0] = first ? L : log_add(e[0], L);
+                e[1] = e[0];
+                e[2] = e[0];
+                e[3] = 0.0;
+            }
+            if (vq && a.lw_out) a.lw_out[pbase + tid] = sh.lw[tid];
+        }
+        if (valid && a.x_out)
+            for (int f = r; f < d; f += kTPP)
+                a.x_out[(size_t)n64 * d + f] = sh.theta[p][col_of_wide(f, F, KHW)];
+        lsync();
+    }
+}
+
+template <int NP>
+__global__ void __launch_bounds__(LCfgW::threads) k_oais_logreg_wide(LogregArgs A)
+{
+    extern __shared__ __align__(16) char sh_raw[];
+    LogregSharedW<NP>& sh = *reinterpret_cast<LogregSharedW<NP>*>(sh_raw);
+    logreg_setup_w<NP>(sh, A.a);
+    for (int64_t slot = blockIdx.x; slot < A.a.S; slot += gridDim.x) logreg_slot_w<NP>(sh, A, slot);
+}
+
+template <int NP>
+__global__ void __launch_bounds__(LCfgW::threads)
+    k_oais_logreg_wide_batch(const LogregArgs* __restrict__ args, const int2* __restrict__ items,
+                             int64_t nitems)
+{
+    extern __shared__ __align__(16) char sh_raw[];
+    LogregSharedW<NP>& sh = *reinterpret_cast<LogregSharedW<NP>*>(sh_raw);
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int2 item = items[it];
+        const LogregArgs A = args[item.x];
+        logreg_setup_w<NP>(sh, A.a);
+        logreg_slot_w<NP>(sh, A, (int64_t)item.y);
+        lsync();
+    }
+}
+
+// ell and its gradient for given states, wide layout (the sweep's contraction).
+template <int NP>
+__global__ void __launch_bounds__(LCfgW::threads)
+    k_logreg_eval_wide(const float* __restrict__ theta, int64_t N, int d, const float* Xp, int n,
+                       int n_pad, float* gscratch, double* ell, float* grad)
+{
+    constexpr int kTPP = LCfgW::tpp;
+    constexpr int cols = NP * 64;
+    extern __shared__ __align__(16) char sh_raw[];
+    LogregSharedW<NP>& sh = *reinterpret_cast<LogregSharedW<NP>*>(sh_raw);
+    const int tid = threadIdx.x;
+    const int p = tid / kTPP, r = tid % kTPP;
+    const int F = wide_f(d), KHW = wide_khw(d);
+    for (int e = tid; e < kLPW * (NP * 64 + 4); e += LCfgW::threads) (&sh.prop[0][0])[e] = 0.f;
+    lsync();
+    const int64_t pbase = (int64_t)blockIdx.x * kLPW;
+    const int64_t n64 = pbase + p;
+    const bool valid = n64 < N;
+    for (int f = r; f < d; f += kTPP)
+        if (valid) sh.prop[p][col_of_wide(f, F, KHW)] = theta[(size_t)n64 * d + f];
+    lsync();
+    contraction_w<NP>(sh, Xp, n, n_pad, KHW, gscratch, pbase);
+    if (valid) {
+        for (int f = r; f < d; f += kTPP)
+            grad[(size_t)n64 * d + f] = gscratch[(size_t)n64 * cols + col_of_wide(f, F, KHW)];
+        if (r == 0) ell[n64] = sh.llp[p];
+    }
+}
+
+// ---------------------------------------------------------------------------
+static bool is_wide(int d) { return d > 64; }
+
+int logreg_cols(int d) { return is_wide(d) ? 64 * wide_np(d) : 64; }
+
+int64_t logreg_tiles(int64_t N, int d)
+{
+    const int lp = is_wide(d) ? kLPW : kLP;
+    return (N + lp - 1) / lp;
+}
 
 static int n_pad_of(int n) { return ((n + kRowAlign - 1) / kRowAlign) * kRowAlign; }
 
-size_t logreg_workspace_bytes(const TargetDev& tg, int64_t)
+static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace: the packed rows [n_pad][cols], then (wide layout) the cached
+// gradients at the states and at the proposals, [tiles 32][cols] each.
+size_t logreg_workspace_bytes(const TargetDev& tg, int64_t N)
 {
-    const int np = n_pad_of(tg.n);
-    return (size_t)np * 64 * sizeof(float) + 256;
+    const int cols = logreg_cols(tg.d);
+    size_t b = a256((size_t)n_pad_of(tg.n) * cols * sizeof(float));
+    if (is_wide(tg.d)) b += 2 * a256((size_t)logreg_tiles(N, tg.d) * kLPW * cols * sizeof(float));
+    return b + 256;
 }
 
-size_t logreg_shared_bytes() { return sizeof(LogregShared); }
+void logreg_layout(const TargetDev& tg, int64_t N, void* ws, LogregArgs* A)
+{
+    const int cols = logreg_cols(tg.d);
+    char* base = static_cast<char*>(ws);
+    A->n_pad = n_pad_of(tg.n);
+    A->Xp = reinterpret_cast<float*>(base);
+    A->gl = A->glp = nullptr;
+    if (is_wide(tg.d)) {
+        const size_t xb = a256((size_t)A->n_pad * cols * sizeof(float));
+        const size_t gb = a256((size_t)logreg_tiles(N, tg.d) * kLPW * cols * sizeof(float));
+        A->gl = reinterpret_cast<float*>(base + xb);
+        A->glp = reinterpret_cast<float*>(base + xb + gb);
+    }
+}
+
+size_t logreg_shared_bytes(int d)
+{
+    if (!is_wide(d)) return sizeof(LogregShared);
+    switch (wide_np(d)) {
+    case 2: return sizeof(LogregSharedW<2>);
+    case 3: return sizeof(LogregSharedW<3>);
+    default: return sizeof(LogregSharedW<4>);
+    }
+}
 
 template <int KH>
 static hipError_t launch_kh(const LogregArgs& A, int grid, hipStream_t st)
@@ -674,6 +1152,17 @@ static hipError_t launch_kh(const LogregArgs& A, int grid, hipStream_t st)
     return hipGetLastError();
 }
 
+template <int NP>
+static hipError_t launch_w(const LogregArgs& A, int grid, hipStream_t st)
+{
+    const size_t shb = sizeof(LogregSharedW<NP>);
+    hipError_t e = hipFuncSetAttribute((const void*)k_oais_logreg_wide<NP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_oais_logreg_wide<NP>), dim3(grid), dim3(LCfgW::threads), shb, st, A);
+    return hipGetLastError();
+}
+
 template <int KH>
 static hipError_t launch_eval_kh(const float* theta, int64_t N, int d, const float* Xp,
                                  int n, int n_pad, double* ell, float* grad,
@@ -683,18 +1172,27 @@ static hipError_t launch_eval_kh(const float* theta, int64_t N, int d, const flo
     hipError_t e = hipFuncSetAttribute((const void*)k_logreg_eval<KH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_logreg_eval<KH>), dim3((unsigned)logreg_tiles(N)), dim3(LCfg::threads),
-                       shb, st, theta, N, d, Xp, n, n_pad, ell, grad);
+    hipLaunchKernelGGL((k_logreg_eval<KH>), dim3((unsigned)logreg_tiles(N, d)),
+                       dim3(LCfg::threads), shb, st, theta, N, d, Xp, n, n_pad, ell, grad);
     return hipGetLastError();
 }
 
-static void layout(const TargetDev& tg, void* ws, float** Xp, int* np)
+template <int NP>
+static hipError_t launch_eval_w(const float* theta, int64_t N, int d, const LogregArgs& A, int n,
+                                double* ell, float* grad, hipStream_t st)
 {
-    *np = n_pad_of(tg.n);
-    *Xp = static_cast<float*>(ws);
+    const size_t shb = sizeof(LogregSharedW<NP>);
+    hipError_t e = hipFuncSetAttribute((const void*)k_logreg_eval_wide<NP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_logreg_eval_wide<NP>), dim3((unsigned)logreg_tiles(N, d)),
+                       dim3(LCfgW::threads), shb, st, theta, N, d, A.Xp, n, A.n_pad, A.glp, ell,
+                       grad);
+    return hipGetLastError();
 }
 
 // Exact half-widths with a dedicated instantiation; other widths round up.
+// Above 64 features the class is 1000 + the panel count.
 static int kh_for(int d);
 
 int logreg_kh(int d) { return kh_for(d); }
@@ -705,10 +1203,15 @@ hipError_t logreg_pack_into(const TargetDev& tg, float* Xp, hipStream_t st)
     const int kh = kh_for(tg.d);
     if (kh < 0) return hipErrorInvalidValue;
     const int np = n_pad_of(tg.n);
-    const int64_t total = (int64_t)np * 64;
+    const int cols = logreg_cols(tg.d);
+    const int64_t total = (int64_t)np * cols;
     const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_logreg_pack, dim3(blocks), dim3(256), 0, st, tg.X, tg.y, tg.n, tg.d, kh,
-                       np, Xp);
+    if (is_wide(tg.d))
+        hipLaunchKernelGGL(k_logreg_pack_wide, dim3(blocks), dim3(256), 0, st, tg.X, tg.y, tg.n,
+                           tg.d, cols, np, Xp);
+    else
+        hipLaunchKernelGGL(k_logreg_pack, dim3(blocks), dim3(256), 0, st, tg.X, tg.y, tg.n, tg.d,
+                           kh, np, Xp);
     return hipGetLastError();
 }
 
@@ -725,26 +1228,34 @@ static hipError_t launch_batch_kh(const LogregArgs* args, const int2* items, int
     return hipGetLastError();
 }
 
-hipError_t logreg_prepare(const TargetDev& tg, void* ws, hipStream_t st)
+template <int NP>
+static hipError_t launch_batch_w(const LogregArgs* args, const int2* items, int64_t nitems,
+                                 int grid, hipStream_t st)
 {
-    float* Xp;
-    int np;
-    layout(tg, ws, &Xp, &np);
-    const int kh = kh_for(tg.d);
-    if (kh < 0) return hipErrorInvalidValue;
-    // columns are packed with the instantiated half-width, so features
-    // [0, KH) and [KH, d) land in columns [0, KH) and [32, 32 + d - KH)
-    const int64_t total = (int64_t)np * 64;
-    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_logreg_pack, dim3(blocks), dim3(256), 0, st, tg.X, tg.y, tg.n, tg.d, kh,
-                       np, Xp);
+    const size_t shb = sizeof(LogregSharedW<NP>);
+    hipError_t e = hipFuncSetAttribute((const void*)k_oais_logreg_wide_batch<NP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_oais_logreg_wide_batch<NP>), dim3(grid), dim3(LCfgW::threads), shb, st,
+                       args, items, nitems);
     return hipGetLastError();
 }
 
+// Packs X and y into the kernel's padded, column-permuted layout at the start
+// of ws (features [0, KH) and [KH, d) in columns [0, KH) and [32, 32 + d - KH)
+// of the 64-column layout; the panel layout above 64 features).
+hipError_t logreg_prepare(const TargetDev& tg, void* ws, hipStream_t st)
+{
+    return logreg_pack_into(tg, static_cast<float*>(ws), st);
+}
+
 #define OASMC_KH_LIST(X) X(4) X(8) X(12) X(16) X(20) X(25) X(32)
+#define OASMC_NP_LIST(X) X(2) X(3) X(4)
 
 static int kh_for(int d)
 {
+    if (d < 1 || d > kMaxDLogreg) return -1;
+    if (is_wide(d)) return 1000 + wide_np(d);
     const int kh = (d + 1) / 2;
     const int list[] = {4, 8, 12, 16, 20, 25, 32};
     for (int v : list)
@@ -756,18 +1267,17 @@ hipError_t launch_oais_logreg(const SweepArgs& a, int cus, void* ws, size_t, hip
 {
     LogregArgs A{};
     A.a = a;
-    float* Xp;
-    int np;
     const int kh = kh_for(a.tg.d);
     if (kh < 0) return hipErrorInvalidValue;
-    layout(a.tg, ws, &Xp, &np);
-    A.Xp = Xp;
-    A.n_pad = np;
+    logreg_layout(a.tg, a.N, ws, &A);
     const int grid = (int)std::min<int64_t>(a.S, (int64_t)cus);
     switch (kh) {
 #define OASMC_KH_CASE(K) case K: return launch_kh<K>(A, grid, st);
         OASMC_KH_LIST(OASMC_KH_CASE)
 #undef OASMC_KH_CASE
+#define OASMC_NP_CASE(K) case 1000 + K: return launch_w<K>(A, grid, st);
+        OASMC_NP_LIST(OASMC_NP_CASE)
+#undef OASMC_NP_CASE
     default:
         return hipErrorInvalidValue;
     }
@@ -780,6 +1290,9 @@ hipError_t launch_oais_logreg_batch(int kh, const LogregArgs* args, const int2* 
 #define OASMC_KH_CASE(K) case K: return launch_batch_kh<K>(args, items, nitems, grid, st);
         OASMC_KH_LIST(OASMC_KH_CASE)
 #undef OASMC_KH_CASE
+#define OASMC_NP_CASE(K) case 1000 + K: return launch_batch_w<K>(args, items, nitems, grid, st);
+        OASMC_NP_LIST(OASMC_NP_CASE)
+#undef OASMC_NP_CASE
     default:
         return hipErrorInvalidValue;
     }
@@ -788,15 +1301,18 @@ hipError_t launch_oais_logreg_batch(int kh, const LogregArgs* args, const int2* 
 hipError_t launch_logreg_eval(const TargetDev& tg, const float* theta, int64_t N, double* ell,
                               float* grad, void* ws, hipStream_t st)
 {
-    float* Xp;
-    int np;
     const int kh = kh_for(tg.d);
     if (kh < 0) return hipErrorInvalidValue;
-    layout(tg, ws, &Xp, &np);
+    LogregArgs A{};
+    logreg_layout(tg, N, ws, &A);
     switch (kh) {
-#define OASMC_KH_CASE(K) case K: return launch_eval_kh<K>(theta, N, tg.d, Xp, tg.n, np, ell, grad, st);
+#define OASMC_KH_CASE(K) \
+    case K: return launch_eval_kh<K>(theta, N, tg.d, A.Xp, tg.n, A.n_pad, ell, grad, st);
         OASMC_KH_LIST(OASMC_KH_CASE)
 #undef OASMC_KH_CASE
+#define OASMC_NP_CASE(K) case 1000 + K: return launch_eval_w<K>(theta, N, tg.d, A, tg.n, ell, grad, st);
+        OASMC_NP_LIST(OASMC_NP_CASE)
+#undef OASMC_NP_CASE
     default:
         return hipErrorInvalidValue;
     }

@@ -91,7 +91,7 @@ def synthetic_logw(rng: np.random.Generator, N: int, scale: float = 3.0) -> np.n
     return rng.normal(scale=scale, size=N)
 
 
-def batch_problems(n_problems: int = 256, seed_offset: int = 5, d_max_logreg: int = 64):
+def batch_problems(n_problems: int = 256, seed_offset: int = 5, d_max_logreg: int = 200):
     """Independent problems of uneven size: family by a fair coin (the d-dimensional
     Gaussian target exp(-|x - 2 1|^2 / 0.5) with RWMH, or the logistic-regression
     generator with MALA), d uniform in [5, 200] (logistic regression: [5, d_max_logreg]),

@@ -50,7 +50,8 @@ def _mixed_specs():
     # padded block of components, read from global memory
     specs.append(dict(family="gmm", d=40, N=130, T=8, move="mala",
                       params=wl.random_gmm(rng, 40, 6), eps0=0.3, eps_adapt=True, eps_kappa=2.0))
-    for d, n, N, T in [(7, 300, 64, 8), (50, 1000, 200, 16), (33, 777, 65, 4)]:
+    for d, n, N, T in [(7, 300, 64, 8), (50, 1000, 200, 16), (33, 777, 65, 4), (90, 500, 70, 8),
+                       (180, 400, 40, 4)]:
         X, y, _ = wl.logreg_data(n, d, n + d)
         specs.append(dict(family="logreg", d=d, N=N, T=T, move="mala", params=dict(X=X, y=y),
                           eps0=0.5 * d ** (-1 / 6), eps_adapt=True, eps_kappa=n / 4))

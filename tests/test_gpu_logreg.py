@@ -55,7 +55,11 @@ def _bounds(X, y, theta):
                                    (1, 1, 1),
                                    (512, 50, 100),    # no padding rows
                                    (257, 20, 70),     # one data row in the last chunk
-                                   (2048, 64, 64)])   # widest layout, whole chunks only
+                                   (2048, 64, 64),    # widest 64-column layout
+                                   # panel layouts above 64 features: 2, 3 and 4 panels,
+                                   # ragged panels and tiles, one data row past a chunk
+                                   (1000, 80, 70), (777, 130, 33), (2000, 200, 100),
+                                   (257, 65, 31), (300, 256, 40), (4096, 199, 32)])
 def test_contraction_within_fp32_bound(oa, n, d, N):
     X, y, th_star = wl.logreg_data(n, d, 1000 + n + d)
     rng = np.random.default_rng(n)
@@ -149,7 +153,10 @@ def _check(oa, X, y, g, o, T, rows, eps):
 
 
 @pytest.mark.parametrize("n,d,N,T", [(777, 50, 130, 6), (400, 7, 64, 9), (1500, 64, 70, 4),
-                                     (256, 25, 1, 3)])
+                                     (256, 25, 1, 3),
+                                     # panel layouts (tiles of 32 particles, gradients in HBM)
+                                     (800, 100, 70, 5), (600, 200, 40, 4), (300, 129, 33, 3),
+                                     (500, 65, 1, 3)])
 def test_mala_round_matches_oracle(oa, n, d, N, T):
     X, y, beta, g, o = _round(oa, n, d, N, T, seed=n + d)
     excused, tau = _check(oa, X, y, g, o, T, np.arange(N), _eps(beta, n, d))
@@ -160,11 +167,12 @@ def test_mala_round_matches_oracle(oa, n, d, N, T):
         assert abs(g["logZ"] - o["logZ"]) < 2 * tau
 
 
-@pytest.mark.parametrize("slots", [1, 3])
-def test_mala_round_several_tiles_per_slot(oa, slots):
-    """Tiles of 64 particles folded several to a moment slot (the accumulation
-    branch the default slot count reaches only above 2048 tiles)."""
-    n, d, N, T = 600, 20, 300, 5     # 5 tiles, the last one ragged
+@pytest.mark.parametrize("slots,d", [(1, 20), (3, 20), (2, 150)])
+def test_mala_round_several_tiles_per_slot(oa, slots, d):
+    """Tiles folded several to a moment slot (the accumulation branch the
+    default slot count reaches only above 2048 tiles): 5 tiles of 64
+    particles at d = 20, 10 tiles of 32 at d = 150, the last one ragged."""
+    n, N, T = 600, 300, 5
     X, y, beta, g, o = _round(oa, n, d, N, T, seed=41, slots=slots)
     excused, tau = _check(oa, X, y, g, o, T, np.arange(N), _eps(beta, n, d))
     if not excused:
@@ -173,10 +181,11 @@ def test_mala_round_several_tiles_per_slot(oa, slots):
         assert abs(g["logZ"] - o["logZ"]) < 2 * tau
 
 
-def test_mala_round_with_reference_mean(oa):
-    rm = np.linspace(-0.5, 0.5, 10).astype(np.float32)
-    X, y, beta, g, o = _round(oa, 600, 10, 100, 5, seed=3, ref_mean=rm)
-    _check(oa, X, y, g, o, 5, np.arange(100), _eps(beta, 600, 10))
+@pytest.mark.parametrize("d", [10, 90])
+def test_mala_round_with_reference_mean(oa, d):
+    rm = np.linspace(-0.5, 0.5, d).astype(np.float32)
+    X, y, beta, g, o = _round(oa, 600, d, 100, 5, seed=3, ref_mean=rm)
+    _check(oa, X, y, g, o, 5, np.arange(100), _eps(beta, 600, d))
 
 
 def test_full_size_sampled_particles(oa):
