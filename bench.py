@@ -63,6 +63,17 @@ def logreg_spec(oa, wl):
     return Spec(w, prob, kw, 11, w.N, None, "long run", 16)
 
 
+def logreg_d200_spec(oa, wl):
+    """The panel layout: n = 5000, d = 200, N = 8192, T = 1, 2, ..., 512
+    (10 rounds); no log Z error by default (its long-run reference costs
+    minutes at this d)."""
+    w = wl.logreg_n5000_d200()
+    prob = oa.Problem.logreg(w.params["X"], w.params["y"], w.ref_sigma2)
+    kw = dict(move="mala", budget="double_t", T1=1, T_max=512, eps0=w.eps0, eps_adapt=True,
+              eps_kappa=w.params["X"].shape[0] / 4.0, accept_target=0.574, interp=0)
+    return Spec(w, prob, kw, 10, w.N, None, "long run", 0)
+
+
 def gauss_spec(oa, wl):
     """The d = 10 Gaussian workload as stated: N = 128, 256, 512, 1024 over 4
     rounds, T = 64 (log Z = 5 ln(pi/2))."""
@@ -94,7 +105,8 @@ def asmc_spec(oa, wl, trigger):
     return Spec(w, prob, kw, 12, w.N, 50 * np.log(0.2 * np.pi), "closed form", 4)
 
 
-WORKLOADS = {"logreg": logreg_spec, "gauss": gauss_spec, "gauss_sat": gauss_sat_spec,
+WORKLOADS = {"logreg": logreg_spec, "logreg_d200": logreg_d200_spec, "gauss": gauss_spec,
+             "gauss_sat": gauss_sat_spec,
              "asmc": lambda oa, wl: asmc_spec(oa, wl, "cess"),
              "asmc_ess": lambda oa, wl: asmc_spec(oa, wl, "ess"),
              "asmc_dar": lambda oa, wl: asmc_spec(oa, wl, "dar")}
@@ -307,17 +319,22 @@ def pt_workload(args, oa, wl, torch) -> int:
     """Parallel tempering through the duality (Sec. "Computational duality with
     parallel tempering") on the d = 10 Gaussian target: K = 2048 copies of
     N' + 1 = 64 chains (one wave per copy) on the schedule Alg. 3 builds from an
-    OAIS round, T' = 64 iterations of RWMH plus even/odd swaps.  One step = one
-    PT run; value = chain-steps/s; the stepping-stone log Z error over seeds
-    against the closed form, Lambda_PT and the round-trip rate beside it."""
+    OAIS round, T' = 16384 iterations of RWMH plus even/odd swaps, RWMH scale
+    2.38 / sqrt(d) times the standard deviation of pi_beta along the path
+    (1 / sqrt(1 + 3 beta) here).  One step = one PT run; value = chain-steps/s;
+    the stepping-stone log Z error over seeds against the closed form,
+    Lambda_PT and the round-trip rate beside it.  Every chain starts from eta,
+    so the stepping-stone estimate carries a burn-in bias of order 1 / T'
+    (about -4.4, -1.1, -0.29 at T' = 256, 1024, 4096 in the oracle), and the
+    round-trip rate approaches the non-reversible PT value from below."""
     import oracle as orc
 
     w = wl.gaussian_d10()
     prob = oa.Problem.gauss(w.params["mu"], w.params["sigma2"], w.ref_sigma2)
-    K, Np, Tp = 2048, 63, 64
+    K, Np, Tp = 2048, 63, 16384
     r0 = oa.run(prob, 1024, 2, seed=args.seed, move="rwmh", budget="fixed", T1=64, eps0=w.eps0)
     beta, _ = oa.adapt_schedule(r0["beta"][1], r0["log_g"][1], Np)
-    eps = np.full(Np + 1, w.eps0)
+    eps = 2.38 / np.sqrt(w.d) / np.sqrt(1.0 + 3.0 * np.asarray(beta))
     for i in range(args.warmup):
         oa.pt(prob, K, beta, eps, Tp, args.seed + i)
     torch.cuda.synchronize()
@@ -597,7 +614,8 @@ def main() -> int:
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
                 "traffic": TRAFFIC.get(args.workload),
-                "kernel": "k_oais_logreg_batch<25>", "avg_launch_ms": avg_ms,
+                "kernel": ("k_oais_logreg_wide_batch<4>" if w.d > 64 else
+                           "k_oais_logreg_batch<25>"), "avg_launch_ms": avg_ms,
                 "launches": prof["launches"]}
     else:
         rate = prof["particle_steps"] / (prof["kernel_ms"] * 1e-3) if prof["kernel_ms"] else None
@@ -609,7 +627,7 @@ def main() -> int:
                 "work_lane_cycles_per_particle_step": ALU_WORK[args.workload],
                 "avg_launch_ms": avg_ms, "launches": prof["launches"]}
     err = None
-    if args.rmse_seeds != 0:
+    if args.rmse_seeds > 0 or (args.rmse_seeds < 0 and spec.seeds > 0):
         log("log Z error over seeds (untimed) ...")
         err = logz_error(oa, spec, args, last_logz, res)
     cpu = None

@@ -58,7 +58,8 @@ typedef enum { OASMC_RWMH = 1, OASMC_MALA = 2, OASMC_HMC = 3, OASMC_RWMH3 = 4 } 
  *   OASMC_LOGREG: gamma(x) = eta(x) prod_i s(z_i)^y_i (1 - s(z_i))^(1-y_i),
  *                 z_i = X[i,:] . x, s the logistic function;  X[n][d]
  *                 row-major, y[n] in {0, 1} (a label other than 0 is read
- *                 as 1).  ell is the log-likelihood.
+ *                 as 1), 1 <= d <= 256 (OASMC_EUNSUPPORTED above).  ell is
+ *                 the log-likelihood.
  *   OASMC_GMM   : gamma(x) = (1/K) sum_k exp(-|x - means[k]|^2 / (2 exp(2 log_scales[k])))
  *                 means[K][d], log_scales[K].
  *   OASMC_UNID  : the unidentifiable product parameterisation (appendix on the

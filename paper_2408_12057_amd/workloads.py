@@ -56,6 +56,14 @@ def logreg_n10000_d50(N: int = 16384, n: int = 10000, d: int = 50) -> Workload:
                     T=1000, eps0=0.5 * d ** (-1.0 / 6.0))
 
 
+def logreg_n5000_d200(N: int = 8192, n: int = 5000, d: int = 200) -> Workload:
+    """Bayesian logistic regression at the batch's widest size, X in
+    R^{5000 x 200}, prior eta = N(0, I_200), MALA (the panel layout)."""
+    X, y, _ = logreg_data(n, d, DATA_SEED + 3)
+    return Workload("logreg_n5000_d200_mala", "logreg", d, 1.0, "mala", dict(X=X, y=y), N=N,
+                    T=512, eps0=0.5 * d ** (-1.0 / 6.0))
+
+
 def gmm8_d100(N: int = 65536) -> Workload:
     """Equal-weight mixture of 8 Gaussians in d = 100: means iid N(0, 16 I),
     covariance 0.1 I, eta = N(0, 25 I); HMC with 5 leapfrog steps."""
