@@ -450,6 +450,20 @@ int oasmc_logreg_eval(oasmc_handle* h, const oasmc_problem* problem, int64_t N,
                       const float* theta, double* ell, float* grad, void* stream);
 
 /*
+ * ell(x) = log gamma(x) - log eta(x) and its gradient for the closed-form
+ * families (OASMC_GAUSS, OASMC_GMM, OASMC_UNID; the target definitions above)
+ * at N given states x[N][d] (device fp32, row-major), evaluated by the
+ * annealing sweeps' own binary64 particle arithmetic in the lane layout of
+ * the shape lpp lanes x dpl coordinates per particle (lpp = dpl = 0: the
+ * sweep's default shape for this d and N; otherwise a built shape with
+ * lpp dpl >= d, else OASMC_EINVAL).  Writes ell[N] and grad[N][d] (device
+ * binary64; the Unid target's gradient is zero).  Device-synchronous on
+ * `stream`.  Logistic regression: OASMC_EINVAL (use oasmc_logreg_eval).
+ */
+int oasmc_target_eval(oasmc_handle* h, const oasmc_problem* problem, int64_t N, const float* x,
+                      int32_t lpp, int32_t dpl, double* ell, double* grad, void* stream);
+
+/*
  * Live timing of the annealing-sweep kernels.  enable = 1 starts recording a
  * HIP event pair around every sweep-kernel launch (on the launch stream) and
  * clears the totals; enable = 0 stops.  Outputs (each may be NULL): summed

@@ -8,7 +8,7 @@ Importing the package does not load the library; the first call does, and it
 raises if the library is missing.
 """
 from .api import (  # noqa: F401
-    Problem, asmc, adapt_schedule, dar_times, rejuvenate, zja, pt, autotune, shape, run, resample, resample_noalloc, philox, logreg_eval, profile,
+    Problem, asmc, adapt_schedule, dar_times, rejuvenate, zja, pt, autotune, shape, run, resample, resample_noalloc, philox, logreg_eval, target_eval, profile,
     library_path,
     OasmcError, logZ_backward, LogZ, BatchItem, run_batch,
 )

@@ -113,6 +113,8 @@ def _load():
     L.oasmc_run_batch.argtypes = [vp, C.POINTER(_BatchProblem), C.c_int32, C.c_int32, C.c_int32,
                                   C.POINTER(_BatchOut), vp]
     L.oasmc_logreg_eval.argtypes = [vp, C.POINTER(_Problem), C.c_int64, vp, vp, vp, vp]
+    L.oasmc_target_eval.argtypes = [vp, C.POINTER(_Problem), C.c_int64, vp, C.c_int32, C.c_int32,
+                                    vp, vp, vp]
     L.oasmc_pt.argtypes = [vp, C.POINTER(_Problem), C.POINTER(_Kernel), C.c_int32, C.c_int32,
                            C.c_int32, vp, vp, C.c_uint64, C.c_uint32, C.c_uint32, vp, vp, vp, vp,
                            vp, vp, vp]
@@ -130,7 +132,7 @@ def _load():
               "oasmc_dar_times",
               "oasmc_run", "oasmc_resample", "oasmc_resample_noalloc", "oasmc_philox", "oasmc_logreg_eval",
               "oasmc_profile", "oasmc_logZ_backward", "oasmc_run_batch", "oasmc_rejuvenate",
-              "oasmc_zja", "oasmc_autotune", "oasmc_shape", "oasmc_pt"):
+              "oasmc_zja", "oasmc_autotune", "oasmc_shape", "oasmc_pt", "oasmc_target_eval"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -499,6 +501,22 @@ def logreg_eval(problem: Problem, theta: torch.Tensor):
     _check(_load().oasmc_logreg_eval(_handle(problem.device.index or 0), C.byref(P), N,
                                      C.c_void_p(theta.data_ptr()), C.c_void_p(ell.data_ptr()),
                                      C.c_void_p(grad.data_ptr()), _stream(problem.device)))
+    return ell, grad
+
+
+def target_eval(problem: Problem, x: torch.Tensor, lpp: int = 0, dpl: int = 0):
+    """ell (float64) and its gradient (float64) of a closed-form target at
+    states x [N, d], by the sweeps' particle arithmetic in the lane layout
+    lpp x dpl (0, 0: the default shape)."""
+    x = x.to(device=problem.device, dtype=torch.float32).contiguous()
+    N = int(x.shape[0])
+    ell = torch.empty(N, dtype=torch.float64, device=problem.device)
+    grad = torch.empty((N, problem.d), dtype=torch.float64, device=problem.device)
+    P = problem.c()
+    _check(_load().oasmc_target_eval(_handle(problem.device.index or 0), C.byref(P), N,
+                                     C.c_void_p(x.data_ptr()), int(lpp), int(dpl),
+                                     C.c_void_p(ell.data_ptr()), C.c_void_p(grad.data_ptr()),
+                                     _stream(problem.device)))
     return ell, grad
 
 

@@ -193,6 +193,15 @@ struct PtArgs {
     double* fpart;        // device [K][16][2d]
 };
 
+// ell and grad ell of the closed-form families at given states, evaluated by
+// the sweeps' own particle arithmetic in the lane layout of a shape.
+struct EvalArgs {
+    SweepArgs a;          // target, N, ntiles of the shape
+    const float* x;       // device [N][d]
+    double* ell;          // device [N]
+    double* grad;         // device [N][d]
+};
+
 // Validated launch configuration of a VALU sweep.
 struct ValuShape {
     int lpp;  // lanes per particle
@@ -237,6 +246,9 @@ hipError_t launch_resample_step(const SweepArgs& a, const AsmcState& z, int t, h
 // of the tile sums into out [2 d + 1] (averages over N T samples, accepted fraction).
 hipError_t launch_rejuv(const RejuvArgs& R, const ValuShape& s, hipStream_t st);
 hipError_t launch_pt(const PtArgs& A, const ValuShape& s, hipStream_t st);
+// The evaluation kernel is built for the (family, move) pairs (kGauss, kMala),
+// (kGmm, kMala) and (kUnid, kRwmh): E.a.move must name that pair's move.
+hipError_t launch_target_eval(const EvalArgs& E, const ValuShape& s, hipStream_t st);
 // Dynamic LDS of one PT workgroup (staged target parameters, then the
 // replicas' ell, rejection sums, temperature maps and a reduction buffer).
 __host__ __device__ inline size_t pt_shared_bytes(const PtArgs& A, int lpp, int dpl)

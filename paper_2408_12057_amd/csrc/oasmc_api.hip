@@ -1452,6 +1452,48 @@ int oasmc_logreg_eval(oasmc_handle* h, const oasmc_problem* problem, int64_t N,
     return OASMC_OK;
 }
 
+int oasmc_target_eval(oasmc_handle* h, const oasmc_problem* problem, int64_t N, const float* x,
+                      int32_t lpp, int32_t dpl, double* ell, double* grad, void* stream)
+{
+    if (!h || !problem || !x || !ell || !grad) return fail(OASMC_EINVAL, "NULL argument");
+    if (problem->family == OASMC_LOGREG)
+        return fail(OASMC_EINVAL, "logistic regression is evaluated by oasmc_logreg_eval");
+    oasmc_kernel k{};
+    k.move = problem->family == OASMC_UNID ? OASMC_RWMH : OASMC_MALA;
+    k.leapfrog = 1;
+    const int cs = check_problem(problem, &k);
+    if (cs) return cs;
+    if (N < 1 || N > ((int64_t)1 << 30)) return fail(OASMC_EINVAL, "N must lie in [1, 2^30]");
+    ValuShape shape{};
+    if (lpp == 0 && dpl == 0) {
+        if (!valu_shape(problem->d, N, &shape))
+            return fail(OASMC_EUNSUPPORTED, "no kernel shape for d=%d", problem->d);
+    } else {
+        bool known = false;
+        for (const ValuShape& c : kShapes) known |= (c.lpp == lpp && c.dpl == dpl);
+        if (!known || (int64_t)lpp * dpl < problem->d)
+            return fail(OASMC_EINVAL, "shape %d x %d is not built or does not hold d=%d", lpp, dpl,
+                        problem->d);
+        if (problem->family == OASMC_UNID && !(lpp == 1 && dpl == 4))
+            return fail(OASMC_EUNSUPPORTED, "the Unid target runs on one lane of 4 coordinates");
+        shape = ValuShape{lpp, dpl};
+    }
+    HIP_TRY(hipSetDevice(h->device));
+    EvalArgs E{};
+    E.a.tg = target_dev(problem);
+    E.a.move = k.move;
+    E.a.leapfrog = 1;
+    E.a.N = N;
+    E.a.ntiles = valu_tiles(N, shape);
+    E.x = x;
+    E.ell = ell;
+    E.grad = grad;
+    HIP_TRY(launch_target_eval(E, shape, (hipStream_t)stream));
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    g_err.clear();
+    return OASMC_OK;
+}
+
 int oasmc_logZ_backward(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel* kernel,
                         int64_t N, int32_t T, const double* beta, const double* eps, uint64_t seed,
                         uint32_t round_k, uint32_t problem_id, double* logZ, double* grad,

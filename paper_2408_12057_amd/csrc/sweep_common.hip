@@ -656,6 +656,11 @@ hipError_t launch_rejuv(const RejuvArgs& R, const ValuShape& s, hipStream_t st)
     return dispatch_all(4, R.a, s, 0, nullptr, 0, st, nullptr, &R);
 }
 
+hipError_t launch_target_eval(const EvalArgs& E, const ValuShape& s, hipStream_t st)
+{
+    return dispatch_all(6, E.a, s, 0, nullptr, 0, st, nullptr, &E);
+}
+
 // Column b of the tile sums over tiles in a fixed order (one wave per column).
 __global__ void __launch_bounds__(kWave) k_rejuv_reduce(const double* __restrict__ tsum,
                                                          int64_t ntiles, int d, double samples,

@@ -1103,6 +1103,44 @@ __global__ void __launch_bounds__(1024) k_pt(PtArgs A)
     }
 }
 
+// ell and grad ell at given binary32 states: the particle's coordinates are
+// loaded into the lane layout (zero beyond d) and evaluated by the sweep's
+// Particle::eval, one lane group per particle.
+template <int FAM, int LPP, int DPL>
+__global__ void __launch_bounds__(256) k_target_eval(EvalArgs E)
+{
+    constexpr int P = kWave / LPP;
+    extern __shared__ __align__(16) char sh_dyn[];
+    const SweepArgs& a = E.a;
+    const ParView pv = stage_params_lanes<LPP, DPL>(a.tg, sh_dyn);
+    const Consts c = make_consts(a.tg);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int r = lane % LPP, pl = lane / LPP;
+    const int64_t tile =
+        (int64_t)blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (tile >= a.ntiles) return;
+    // a tile's particles beyond N evaluate zeros and write nothing, so the
+    // lane groups of a wave stay converged through the evaluation
+    const int64_t n64 = tile * P + pl;
+    const bool valid = n64 < a.N;
+    const int d = a.tg.d;
+    float x[DPL];
+    double g[DPL];
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+        const int i = r * DPL + j;
+        x[j] = (valid && i < d) ? E.x[(size_t)n64 * d + i] : 0.f;
+    }
+    const double ell = Particle<FAM, LPP, DPL>::template eval<true>(a.tg, c, pv, r, x, g);
+    if (!valid) return;
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+        const int i = r * DPL + j;
+        if (i < d) E.grad[(size_t)n64 * d + i] = g[j];
+    }
+    if (r == 0) E.ell[n64] = ell;
+}
+
 template <int FAM, int MOVE, int LPP, int DPL>
 struct Launch {
     static hipError_t oais(const SweepArgs& a, int grid_waves, hipStream_t st)
@@ -1143,6 +1181,20 @@ struct Launch {
                            shb, st, A);
         return hipGetLastError();
     }
+    static hipError_t eval(const EvalArgs& E, hipStream_t st)
+    {
+        // one instantiation per family: the evaluation does not depend on the move
+        if constexpr (MOVE == kMala || (FAM == kUnid && MOVE == kRwmh)) {
+            const int64_t blocks = (E.a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+            hipLaunchKernelGGL((k_target_eval<FAM, LPP, DPL>), dim3((unsigned)blocks), dim3(256),
+                               params_bytes_lanes(E.a.tg, LPP, DPL), st, E);
+            return hipGetLastError();
+        } else {
+            (void)E;
+            (void)st;
+            return hipErrorInvalidValue;
+        }
+    }
     static hipError_t step(const SweepArgs& a, const AsmcState& z, int t, hipStream_t st)
     {
         const int64_t blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -1159,6 +1211,7 @@ hipError_t valu_dispatch(int what, const SweepArgs& a, const ValuShape& s, int g
 {
     const RejuvArgs* rj = static_cast<const RejuvArgs*>(ext);
     const PtArgs* pt = static_cast<const PtArgs*>(ext);
+    const EvalArgs* ev = static_cast<const EvalArgs*>(ext);
 #define OASMC_CASE(L, D)                                                     \
     if (s.lpp == L && s.dpl == D) {                                          \
         if (what == 0) return Launch<FAM, MOVE, L, D>::oais(a, gw, st);      \
@@ -1168,6 +1221,7 @@ hipError_t valu_dispatch(int what, const SweepArgs& a, const ValuShape& s, int g
                                                   b->nitems, gw, st);        \
         if (what == 4) return Launch<FAM, MOVE, L, D>::rejuv(*rj, st);       \
         if (what == 5) return Launch<FAM, MOVE, L, D>::pt(*pt, st);          \
+        if (what == 6) return Launch<FAM, MOVE, L, D>::eval(*ev, st);        \
         return Launch<FAM, MOVE, L, D>::step(a, *z, t, st);                  \
     }
     OASMC_CASE(1, 4)
