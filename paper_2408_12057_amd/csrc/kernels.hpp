@@ -339,7 +339,9 @@ int logreg_cols(int d);    // packed columns (64, or 64 per panel above 64 featu
 // Points A's data and gradient buffers into a workspace of
 // logreg_workspace_bytes(tg, N) bytes.
 void logreg_layout(const TargetDev& tg, int64_t N, void* ws, LogregArgs* A);
-hipError_t logreg_pack_into(const TargetDev& tg, float* Xp, hipStream_t st);
+// Packs the rows into a workspace laid out by logreg_layout
+// (logreg_workspace_bytes(tg, N) bytes).
+hipError_t logreg_pack_into(const TargetDev& tg, int64_t N, void* ws, hipStream_t st);
 hipError_t launch_oais_logreg_batch(int kh, const LogregArgs* args, const int2* items,
                                    int64_t nitems, int grid, hipStream_t st);
 hipError_t launch_logreg_eval(const TargetDev& tg, const float* theta, int64_t N, double* ell,
@@ -347,7 +349,7 @@ hipError_t launch_logreg_eval(const TargetDev& tg, const float* theta, int64_t N
 size_t logreg_workspace_bytes(const TargetDev& tg, int64_t N);
 size_t logreg_shared_bytes(int d);
 // Packs X and y into the kernel's padded, column-permuted layout in ws.
-hipError_t logreg_prepare(const TargetDev& tg, void* ws, hipStream_t st);
+hipError_t logreg_prepare(const TargetDev& tg, int64_t N, void* ws, hipStream_t st);
 int64_t logreg_tiles(int64_t N, int d);
 // Sets / clears the message oasmc_last_error() returns on this thread.
 int record_error(int code, const char* fmt, ...);

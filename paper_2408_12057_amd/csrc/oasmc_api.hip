@@ -712,9 +712,8 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
         }
         for (int p = 0; p < P; ++p)
             if (ps[p].logreg) {
-                float* Xp = at<float>(ws, ps[p].off_data);
                 const TargetDev tg = target_dev(&ps[p].prob);
-                HIP_TRY(logreg_pack_into(tg, Xp, st));
+                HIP_TRY(logreg_pack_into(tg, ps[p].N, ws + ps[p].off_data, st));
             }
     }
     HIP_TRY(hipStreamSynchronize(st));
@@ -1015,7 +1014,7 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
         if (problem->family == OASMC_LOGREG) {
             wb = logreg_workspace_bytes(a.tg, N);
             HIP_TRY(h->get(B_LOGREG, wb, &ws));
-            HIP_TRY(logreg_prepare(a.tg, ws, st));
+            HIP_TRY(logreg_prepare(a.tg, N, ws, st));
         }
         if (h->prof) HIP_TRY(hipEventRecord(h->ev0, st));
         if (problem->family == OASMC_LOGREG) {
@@ -1445,7 +1444,7 @@ int oasmc_logreg_eval(oasmc_handle* h, const oasmc_problem* problem, int64_t N,
     const TargetDev tg = target_dev(problem);
     void* ws;
     HIP_TRY(h->get(B_LOGREG, logreg_workspace_bytes(tg, N), &ws));
-    HIP_TRY(logreg_prepare(tg, ws, (hipStream_t)stream));
+    HIP_TRY(logreg_prepare(tg, N, ws, (hipStream_t)stream));
     HIP_TRY(launch_logreg_eval(tg, theta, N, ell, grad, ws, (hipStream_t)stream));
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
     g_err.clear();

@@ -26,11 +26,18 @@
 // Labels are folded into the rows: row i is stored as s_i X_i with
 // s_i = 2 y_i - 1, so the first product gives u_i = s_i z_i and, with
 // sigma the logistic function,
-//     y_i z_i - softplus(z_i) = min(u_i, 0) - log(1 + exp(-|u_i|)),
-//     (y_i - sigma(z_i)) X_i  = sigma(-u_i) (s_i X_i),
-// i.e. the epilogue needs no labels and the second product takes sigma(-u)
-// directly.  Padding rows are zero, so u = 0 and they add nothing to either
-// product; their factor 2 in the product of (1 + exp(-|u|)) is divided out.
+//     y_i z_i - softplus(z_i) = log sigma(u_i) = min(u_i, 0) + log max(s_i, 1 - s_i),
+//     (y_i - sigma(z_i)) X_i  = s_i (s_i X_i)   with s_i = sigma(-u_i) = 1 / (1 + exp(u_i)),
+// i.e. the epilogue needs no labels and the second product takes s directly
+// (1 / (1 + exp(u)) has the exact limits 0 and 1 at both ends).  The factor
+// max(s, 1 - s) lies in [1/2, 1], so a running product over a chunk's rows
+// cannot underflow and its log is taken once per chunk.  The rounding of
+// exp(u) reaches ell with the weight sigma(-|u|) of the bounded form (small
+// for well-classified rows), not with the weight sigma(u) that
+// u - log(1 + exp(u)) would give it (which biases ell by the exponential's
+// rounding over many rows).  Padding rows are zero, so u = 0 and they add
+// nothing to either product; their factor 1/2 in the running product is
+// divided out.
 #include "kernels.hpp"
 
 namespace oasmc {
@@ -117,38 +124,41 @@ __global__ void k_logreg_pack(const float* __restrict__ X, const float* __restri
 // (the 32 x 32 output layout of v_mfma_f32_32x32x2f32).
 __device__ __forceinline__ int slot_row(int q, int h) { return 8 * (q / 4) + 4 * h + (q % 4); }
 
-// The epilogue of one signed logit u = s z, in two halves:
-//   a: e = exp(-|u|), 1 + e, 1 / (1 + e)
-//   b: the row's share min(u, 0) of ell; the factor 1 + e of the running
-//      product whose log2 gives the sum of log(1 + e) over the chunk's rows
-//      (one log per chunk instead of one per row); and sigma(-u), which
-//      replaces u as the second product's operand.
-// On gfx950 FP32 matrix-core instructions and VALU instructions do not run
-// concurrently on a SIMD (measured: the time of an interleaved sequence is
-// the sum of the two), so every VALU instruction here costs matrix-core
-// time; the halves are placed between the gradient products only to keep
-// the wave's dependencies short.
+// The epilogue of one signed logit u, in two halves:
+//   a: w = 1 + exp(u)  (exp(u) = 2^(u log2 e), +inf above about 88)
+//   b: s = 1 / w, which replaces u as the second product's operand; min(u, 0)
+//      into the running sum and max(s, 1 - s) into the running product whose
+//      log2 gives the rest of the chunk's rows' ell (one log per chunk).
+// Seven VALU instructions and two transcendentals per logit.  On gfx950 FP32
+// matrix-core instructions and VALU instructions do not run concurrently on
+// a SIMD (measured: the time of an interleaved sequence is the sum of the
+// two), so every VALU instruction here costs matrix-core time; the halves are
+// placed between the gradient products only to keep the wave's dependencies
+// short.
+constexpr float kLog2eF = 1.44269504088896341f;
+
 struct EpiTmp {
-    float e, ope, inv;
+    float w;
 };
 
 __device__ __forceinline__ void epi_a(float u, EpiTmp& t)
 {
-    t.e = __expf(-fabsf(u));
-    t.ope = 1.0f + t.e;
-    t.inv = __builtin_amdgcn_rcpf(t.ope);
-    // an empty volatile asm that consumes and redefines the three values pins
-    // this half where it is written (the IR passes would otherwise sink it
-    // next to its uses in the second half)
-    asm volatile("" : "+v"(t.e), "+v"(t.ope), "+v"(t.inv));
+    t.w = 1.0f + __builtin_amdgcn_exp2f(u * kLog2eF);
+    // an empty volatile asm that consumes and redefines the value pins this
+    // half where it is written (the IR passes would otherwise sink it next to
+    // its uses in the second half)
+    asm volatile("" : "+v"(t.w));
 }
 
-__device__ __forceinline__ float epi_b(float u, const EpiTmp& t, float& llc, float& prod)
+__device__ __forceinline__ float epi_b(float u, const EpiTmp& t, float& lin, float& prod)
 {
-    const bool pos = u >= 0.f;
-    llc += pos ? 0.f : u;
-    prod *= t.ope;
-    return pos ? t.e * t.inv : t.inv;
+    const float sg = __builtin_amdgcn_rcpf(t.w);
+    // min(u, 0) = (u - |u|) / 2 and max(s, 1 - s) = 1/2 + |s - 1/2|: absolute
+    // values are free source modifiers, where fminf / fmaxf would add NaN
+    // canonicalisations
+    lin = fmaf(0.5f, u - fabsf(u), lin);
+    prod *= 0.5f + fabsf(sg - 0.5f);
+    return sg;
 }
 
 // Padding rows among the 16 rows a lane half h holds in a chunk whose first
@@ -278,12 +288,12 @@ __device__ __forceinline__ void contraction(LogregShared& sh, const float* __res
         // row slots: the epilogue of slot q + 1 is issued between the four
         // gradient products of slot q (G[g][ft] += sigma(-u_g)^T X'_ft over
         // its rows)
-        float llc[2] = {0.f, 0.f}, prod[2] = {1.f, 1.f};
+        float lin[2] = {0.f, 0.f}, prod[2] = {1.f, 1.f};
         EpiTmp t0, t1;
         epi_a(acc[0][0], t0);
-        acc[0][0] = epi_b(acc[0][0], t0, llc[0], prod[0]);
+        acc[0][0] = epi_b(acc[0][0], t0, lin[0], prod[0]);
         epi_a(acc[1][0], t1);
-        acc[1][0] = epi_b(acc[1][0], t1, llc[1], prod[1]);
+        acc[1][0] = epi_b(acc[1][0], t1, lin[1], prod[1]);
         float bx0 = stc[slot_row(0, h)][j], bx1 = stc[slot_row(0, h)][32 + j];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
@@ -294,24 +304,25 @@ __device__ __forceinline__ void contraction(LogregShared& sh, const float* __res
             if (q < 15) epi_a(acc[0][qn], t0);
             __builtin_amdgcn_sched_barrier(0);
             G[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[1][q], bx0, G[1][0], 0, 0, 0);
-            if (q < 15) acc[0][qn] = epi_b(acc[0][qn], t0, llc[0], prod[0]);
+            if (q < 15) acc[0][qn] = epi_b(acc[0][qn], t0, lin[0], prod[0]);
             __builtin_amdgcn_sched_barrier(0);
             G[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[0][q], bx1, G[0][1], 0, 0, 0);
             if (q < 15) epi_a(acc[1][qn], t1);
             __builtin_amdgcn_sched_barrier(0);
             G[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[1][q], bx1, G[1][1], 0, 0, 0);
-            if (q < 15) acc[1][qn] = epi_b(acc[1][qn], t1, llc[1], prod[1]);
+            if (q < 15) acc[1][qn] = epi_b(acc[1][qn], t1, lin[1], prod[1]);
             __builtin_amdgcn_sched_barrier(0);
             bx0 = nbx0;
             bx1 = nbx1;
         }
-        // sum of log(1 + e) over the chunk's data rows: divide out the
-        // padding rows' exact factors of 2, one log per chunk
+        // the chunk's data rows: the sum of min(u, 0) plus the log of the
+        // product (the padding rows' exact factors of 1/2 divided out), one log
+        // per chunk
         const int npad_rows = padding_rows(n - (r0 + c * kRows), h);
 #pragma unroll
         for (int g = 0; g < 2; ++g) {
-            const float lp = __builtin_amdgcn_logf(__builtin_amdgcn_ldexpf(prod[g], -npad_rows));
-            llacc[g] += (double)llc[g] - kLn2 * (double)lp;
+            const float lp = __builtin_amdgcn_logf(__builtin_amdgcn_ldexpf(prod[g], npad_rows));
+            llacc[g] += (double)lin[g] + kLn2 * (double)lp;
         }
         wsync();
     }
@@ -374,9 +385,10 @@ __device__ __forceinline__ int feat_of(int r, int u) { return 4 * (r + TPP * (u 
 // The parameters shared by every tile of a problem: zero the particle arrays
 // (columns beyond d stay zero) and stage the reference mean in packed columns.
 template <int KH>
-__device__ __forceinline__ void logreg_setup(LogregShared& sh, const SweepArgs& a)
+__device__ __forceinline__ void logreg_setup(LogregShared& sh, const LogregArgs& A)
 {
     constexpr int kLThreads = LCfg::threads;
+    const SweepArgs& a = A.a;
     const int tid = threadIdx.x;
     const int d = a.tg.d;
     for (int e = tid; e < kLP * kPs; e += kLThreads) {
@@ -592,7 +604,7 @@ __global__ void __launch_bounds__(LCfg::threads) k_oais_logreg(LogregArgs A)
 {
     extern __shared__ __align__(16) char sh_raw[];
     LogregShared& sh = *reinterpret_cast<LogregShared*>(sh_raw);
-    logreg_setup<KH>(sh, A.a);
+    logreg_setup<KH>(sh, A);
     for (int64_t slot = blockIdx.x; slot < A.a.S; slot += gridDim.x) logreg_slot<KH>(sh, A, slot);
 }
 
@@ -608,7 +620,7 @@ __global__ void __launch_bounds__(LCfg::threads)
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int2 item = items[it];
         const LogregArgs A = args[item.x];
-        logreg_setup<KH>(sh, A.a);
+        logreg_setup<KH>(sh, A);
         logreg_slot<KH>(sh, A, (int64_t)item.y);
         lsync();
     }
@@ -784,16 +796,16 @@ __device__ __forceinline__ void contraction_w(LogregSharedW<NP>& sh, const float
         }
         // the epilogue (see epi_a, epi_b): acc becomes sigma(-u)
         {
-            float llc = 0.f, prod = 1.f;
+            float prod = 1.f, lin = 0.f;
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 EpiTmp tq;
                 epi_a(acc[q], tq);
-                acc[q] = epi_b(acc[q], tq, llc, prod);
+                acc[q] = epi_b(acc[q], tq, lin, prod);
             }
             const int npad_rows = padding_rows(n - (r0 + c * kRows), h);
-            const float lp = __builtin_amdgcn_logf(__builtin_amdgcn_ldexpf(prod, -npad_rows));
-            llacc += (double)llc - kLn2 * (double)lp;
+            const float lp = __builtin_amdgcn_logf(__builtin_amdgcn_ldexpf(prod, npad_rows));
+            llacc += (double)lin + kLn2 * (double)lp;
         }
         // gradient, panel by panel: G[p][ft] += sigma(-u)^T X'_{p, ft}
 #pragma unroll
@@ -860,8 +872,9 @@ __device__ __forceinline__ void contraction_w(LogregSharedW<NP>& sh, const float
 }
 
 template <int NP>
-__device__ __forceinline__ void logreg_setup_w(LogregSharedW<NP>& sh, const SweepArgs& a)
+__device__ __forceinline__ void logreg_setup_w(LogregSharedW<NP>& sh, const LogregArgs& A)
 {
+    const SweepArgs& a = A.a;
     const int tid = threadIdx.x;
     const int d = a.tg.d, F = wide_f(d), KHW = wide_khw(d);
     for (int e = tid; e < kLPW * (NP * 64 + 4); e += LCfgW::threads) {
@@ -1042,7 +1055,7 @@ __global__ void __launch_bounds__(LCfgW::threads) k_oais_logreg_wide(LogregArgs 
 {
     extern __shared__ __align__(16) char sh_raw[];
     LogregSharedW<NP>& sh = *reinterpret_cast<LogregSharedW<NP>*>(sh_raw);
-    logreg_setup_w<NP>(sh, A.a);
+    logreg_setup_w<NP>(sh, A);
     for (int64_t slot = blockIdx.x; slot < A.a.S; slot += gridDim.x) logreg_slot_w<NP>(sh, A, slot);
 }
 
@@ -1056,7 +1069,7 @@ __global__ void __launch_bounds__(LCfgW::threads)
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int2 item = items[it];
         const LogregArgs A = args[item.x];
-        logreg_setup_w<NP>(sh, A.a);
+        logreg_setup_w<NP>(sh, A);
         logreg_slot_w<NP>(sh, A, (int64_t)item.y);
         lsync();
     }
@@ -1108,27 +1121,36 @@ static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Workspace: the packed rows [n_pad][cols], then (wide layout) the cached
 // gradients at the states and at the proposals, [tiles 32][cols] each.
-size_t logreg_workspace_bytes(const TargetDev& tg, int64_t N)
+struct WsLayout {
+    size_t xp, gl, glp, total;
+};
+
+static WsLayout ws_layout(const TargetDev& tg, int64_t N)
 {
     const int cols = logreg_cols(tg.d);
-    size_t b = a256((size_t)n_pad_of(tg.n) * cols * sizeof(float));
-    if (is_wide(tg.d)) b += 2 * a256((size_t)logreg_tiles(N, tg.d) * kLPW * cols * sizeof(float));
-    return b + 256;
+    const size_t np = (size_t)n_pad_of(tg.n);
+    WsLayout L{};
+    size_t b = 0;
+    L.xp = b; b += a256(np * cols * sizeof(float));
+    if (is_wide(tg.d)) {
+        const size_t gb = a256((size_t)logreg_tiles(N, tg.d) * kLPW * cols * sizeof(float));
+        L.gl = b; b += gb;
+        L.glp = b; b += gb;
+    }
+    L.total = b + 256;
+    return L;
 }
+
+size_t logreg_workspace_bytes(const TargetDev& tg, int64_t N) { return ws_layout(tg, N).total; }
 
 void logreg_layout(const TargetDev& tg, int64_t N, void* ws, LogregArgs* A)
 {
-    const int cols = logreg_cols(tg.d);
+    const WsLayout L = ws_layout(tg, N);
     char* base = static_cast<char*>(ws);
     A->n_pad = n_pad_of(tg.n);
-    A->Xp = reinterpret_cast<float*>(base);
-    A->gl = A->glp = nullptr;
-    if (is_wide(tg.d)) {
-        const size_t xb = a256((size_t)A->n_pad * cols * sizeof(float));
-        const size_t gb = a256((size_t)logreg_tiles(N, tg.d) * kLPW * cols * sizeof(float));
-        A->gl = reinterpret_cast<float*>(base + xb);
-        A->glp = reinterpret_cast<float*>(base + xb + gb);
-    }
+    A->Xp = reinterpret_cast<float*>(base + L.xp);
+    A->gl = is_wide(tg.d) ? reinterpret_cast<float*>(base + L.gl) : nullptr;
+    A->glp = is_wide(tg.d) ? reinterpret_cast<float*>(base + L.glp) : nullptr;
 }
 
 size_t logreg_shared_bytes(int d)
@@ -1198,10 +1220,13 @@ static int kh_for(int d);
 int logreg_kh(int d) { return kh_for(d); }
 int logreg_npad(int n) { return n_pad_of(n); }
 
-hipError_t logreg_pack_into(const TargetDev& tg, float* Xp, hipStream_t st)
+hipError_t logreg_pack_into(const TargetDev& tg, int64_t N, void* ws, hipStream_t st)
 {
     const int kh = kh_for(tg.d);
     if (kh < 0) return hipErrorInvalidValue;
+    const WsLayout L = ws_layout(tg, N);
+    char* base = static_cast<char*>(ws);
+    float* Xp = reinterpret_cast<float*>(base + L.xp);
     const int np = n_pad_of(tg.n);
     const int cols = logreg_cols(tg.d);
     const int64_t total = (int64_t)np * cols;
@@ -1241,12 +1266,12 @@ static hipError_t launch_batch_w(const LogregArgs* args, const int2* items, int6
     return hipGetLastError();
 }
 
-// Packs X and y into the kernel's padded, column-permuted layout at the start
-// of ws (features [0, KH) and [KH, d) in columns [0, KH) and [32, 32 + d - KH)
-// of the 64-column layout; the panel layout above 64 features).
-hipError_t logreg_prepare(const TargetDev& tg, void* ws, hipStream_t st)
+// Packs X and y into the kernel's padded, column-permuted layout in ws
+// (features [0, KH) and [KH, d) in columns [0, KH) and [32, 32 + d - KH) of
+// the 64-column layout; the panel layout above 64 features).
+hipError_t logreg_prepare(const TargetDev& tg, int64_t N, void* ws, hipStream_t st)
 {
-    return logreg_pack_into(tg, static_cast<float*>(ws), st);
+    return logreg_pack_into(tg, N, ws, st);
 }
 
 #define OASMC_KH_LIST(X) X(4) X(8) X(12) X(16) X(20) X(25) X(32)
