@@ -36,9 +36,29 @@ PEAK_LANE_CYCLES = 256 * 64 * 2.4e9
 ALU_WORK = {"gauss": 700.0, "gauss_sat": 700.0, "asmc": 1.0e4, "asmc_ess": 1.0e4,
             "asmc_dar": 1.0e4}
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (scaled by the copy-kernel calibration); absent until measured
-# for the current kernel.
-TRAFFIC = {"logreg": 3.968e9}
+# WRITE_SIZE (scaled by the copy-kernel calibration), with the sha256 prefix of
+# the kernel source they were measured on and the summary that records them;
+# reported only while the source is unchanged.
+TRAFFIC = {
+    "logreg": dict(bytes=3.407e9, source="paper_2408_12057_amd/csrc/sweep_logreg.hip",
+                   sha256="d098bdbebd5119af",
+                   profile="profiles/k_oais_logreg_batch__logreg_n10000_d50.md"),
+    "logreg_d200": dict(bytes=10.77e9, source="paper_2408_12057_amd/csrc/sweep_logreg.hip",
+                        sha256="d098bdbebd5119af",
+                        profile="profiles/k_oais_logreg_wide_batch__logreg_n5000_d200.md"),
+}
+
+
+def measured_traffic(workload: str):
+    """(bytes, profile) of the workload's dominant kernel if its source still
+    has the hash the counters were taken on, else (None, None)."""
+    import hashlib
+    t = TRAFFIC.get(workload)
+    if not t:
+        return None, None
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()[:16]
+    return (t["bytes"], t["profile"]) if h == t["sha256"] else (None, None)
 METRIC = "particle-steps/sec and fraction of roofline at matched log Z error"
 
 
@@ -610,10 +630,11 @@ def main() -> int:
     value = steps_done / elapsed
     avg_ms = prof["kernel_ms"] / prof["launches"] if prof["launches"] else None
     if w.family == "logreg":
+        traffic, traffic_profile = measured_traffic(args.workload)
         achieved = prof["flops"] / (prof["kernel_ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
-                "traffic": TRAFFIC.get(args.workload),
+                "traffic": traffic, "traffic_profile": traffic_profile,
                 "kernel": ("k_oais_logreg_wide_batch<4>" if w.d > 64 else
                            "k_oais_logreg_batch<25>"), "avg_launch_ms": avg_ms,
                 "launches": prof["launches"]}
