@@ -261,7 +261,12 @@ def zja_workload(args, oa, torch) -> int:
     D ~ Lambda^2 / T^2 (Lambda_hat and T of OAIS's last round).  Both are timed
     over the same seeds, with the relative variance of Z_hat against the Laplace
     form of the evidence, so the line reports OAIS's speed-up over ZJA at equal
-    variance (time x variance, since the variance falls as 1/cost)."""
+    variance (time x variance, since the variance falls as 1/cost).  The
+    relative variance is the sample variance of Z_hat over the seeds divided by
+    the square of its sample mean; the log Z error against the Laplace form is
+    reported beside it (at n = 1e11 the posterior sits on a ridge about 1e-7
+    wide, which the three random-walk scales rarely move along, so both methods'
+    estimates fall far below Z at these budgets)."""
     n, k, box, N, R = 1e11, 1e10, 10.0, 1 << 14, args.zja_rounds
     p = k / n
     logZ_ref = (np.log(np.log(box * box / p)) - 2 * np.log(box) +
@@ -289,9 +294,15 @@ def zja_workload(args, oa, torch) -> int:
           for i in range(S)]
     torch.cuda.synchronize()
     t_zja = (time.perf_counter() - t0) / S
-    z_o = np.exp(np.array([r["logZ"][-1] for r in runs]) - logZ_ref)
-    z_z = np.exp(np.array([r["logZ"] for r in zr]) - logZ_ref)
-    v_o, v_z = float(np.var(z_o, ddof=1)), float(np.var(z_z, ddof=1))
+    lz_o = np.array([r["logZ"][-1] for r in runs])
+    lz_z = np.array([r["logZ"] for r in zr])
+
+    def rel_var(lz):
+        # sample variance of Z_hat over the seeds relative to its mean (the
+        # estimator is unbiased, so the mean stands in for Z); on log values
+        w = np.exp(lz - lz.max())
+        return float(np.var(w, ddof=1) / np.mean(w) ** 2)
+    v_o, v_z = rel_var(lz_o), rel_var(lz_z)
     steps_run = float(np.sum(runs[0]["N"].astype(np.float64) * runs[0]["T"]))
     rate = prof["particle_steps"] / (prof["kernel_ms"] * 1e-3) if prof["kernel_ms"] else None
     peak = PEAK_LANE_CYCLES / UNID_WORK
@@ -303,7 +314,9 @@ def zja_workload(args, oa, torch) -> int:
                        "T_last": TR},
             "logZ_error": {"seeds": S, "reference": float(logZ_ref),
                            "reference_kind": "Laplace form of the evidence",
-                           "rmse": float(np.sqrt(np.mean(np.log(z_o) ** 2))),
+                           "rmse": float(np.sqrt(np.mean((lz_o - logZ_ref) ** 2))),
+                           "mean_error": float(np.mean(lz_o - logZ_ref)),
+                           "mean_error_zja": float(np.mean(lz_z - logZ_ref)),
                            "rel_var_Z_oais": v_o, "rel_var_Z_zja": v_z},
             "comparison": {"zja_rho": rho, "zja_T_mean": float(np.mean([r["T"] for r in zr])),
                            "oais_ms_per_run": t_oais * 1e3, "zja_ms_per_run": t_zja * 1e3,
