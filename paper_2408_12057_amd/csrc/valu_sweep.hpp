@@ -571,6 +571,10 @@ __device__ __forceinline__ void oais_slot(const SweepArgs& a, const ParView& pv,
         wave_sync();
         const int tcl = lane % kTC;
         const int part = lane / kTC;
+        // the maximum over the tile's particles first (an xor butterfly over
+        // the lanes of one step: every lane ends with the same value), then
+        // one exponential per term against it and a butterfly sum: no
+        // rescaling exponentials in the merge
         double m[3] = {-INFINITY, -INFINITY, -INFINITY};
         double s[3] = {0.0, 0.0, 0.0};
         if (tcl < cnt) {
@@ -583,6 +587,12 @@ __device__ __forceinline__ void oais_slot(const SweepArgs& a, const ParView& pv,
                     for (int i = 0; i < 3; ++i) m[i] = fmax(m[i], mom_term(v, i));
                 }
             }
+        }
+#pragma unroll
+        for (int o = kTC; o < kWave; o <<= 1)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) m[i] = fmax(m[i], __shfl_xor(m[i], o, kWave));
+        if (tcl < cnt) {
 #pragma unroll
             for (int q = 0; q < PP; ++q) {
                 const int p = part * PP + q;
@@ -595,14 +605,9 @@ __device__ __forceinline__ void oais_slot(const SweepArgs& a, const ParView& pv,
             }
         }
 #pragma unroll
-        for (int o = kTC; o < kWave; o <<= 1) {
+        for (int o = kTC; o < kWave; o <<= 1)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const double m2 = __shfl_xor(m[i], o, kWave);
-                const double s2 = __shfl_xor(s[i], o, kWave);
-                lse_merge(m[i], s[i], m2, s2);
-            }
-        }
+            for (int i = 0; i < 3; ++i) s[i] += __shfl_xor(s[i], o, kWave);
         if (part == 0 && tcl < cnt) {
             double* e = a.part + ((size_t)slot * (T + 1) + (size_t)(e0 + tcl)) * 4;
 #pragma unroll
@@ -817,24 +822,25 @@ __global__ void __launch_bounds__(256, MinWaves<DPL>::value)
     double ell = z.ell[nl];
     double lw = z.lw[nl];
     const double lg = (a.beta[t] - a.beta[t - 1]) * ell;
-    // tile statistics: lse of lw, lw+lg, lw+2lg, 2(lw+lg)
+    // tile statistics: lse of lw, lw+lg, lw+2lg, 2(lw+lg) over the tile's
+    // particles: the maximum by an xor butterfly over the particle groups
+    // (every lane ends with the same value), then one exponential per lane
+    // against it and a butterfly sum
     double m[4], s[4];
     {
         const double v[4] = {lw, lw + lg, lw + 2.0 * lg, 2.0 * (lw + lg)};
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            m[i] = valid ? v[i] : -INFINITY;
-            s[i] = valid ? 1.0 : 0.0;
-        }
-    }
+        for (int i = 0; i < 4; ++i) m[i] = valid ? v[i] : -INFINITY;
 #pragma unroll
-    for (int o = LPP; o < kWave; o <<= 1) {
+        for (int o = LPP; o < kWave; o <<= 1)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const double m2 = __shfl_xor(m[i], o, kWave);
-            const double s2 = __shfl_xor(s[i], o, kWave);
-            lse_merge(m[i], s[i], m2, s2);
-        }
+            for (int i = 0; i < 4; ++i) m[i] = fmax(m[i], __shfl_xor(m[i], o, kWave));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s[i] = (valid && m[i] > -INFINITY) ? exp(v[i] - m[i]) : 0.0;
+#pragma unroll
+        for (int o = LPP; o < kWave; o <<= 1)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s[i] += __shfl_xor(s[i], o, kWave);
     }
     lw += lg;
     const bool acc = Particle<FAM, LPP, DPL>::template move<MOVE>(
