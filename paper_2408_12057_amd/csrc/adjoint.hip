@@ -27,26 +27,38 @@ hipError_t launch_adjoint(const AdjointArgs& A, const ValuShape& s, int kb, hipS
     OASMC_ADJ_K(1, 24)
     OASMC_ADJ_K(2, 16)
     OASMC_ADJ_K(4, 8)
+    OASMC_ADJ_K(8, 4)
 #undef OASMC_ADJ_K
 #undef OASMC_ADJ
     return hipErrorInvalidValue;
 }
 
-__global__ void k_adjoint_reduce(const double* __restrict__ partial, int64_t nwaves, int np,
-                                 double* grad)
+// One workgroup per parameter: each thread sums a strided share of the wave
+// records in wave order, then a fixed tree over the threads (the same bits
+// for a given number of waves).
+constexpr int kAdjRedThreads = 256;
+
+__global__ void __launch_bounds__(kAdjRedThreads)
+    k_adjoint_reduce(const double* __restrict__ partial, int64_t nwaves, int np, double* grad)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= np) return;
+    __shared__ double red[kAdjRedThreads];
+    const int c = blockIdx.x;
     double s = 0.0;
-    for (int64_t w = 0; w < nwaves; ++w) s += partial[(size_t)w * np + c];
-    grad[c] = s;
+    for (int64_t w = threadIdx.x; w < nwaves; w += kAdjRedThreads) s += partial[(size_t)w * np + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = kAdjRedThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad[c] = red[0];
 }
 
 hipError_t launch_adjoint_reduce(const double* partial, int64_t nwaves, int np, double* grad,
                                  hipStream_t st)
 {
-    hipLaunchKernelGGL(k_adjoint_reduce, dim3((np + 127) / 128), dim3(128), 0, st, partial, nwaves,
-                       np, grad);
+    hipLaunchKernelGGL(k_adjoint_reduce, dim3((unsigned)np), dim3(kAdjRedThreads), 0, st, partial,
+                       nwaves, np, grad);
     return hipGetLastError();
 }
 

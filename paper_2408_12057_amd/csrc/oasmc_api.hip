@@ -383,7 +383,7 @@ int dar_times_impl(int T, const double* beta, const double* log_g, int Tn,
 // Shapes (lanes per particle, coordinates per lane) the VALU sweeps are built
 // for; a shape holds d when LPP DPL >= d.
 const ValuShape kShapes[] = {{1, 4}, {1, 8}, {1, 12}, {1, 16}, {1, 20}, {1, 24}, {2, 16},
-                             {4, 8}, {4, 16}, {8, 8}, {8, 16}, {16, 8}, {16, 16}};
+                             {4, 8}, {8, 4}, {4, 16}, {8, 8}, {8, 16}, {16, 8}, {16, 16}};
 
 // The launch shape of a loop-swapped VALU sweep.  Without autotuning the
 // fixed rule of valu_shape; with it, the shape measured fastest for the

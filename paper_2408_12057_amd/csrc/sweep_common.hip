@@ -479,6 +479,12 @@ bool valu_shape(int d, int64_t N, ValuShape* s)
     if (d > 8 && d <= 32 && N * s->lpp < kFillLanes) {
         s->lpp = 4;
         s->dpl = 8;
+        // fewer still (4 lanes per particle would leave the SIMDs at most half
+        // a wave each): 8 lanes of 4 coordinates
+        if (N * 4 <= kFillLanes / 4) {
+            s->lpp = 8;
+            s->dpl = 4;
+        }
     }
     return true;
 }

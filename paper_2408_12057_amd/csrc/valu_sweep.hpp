@@ -1244,6 +1244,7 @@ hipError_t valu_dispatch(int what, const SweepArgs& a, const ValuShape& s, int g
     OASMC_CASE(8, 8)
     OASMC_CASE(16, 8)
     OASMC_CASE(4, 8)
+    OASMC_CASE(8, 4)
 #undef OASMC_CASE
     return hipErrorInvalidValue;
 }

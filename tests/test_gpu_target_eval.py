@@ -19,8 +19,8 @@ from paper_2408_12057_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(1, 4), (1, 8), (1, 12), (1, 16), (1, 20), (1, 24), (2, 16), (4, 8), (4, 16), (8, 8),
-          (8, 16), (16, 8), (16, 16)]
+SHAPES = [(1, 4), (1, 8), (1, 12), (1, 16), (1, 20), (1, 24), (2, 16), (4, 8), (8, 4), (4, 16),
+          (8, 8), (8, 16), (16, 8), (16, 16)]
 
 
 @pytest.fixture(scope="module")
