@@ -365,6 +365,8 @@ def pt_workload(args, oa, wl, torch) -> int:
     w = wl.gaussian_d10()
     prob = oa.Problem.gauss(w.params["mu"], w.params["sigma2"], w.ref_sigma2)
     K, Np, Tp = 2048, 63, 16384
+    if args.autotune:
+        oa.autotune(1)
     r0 = oa.run(prob, 1024, 2, seed=args.seed, move="rwmh", budget="fixed", T1=64, eps0=w.eps0)
     beta, _ = oa.adapt_schedule(r0["beta"][1], r0["log_g"][1], Np)
     eps = 2.38 / np.sqrt(w.d) / np.sqrt(1.0 + 3.0 * np.asarray(beta))
@@ -389,7 +391,8 @@ def pt_workload(args, oa, wl, torch) -> int:
             "vs_baseline": None, "dtype": "f32 state / f64 arithmetic and weights",
             "data": "synthetic",
             "config": {"workload": "gauss_d10_rwmh_parallel_tempering", "copies": K,
-                       "chains_per_copy": Np + 1, "iterations": Tp},
+                       "chains_per_copy": Np + 1, "iterations": Tp,
+                       "shape": list(oa.shape(prob, K * (Np + 1)))},
             "logZ_error": {"seeds": int(len(lz)), "reference": float(ref),
                            "reference_kind": "closed form",
                            "rmse": float(np.sqrt(np.mean((lz - ref) ** 2))),
@@ -582,7 +585,8 @@ def main() -> int:
                     choices=sorted(WORKLOADS) + ["grad", "rejuv", "batch", "batch_seq", "zja",
                                                  "pt"])
     ap.add_argument("--autotune", action="store_true",
-                    help="measure the VALU sweeps' launch shapes per problem class first (batch)")
+                    help="measure the VALU sweeps' launch shapes per problem class first "
+                         "(batch, pt)")
     ap.add_argument("--zja-rounds", type=int, default=10,
                     help="OAIS rounds of the zja workload (T doubles from 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -1261,14 +1261,18 @@ int oasmc_pt(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel* 
         if (!(eps[n] > 0.0) || !std::isfinite(eps[n]))
             return fail(OASMC_EINVAL, "eps[%d] must be positive and finite", n);
     const int R = Np + 1;
+    HIP_TRY(hipSetDevice(h->device));
+    hipStream_t st = (hipStream_t)stream;
+    // the sweeps' shape for K (N' + 1) chains (measured when autotuning is on);
+    // the rule's shape when the measured one cannot hold a copy in 16 waves
     ValuShape shape{};
-    if (!valu_shape(problem->d, (int64_t)K * R, &shape))
+    const int ps = pick_shape(h, problem, kernel, (int64_t)K * R, &shape, st);
+    if (ps) return ps;
+    if (R > 16 * (kWave / shape.lpp) && !valu_shape(problem->d, (int64_t)K * R, &shape))
         return fail(OASMC_EUNSUPPORTED, "no kernel shape for d=%d", problem->d);
     const int P = kWave / shape.lpp;
     if (R > 16 * P)
         return fail(OASMC_EUNSUPPORTED, "a copy holds at most %d chains at d=%d", 16 * P, problem->d);
-    HIP_TRY(hipSetDevice(h->device));
-    hipStream_t st = (hipStream_t)stream;
     const int d = problem->d;
     PtArgs A{};
     A.a.tg = target_dev(problem);
