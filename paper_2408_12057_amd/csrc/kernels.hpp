@@ -241,7 +241,12 @@ hipError_t launch_asmc_init(const SweepArgs& a, const ValuShape& s, const AsmcSt
                             hipStream_t st);
 hipError_t launch_asmc_step(const SweepArgs& a, const ValuShape& s, const AsmcState& z, int t,
                             int trigger, double nu, hipStream_t st);
-hipError_t launch_resample_step(const SweepArgs& a, const AsmcState& z, int t, hipStream_t st);
+// The resampler after step t: integer CDF, ancestors and the gather into
+// X2, G2, ell2 (idle unless the merge flagged an event).  commit copies the
+// gathered state back (with log w = 0) for the segment path; the per-step
+// path leaves it for the next step kernel to read.
+hipError_t launch_resample_step(const SweepArgs& a, const AsmcState& z, int t, bool commit,
+                                hipStream_t st);
 // Rejuvenation: chains and the per-tile sums, then the fixed-order reduction
 // of the tile sums into out [2 d + 1] (averages over N T samples, accepted fraction).
 hipError_t launch_rejuv(const RejuvArgs& R, const ValuShape& s, hipStream_t st);

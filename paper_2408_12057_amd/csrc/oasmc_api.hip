@@ -1100,7 +1100,7 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
                 a.t_end = t;
                 HIP_TRY(launch_oais_valu(a, shape, grid_waves, st));
                 HIP_TRY(launch_segment_merge(a, z, st));
-                if (t < T) HIP_TRY(launch_resample_step(a, z, t, st));
+                if (t < T) HIP_TRY(launch_resample_step(a, z, t, true, st));
                 t0 = t;
             }
             if (h->prof) HIP_TRY(hipEventRecord(h->ev1, st));
@@ -1110,7 +1110,7 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
             HIP_TRY(launch_asmc_init(a, shape, z, st));
             for (int t = 1; t <= T; ++t) {
                 HIP_TRY(launch_asmc_step(a, shape, z, t, kernel->trigger, kernel->nu, st));
-                if (t < T) HIP_TRY(launch_resample_step(a, z, t, st));
+                if (t < T) HIP_TRY(launch_resample_step(a, z, t, false, st));
             }
             if (h->prof) HIP_TRY(hipEventRecord(h->ev1, st));
         }

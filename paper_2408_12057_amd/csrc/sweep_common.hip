@@ -772,7 +772,8 @@ hipError_t launch_asmc_step(const SweepArgs& a, const ValuShape& s, const AsmcSt
 // Grid cap of the gather and commit kernels of the resampling variant.
 constexpr int64_t kIdleGrid = 2048;
 
-hipError_t launch_resample_step(const SweepArgs& a, const AsmcState& z, int t, hipStream_t st)
+hipError_t launch_resample_step(const SweepArgs& a, const AsmcState& z, int t, bool commit,
+                                hipStream_t st)
 {
     (void)t;
     const int64_t N = a.N;
@@ -786,9 +787,11 @@ hipError_t launch_resample_step(const SweepArgs& a, const AsmcState& z, int t, h
     const int ty = 256 / tx;
     const int64_t gblocks = std::min<int64_t>((N + ty - 1) / ty, kIdleGrid);
     hipLaunchKernelGGL(k_rs_gather, dim3((unsigned)gblocks), dim3(tx, ty), 0, st, N, d, z, nb);
-    const int64_t total = N * (int64_t)d;
-    const int64_t blocks = std::min<int64_t>((total + 255) / 256, kIdleGrid);
-    hipLaunchKernelGGL(k_rs_commit, dim3((unsigned)blocks), dim3(256), 0, st, N, d, z);
+    if (commit) {
+        const int64_t total = N * (int64_t)d;
+        const int64_t blocks = std::min<int64_t>((total + 255) / 256, kIdleGrid);
+        hipLaunchKernelGGL(k_rs_commit, dim3((unsigned)blocks), dim3(256), 0, st, N, d, z);
+    }
     return hipGetLastError();
 }
 

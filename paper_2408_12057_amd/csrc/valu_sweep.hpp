@@ -810,17 +810,24 @@ __global__ void __launch_bounds__(256, MinWaves<DPL>::value)
     const bool valid = n64 < a.N;
     const int d = a.tg.d;
     const int64_t nl = valid ? n64 : a.N - 1;  // invalid lanes work on a copy, write nothing
-    // state, ell and (MALA, HMC) grad ell as the previous step left them
+    // state, ell and (MALA, HMC) grad ell as the previous step left them:
+    // after a resampling event at the previous step (its flag is still set:
+    // the merge of this step has not run) the gathered copies X2, G2, ell2
+    // with log w = 0; this step writes X, G, ell as always, so the gathered
+    // state is never copied back (runs without a gather target never resample)
+    const bool rs = z.X2 != nullptr && z.scal[2] != 0.0;
+    const float* Xs = rs ? z.X2 : z.X;
+    const double* Gs = rs ? z.G2 : z.G;
     float x[DPL];
     double g[DPL];
 #pragma unroll
     for (int j = 0; j < DPL; ++j) {
         const int i = r * DPL + j;
-        x[j] = (i < d) ? z.X[(size_t)nl * d + i] : 0.f;
-        g[j] = (uses_grad(MOVE) && i < d) ? z.G[(size_t)nl * d + i] : 0.0;
+        x[j] = (i < d) ? Xs[(size_t)nl * d + i] : 0.f;
+        g[j] = (uses_grad(MOVE) && i < d) ? Gs[(size_t)nl * d + i] : 0.0;
     }
-    double ell = z.ell[nl];
-    double lw = z.lw[nl];
+    double ell = rs ? z.ell2[nl] : z.ell[nl];
+    double lw = rs ? 0.0 : z.lw[nl];
     const double lg = (a.beta[t] - a.beta[t - 1]) * ell;
     // tile statistics: lse of lw, lw+lg, lw+2lg, 2(lw+lg) over the tile's
     // particles: the maximum by an xor butterfly over the particle groups
