@@ -72,7 +72,7 @@ struct LogregShared {
     float prop[kLP][kPs];   // proposals
     float gl[kLP][kPs];     // gradient of ell at theta
     float glp[kLP][kPs];    // gradient of ell at prop
-    float stage[LCfg::waves][kRows][kSt];
+    alignas(16) float stage[LCfg::waves][kRows][kSt];  // 128-bit staging stores
     double ll[kLP], llp[kLP], lw[kLP];
     double llpart[LCfg::waves][kLP];
     double fwd[kLP], dle[kLP], logu[kLP];
@@ -687,9 +687,11 @@ struct LCfgW {
 
 template <int NP>
 struct LogregSharedW {
-    float theta[kLPW][NP * 64 + 4];
-    float prop[kLPW][NP * 64 + 4];
-    float stage[LCfgW::waves][kRows][kSt];
+    // rows of NP 64 + 1 floats: lane (h, j) of an MFMA operand read hits
+    // bank j + 32 h (conflict-free on 64 banks)
+    float theta[kLPW][NP * 64 + 1];
+    float prop[kLPW][NP * 64 + 1];
+    alignas(16) float stage[LCfgW::waves][kRows][kSt];
     double ll[kLPW], llp[kLPW], lw[kLPW];
     double llpart[LCfgW::waves][kLPW];
     double fwd[kLPW], dle[kLPW], logu[kLPW];
@@ -877,7 +879,7 @@ __device__ __forceinline__ void logreg_setup_w(LogregSharedW<NP>& sh, const Logr
     const SweepArgs& a = A.a;
     const int tid = threadIdx.x;
     const int d = a.tg.d, F = wide_f(d), KHW = wide_khw(d);
-    for (int e = tid; e < kLPW * (NP * 64 + 4); e += LCfgW::threads) {
+    for (int e = tid; e < kLPW * (NP * 64 + 1); e += LCfgW::threads) {
         (&sh.theta[0][0])[e] = 0.f;
         (&sh.prop[0][0])[e] = 0.f;
     }
@@ -1088,7 +1090,7 @@ __global__ void __launch_bounds__(LCfgW::threads)
     const int tid = threadIdx.x;
     const int p = tid / kTPP, r = tid % kTPP;
     const int F = wide_f(d), KHW = wide_khw(d);
-    for (int e = tid; e < kLPW * (NP * 64 + 4); e += LCfgW::threads) (&sh.prop[0][0])[e] = 0.f;
+    for (int e = tid; e < kLPW * (NP * 64 + 1); e += LCfgW::threads) (&sh.prop[0][0])[e] = 0.f;
     lsync();
     const int64_t pbase = (int64_t)blockIdx.x * kLPW;
     const int64_t n64 = pbase + p;
