@@ -328,34 +328,36 @@ hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int6
 
 int64_t resample_blocks(int64_t N);
 
-hipError_t launch_oais_logreg(const SweepArgs& a, int cus, void* ws, size_t ws_bytes,
-                              hipStream_t st);
 // One logistic-regression problem as its sweep kernel sees it.
 struct LogregArgs {
     SweepArgs a;
     const float* Xp;   // packed [n_pad][cols], rows signed by 2 y - 1, padding rows zero
     int n_pad;
-    float* gl;         // d > 64: cached gradients at the states, [tiles 32][cols]
-    float* glp;        // d > 64: gradients at the proposals, [tiles 32][cols]
+    float* gl;         // panel layout: cached gradients at the states, [tiles 32][cols]
+    float* glp;        // panel layout: gradients at the proposals, [tiles 32][cols]
 };
-int logreg_kh(int d);      // column class of d (half-width, or 1000 + panels; -1 if unsupported)
-int logreg_npad(int n);    // padded row count
-int logreg_cols(int d);    // packed columns (64, or 64 per panel above 64 features)
+// Layout class of a problem: the 64-column kernel's half-width KH, or
+// 1000 + panels for the panel layout (always above 64 features; below, when
+// 64-particle tiles would leave CUs idle); -1 if d is unsupported.  Every
+// helper below takes this class.
+int logreg_kh(int d, int64_t N, int cus);
+int logreg_npad(int n);      // padded row count
+int logreg_cols(int kh);     // packed columns
+int64_t logreg_tiles(int64_t N, int kh);
+size_t logreg_shared_bytes(int kh);
+size_t logreg_workspace_bytes(const TargetDev& tg, int64_t N, int kh);
 // Points A's data and gradient buffers into a workspace of
-// logreg_workspace_bytes(tg, N) bytes.
-void logreg_layout(const TargetDev& tg, int64_t N, void* ws, LogregArgs* A);
-// Packs the rows into a workspace laid out by logreg_layout
-// (logreg_workspace_bytes(tg, N) bytes).
-hipError_t logreg_pack_into(const TargetDev& tg, int64_t N, void* ws, hipStream_t st);
+// logreg_workspace_bytes(tg, N, kh) bytes.
+void logreg_layout(const TargetDev& tg, int64_t N, int kh, void* ws, LogregArgs* A);
+// Packs X and y into the class's padded, column-permuted layout in such a
+// workspace (logreg_prepare is the same call).
+hipError_t logreg_pack_into(const TargetDev& tg, int64_t N, int kh, void* ws, hipStream_t st);
+hipError_t logreg_prepare(const TargetDev& tg, int64_t N, int kh, void* ws, hipStream_t st);
+hipError_t launch_oais_logreg(const SweepArgs& a, int kh, int cus, void* ws, hipStream_t st);
 hipError_t launch_oais_logreg_batch(int kh, const LogregArgs* args, const int2* items,
                                    int64_t nitems, int grid, hipStream_t st);
-hipError_t launch_logreg_eval(const TargetDev& tg, const float* theta, int64_t N, double* ell,
-                              float* grad, void* ws, hipStream_t st);
-size_t logreg_workspace_bytes(const TargetDev& tg, int64_t N);
-size_t logreg_shared_bytes(int d);
-// Packs X and y into the kernel's padded, column-permuted layout in ws.
-hipError_t logreg_prepare(const TargetDev& tg, int64_t N, void* ws, hipStream_t st);
-int64_t logreg_tiles(int64_t N, int d);
+hipError_t launch_logreg_eval(const TargetDev& tg, int kh, const float* theta, int64_t N,
+                              double* ell, float* grad, void* ws, hipStream_t st);
 // Sets / clears the message oasmc_last_error() returns on this thread.
 int record_error(int code, const char* fmt, ...);
 void clear_error();

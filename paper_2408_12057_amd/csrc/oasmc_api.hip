@@ -549,7 +549,7 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
                    align256(sizeof(double) * lane_param_doubles(tg, q.shape.lpp, q.shape.dpl));
         }
         q.off_data = off;
-        if (q.logreg) off += align256(logreg_workspace_bytes(target_dev(&q.prob), q.N));
+        if (q.logreg) off += align256(logreg_workspace_bytes(target_dev(&q.prob), q.N, q.kh));
     }
     char* ws;
     {
@@ -659,7 +659,7 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
             reinterpret_cast<SweepArgs*>(blob.data() + d_sweep)[(size_t)k * P + p] = a;
             LogregArgs la{};
             la.a = a;
-            if (q.logreg) logreg_layout(a.tg, q.N, ws + q.off_data, &la);
+            if (q.logreg) logreg_layout(a.tg, q.N, q.kh, ws + q.off_data, &la);
             reinterpret_cast<LogregArgs*>(blob.data() + d_lr)[(size_t)k * P + p] = la;
             RoundDev rd{};
             rd.T = T;
@@ -713,7 +713,7 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
         for (int p = 0; p < P; ++p)
             if (ps[p].logreg) {
                 const TargetDev tg = target_dev(&ps[p].prob);
-                HIP_TRY(logreg_pack_into(tg, ps[p].N, ws + ps[p].off_data, st));
+                HIP_TRY(logreg_pack_into(tg, ps[p].N, ps[p].kh, ws + ps[p].off_data, st));
             }
     }
     HIP_TRY(hipStreamSynchronize(st));
@@ -830,13 +830,13 @@ int prepare_dev_problem(oasmc_handle* h, DevProblem& q, hipStream_t st)
     if (!(q.eps0 > 0.0)) return fail(OASMC_EINVAL, "eps0 must be positive");
     q.logreg = (q.prob.family == OASMC_LOGREG);
     if (q.logreg) {
-        if (h->lds_per_block < logreg_shared_bytes(q.prob.d))
-            return fail(OASMC_EUNSUPPORTED, "device offers %zu bytes of LDS per workgroup, need %zu",
-                        h->lds_per_block, logreg_shared_bytes(q.prob.d));
-        q.kh = logreg_kh(q.prob.d);
+        q.kh = logreg_kh(q.prob.d, q.N, h->cus);
         if (q.kh < 0) return fail(OASMC_EUNSUPPORTED, "no kernel for d=%d", q.prob.d);
+        if (h->lds_per_block < logreg_shared_bytes(q.kh))
+            return fail(OASMC_EUNSUPPORTED, "device offers %zu bytes of LDS per workgroup, need %zu",
+                        h->lds_per_block, logreg_shared_bytes(q.kh));
         q.shape = ValuShape{0, 0};
-        q.ntiles = logreg_tiles(q.N, q.prob.d);
+        q.ntiles = logreg_tiles(q.N, q.kh);
     } else {
         const int ps = pick_shape(h, &q.prob, &q.kern, q.N, &q.shape, st);
         if (ps) return ps;
@@ -993,11 +993,14 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
     if (!kernel->resample) {
         int64_t ntiles;
         ValuShape shape{};
+        int kh = -1;
         if (problem->family == OASMC_LOGREG) {
-            if (h->lds_per_block < logreg_shared_bytes(problem->d))
+            kh = logreg_kh(problem->d, N, h->cus);
+            if (kh < 0) return fail(OASMC_EUNSUPPORTED, "no kernel for d=%d", problem->d);
+            if (h->lds_per_block < logreg_shared_bytes(kh))
                 return fail(OASMC_EUNSUPPORTED, "device offers %zu bytes of LDS per workgroup, need %zu",
-                            h->lds_per_block, logreg_shared_bytes(problem->d));
-            ntiles = logreg_tiles(N, problem->d);
+                            h->lds_per_block, logreg_shared_bytes(kh));
+            ntiles = logreg_tiles(N, kh);
         } else {
             const int ps = pick_shape(h, problem, kernel, N, &shape, st);
             if (ps) return ps;
@@ -1010,15 +1013,13 @@ int oasmc_asmc(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel
         a.S = S;
         a.ntiles = ntiles;
         void* ws = nullptr;
-        size_t wb = 0;
         if (problem->family == OASMC_LOGREG) {
-            wb = logreg_workspace_bytes(a.tg, N);
-            HIP_TRY(h->get(B_LOGREG, wb, &ws));
-            HIP_TRY(logreg_prepare(a.tg, N, ws, st));
+            HIP_TRY(h->get(B_LOGREG, logreg_workspace_bytes(a.tg, N, kh), &ws));
+            HIP_TRY(logreg_prepare(a.tg, N, kh, ws, st));
         }
         if (h->prof) HIP_TRY(hipEventRecord(h->ev0, st));
         if (problem->family == OASMC_LOGREG) {
-            HIP_TRY(launch_oais_logreg(a, h->cus, ws, wb, st));
+            HIP_TRY(launch_oais_logreg(a, kh, h->cus, ws, st));
         } else {
             const int grid_waves = (int)std::min<int64_t>(S, (int64_t)h->cus * 8);
             HIP_TRY(launch_oais_valu(a, shape, grid_waves, st));
@@ -1441,15 +1442,17 @@ int oasmc_logreg_eval(oasmc_handle* h, const oasmc_problem* problem, int64_t N,
     if (problem->d < 1 || problem->d > kMaxDLogreg)
         return fail(OASMC_EUNSUPPORTED, "logistic regression supports 1 <= d <= %d", kMaxDLogreg);
     if (N < 1 || N > ((int64_t)1 << 30)) return fail(OASMC_EINVAL, "N must lie in [1, 2^30]");
-    if (h->lds_per_block < logreg_shared_bytes(problem->d))
+    const int kh = logreg_kh(problem->d, N, h->cus);
+    if (kh < 0) return fail(OASMC_EUNSUPPORTED, "no kernel for d=%d", problem->d);
+    if (h->lds_per_block < logreg_shared_bytes(kh))
         return fail(OASMC_EUNSUPPORTED, "device offers %zu bytes of LDS per workgroup, need %zu",
-                    h->lds_per_block, logreg_shared_bytes(problem->d));
+                    h->lds_per_block, logreg_shared_bytes(kh));
     HIP_TRY(hipSetDevice(h->device));
     const TargetDev tg = target_dev(problem);
     void* ws;
-    HIP_TRY(h->get(B_LOGREG, logreg_workspace_bytes(tg, N), &ws));
-    HIP_TRY(logreg_prepare(tg, N, ws, (hipStream_t)stream));
-    HIP_TRY(launch_logreg_eval(tg, theta, N, ell, grad, ws, (hipStream_t)stream));
+    HIP_TRY(h->get(B_LOGREG, logreg_workspace_bytes(tg, N, kh), &ws));
+    HIP_TRY(logreg_prepare(tg, N, kh, ws, (hipStream_t)stream));
+    HIP_TRY(launch_logreg_eval(tg, kh, theta, N, ell, grad, ws, (hipStream_t)stream));
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
     g_err.clear();
     return OASMC_OK;

@@ -1107,13 +1107,15 @@ __global__ void __launch_bounds__(LCfgW::threads)
 }
 
 // ---------------------------------------------------------------------------
-static bool is_wide(int d) { return d > 64; }
+// Layout classes: the 64-column kernel's packed half-width KH (4 .. 32), or
+// 1000 + NP for the panel layout with NP panels (1 .. 4).
+static int panels_of(int kh) { return kh >= 1000 ? kh - 1000 : 0; }
 
-int logreg_cols(int d) { return is_wide(d) ? 64 * wide_np(d) : 64; }
+int logreg_cols(int kh) { return panels_of(kh) ? 64 * panels_of(kh) : 64; }
 
-int64_t logreg_tiles(int64_t N, int d)
+int64_t logreg_tiles(int64_t N, int kh)
 {
-    const int lp = is_wide(d) ? kLPW : kLP;
+    const int lp = panels_of(kh) ? kLPW : kLP;
     return (N + lp - 1) / lp;
 }
 
@@ -1127,15 +1129,15 @@ struct WsLayout {
     size_t xp, gl, glp, total;
 };
 
-static WsLayout ws_layout(const TargetDev& tg, int64_t N)
+static WsLayout ws_layout(const TargetDev& tg, int64_t N, int kh)
 {
-    const int cols = logreg_cols(tg.d);
+    const int cols = logreg_cols(kh);
     const size_t np = (size_t)n_pad_of(tg.n);
     WsLayout L{};
     size_t b = 0;
     L.xp = b; b += a256(np * cols * sizeof(float));
-    if (is_wide(tg.d)) {
-        const size_t gb = a256((size_t)logreg_tiles(N, tg.d) * kLPW * cols * sizeof(float));
+    if (panels_of(kh)) {
+        const size_t gb = a256((size_t)logreg_tiles(N, kh) * kLPW * cols * sizeof(float));
         L.gl = b; b += gb;
         L.glp = b; b += gb;
     }
@@ -1143,22 +1145,26 @@ static WsLayout ws_layout(const TargetDev& tg, int64_t N)
     return L;
 }
 
-size_t logreg_workspace_bytes(const TargetDev& tg, int64_t N) { return ws_layout(tg, N).total; }
-
-void logreg_layout(const TargetDev& tg, int64_t N, void* ws, LogregArgs* A)
+size_t logreg_workspace_bytes(const TargetDev& tg, int64_t N, int kh)
 {
-    const WsLayout L = ws_layout(tg, N);
+    return ws_layout(tg, N, kh).total;
+}
+
+void logreg_layout(const TargetDev& tg, int64_t N, int kh, void* ws, LogregArgs* A)
+{
+    const WsLayout L = ws_layout(tg, N, kh);
     char* base = static_cast<char*>(ws);
     A->n_pad = n_pad_of(tg.n);
     A->Xp = reinterpret_cast<float*>(base + L.xp);
-    A->gl = is_wide(tg.d) ? reinterpret_cast<float*>(base + L.gl) : nullptr;
-    A->glp = is_wide(tg.d) ? reinterpret_cast<float*>(base + L.glp) : nullptr;
+    A->gl = panels_of(kh) ? reinterpret_cast<float*>(base + L.gl) : nullptr;
+    A->glp = panels_of(kh) ? reinterpret_cast<float*>(base + L.glp) : nullptr;
 }
 
-size_t logreg_shared_bytes(int d)
+size_t logreg_shared_bytes(int kh)
 {
-    if (!is_wide(d)) return sizeof(LogregShared);
-    switch (wide_np(d)) {
+    switch (panels_of(kh)) {
+    case 0: return sizeof(LogregShared);
+    case 1: return sizeof(LogregSharedW<1>);
     case 2: return sizeof(LogregSharedW<2>);
     case 3: return sizeof(LogregSharedW<3>);
     default: return sizeof(LogregSharedW<4>);
@@ -1196,7 +1202,7 @@ static hipError_t launch_eval_kh(const float* theta, int64_t N, int d, const flo
     hipError_t e = hipFuncSetAttribute((const void*)k_logreg_eval<KH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_logreg_eval<KH>), dim3((unsigned)logreg_tiles(N, d)),
+    hipLaunchKernelGGL((k_logreg_eval<KH>), dim3((unsigned)logreg_tiles(N, KH)),
                        dim3(LCfg::threads), shb, st, theta, N, d, Xp, n, n_pad, ell, grad);
     return hipGetLastError();
 }
@@ -1209,31 +1215,25 @@ static hipError_t launch_eval_w(const float* theta, int64_t N, int d, const Logr
     hipError_t e = hipFuncSetAttribute((const void*)k_logreg_eval_wide<NP>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_logreg_eval_wide<NP>), dim3((unsigned)logreg_tiles(N, d)),
+    hipLaunchKernelGGL((k_logreg_eval_wide<NP>), dim3((unsigned)logreg_tiles(N, 1000 + NP)),
                        dim3(LCfgW::threads), shb, st, theta, N, d, A.Xp, n, A.n_pad, A.glp, ell,
                        grad);
     return hipGetLastError();
 }
 
-// Exact half-widths with a dedicated instantiation; other widths round up.
-// Above 64 features the class is 1000 + the panel count.
-static int kh_for(int d);
-
-int logreg_kh(int d) { return kh_for(d); }
 int logreg_npad(int n) { return n_pad_of(n); }
 
-hipError_t logreg_pack_into(const TargetDev& tg, int64_t N, void* ws, hipStream_t st)
+hipError_t logreg_pack_into(const TargetDev& tg, int64_t N, int kh, void* ws, hipStream_t st)
 {
-    const int kh = kh_for(tg.d);
     if (kh < 0) return hipErrorInvalidValue;
-    const WsLayout L = ws_layout(tg, N);
+    const WsLayout L = ws_layout(tg, N, kh);
     char* base = static_cast<char*>(ws);
     float* Xp = reinterpret_cast<float*>(base + L.xp);
     const int np = n_pad_of(tg.n);
-    const int cols = logreg_cols(tg.d);
+    const int cols = logreg_cols(kh);
     const int64_t total = (int64_t)np * cols;
     const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
-    if (is_wide(tg.d))
+    if (panels_of(kh))
         hipLaunchKernelGGL(k_logreg_pack_wide, dim3(blocks), dim3(256), 0, st, tg.X, tg.y, tg.n,
                            tg.d, cols, np, Xp);
     else
@@ -1271,18 +1271,30 @@ static hipError_t launch_batch_w(const LogregArgs* args, const int2* items, int6
 // Packs X and y into the kernel's padded, column-permuted layout in ws
 // (features [0, KH) and [KH, d) in columns [0, KH) and [32, 32 + d - KH) of
 // the 64-column layout; the panel layout above 64 features).
-hipError_t logreg_prepare(const TargetDev& tg, int64_t N, void* ws, hipStream_t st)
+hipError_t logreg_prepare(const TargetDev& tg, int64_t N, int kh, void* ws, hipStream_t st)
 {
-    return logreg_pack_into(tg, N, ws, st);
+    return logreg_pack_into(tg, N, kh, ws, st);
 }
 
 #define OASMC_KH_LIST(X) X(4) X(8) X(12) X(16) X(20) X(25) X(32)
-#define OASMC_NP_LIST(X) X(2) X(3) X(4)
+#define OASMC_NP_LIST(X) X(1) X(2) X(3) X(4)
 
-static int kh_for(int d)
+// Above 64 features the panel layout with ceil(d / 64) panels.  Up to 64 the
+// 64-column kernel (exact half-widths with a dedicated instantiation; other
+// widths round up), unless its tiles of 64 particles, one workgroup per CU,
+// would leave CUs idle: tiles of 32 (the one-panel layout, about 10% more
+// work per particle) then finish sooner, e.g. d = 50 with N = 8192 (128 tiles
+// of 64 against 256 tiles of 32 on 256 CUs).  Below 4096 particles both are
+// latency-bound and the 64-column kernel is kept.
+int logreg_kh(int d, int64_t N, int cus)
 {
-    if (d < 1 || d > kMaxDLogreg) return -1;
-    if (is_wide(d)) return 1000 + wide_np(d);
+    if (d < 1 || d > kMaxDLogreg || N < 1) return -1;
+    if (d > 64) return 1000 + wide_np(d);
+    if (cus > 0 && N >= 4096) {
+        const int64_t r64 = ((N + kLP - 1) / kLP + cus - 1) / cus;    // rounds of tiles
+        const int64_t r32 = ((N + kLPW - 1) / kLPW + cus - 1) / cus;
+        if (0.55 * (double)r32 < (double)r64) return 1001;
+    }
     const int kh = (d + 1) / 2;
     const int list[] = {4, 8, 12, 16, 20, 25, 32};
     for (int v : list)
@@ -1290,13 +1302,12 @@ static int kh_for(int d)
     return -1;
 }
 
-hipError_t launch_oais_logreg(const SweepArgs& a, int cus, void* ws, size_t, hipStream_t st)
+hipError_t launch_oais_logreg(const SweepArgs& a, int kh, int cus, void* ws, hipStream_t st)
 {
     LogregArgs A{};
     A.a = a;
-    const int kh = kh_for(a.tg.d);
     if (kh < 0) return hipErrorInvalidValue;
-    logreg_layout(a.tg, a.N, ws, &A);
+    logreg_layout(a.tg, a.N, kh, ws, &A);
     const int grid = (int)std::min<int64_t>(a.S, (int64_t)cus);
     switch (kh) {
 #define OASMC_KH_CASE(K) case K: return launch_kh<K>(A, grid, st);
@@ -1325,13 +1336,12 @@ hipError_t launch_oais_logreg_batch(int kh, const LogregArgs* args, const int2* 
     }
 }
 
-hipError_t launch_logreg_eval(const TargetDev& tg, const float* theta, int64_t N, double* ell,
-                              float* grad, void* ws, hipStream_t st)
+hipError_t launch_logreg_eval(const TargetDev& tg, int kh, const float* theta, int64_t N,
+                              double* ell, float* grad, void* ws, hipStream_t st)
 {
-    const int kh = kh_for(tg.d);
     if (kh < 0) return hipErrorInvalidValue;
     LogregArgs A{};
-    logreg_layout(tg, N, ws, &A);
+    logreg_layout(tg, N, kh, ws, &A);
     switch (kh) {
 #define OASMC_KH_CASE(K) \
     case K: return launch_eval_kh<K>(theta, N, tg.d, A.Xp, tg.n, A.n_pad, ell, grad, st);

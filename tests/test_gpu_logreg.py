@@ -167,6 +167,17 @@ def test_mala_round_matches_oracle(oa, n, d, N, T):
         assert abs(g["logZ"] - o["logZ"]) < 2 * tau
 
 
+@pytest.mark.parametrize("N,d", [(4096, 50), (8000, 20), (20000, 64)])
+def test_one_panel_layout_when_tiles_are_few(oa, N, d):
+    """Up to 64 features with 4096 <= N particles whose 64-particle tiles would
+    leave CUs idle, the sweep runs the one-panel layout (tiles of 32): a round
+    against the oracle on a sample of particles spread over the tiles."""
+    n, T = 200, 3
+    rows = np.unique(np.linspace(0, N - 1, 40).astype(int))
+    X, y, beta, g, o = _round(oa, n, d, N, T, seed=N + d, subset=rows)
+    _check(oa, X, y, g, o, T, rows, _eps(beta, n, d))
+
+
 @pytest.mark.parametrize("slots,d", [(1, 20), (3, 20), (2, 150)])
 def test_mala_round_several_tiles_per_slot(oa, slots, d):
     """Tiles folded several to a moment slot (the accumulation branch the
