@@ -191,7 +191,8 @@ int oasmc_zja(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel*
  * t (non-reversible, deterministic even/odd), accepted iff
  * log u < (beta_{n+1} - beta_n)(ell(y at n) - ell(y at n + 1)) with u from stream
  * 4, counter (copy (Np + 1) + n, t).  One workgroup per copy; a copy holds at
- * most 16 waves of chains.  Outputs (host; each but logZ may be NULL):
+ * most 8 waves of chains (OASMC_EUNSUPPORTED above).  Outputs (host; each but
+ * logZ may be NULL):
  * *logZ = sum_n ss[n], ss[n] the log of the mean of
  * exp((beta_{n+1} - beta_n) ell) over the K Tp states at temperature n (the
  * stepping-stone estimator eq. (Z_PT), pooled over copies); rej[n] the mean

@@ -78,15 +78,22 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& zc,
     zs = r * s;
 }
 
-// Normals 4b .. 4b+3 of a (particle, step, stream, substep) sequence.
+// Normals 4b .. 4b+3 of a (particle, step, stream, substep) sequence.  With
+// need = 2 only the first pair is formed (the caller uses normals 4b, 4b+1
+// only: coordinates 4b+2 and up lie beyond d); z[2], z[3] are then zero.
 template <bool FUSED = true>
 __device__ __forceinline__ void normals4(const RngKey& key, uint32_t n, uint32_t t,
                                         uint32_t stream, uint32_t block, double z[4],
-                                        uint32_t substep = 0u)
+                                        uint32_t substep = 0u, int need = 4)
 {
     const uint4 w = draw_block<FUSED>(key, n, t, stream, substep, block);
     box_muller(w.x, w.y, z[0], z[1]);
-    box_muller(w.z, w.w, z[2], z[3]);
+    if (need > 2) {
+        box_muller(w.z, w.w, z[2], z[3]);
+    } else {
+        z[2] = 0.0;
+        z[3] = 0.0;
+    }
 }
 
 // log(exp(a) + exp(b)) with -inf handled.

@@ -1265,15 +1265,16 @@ int oasmc_pt(oasmc_handle* h, const oasmc_problem* problem, const oasmc_kernel* 
     HIP_TRY(hipSetDevice(h->device));
     hipStream_t st = (hipStream_t)stream;
     // the sweeps' shape for K (N' + 1) chains (measured when autotuning is on);
-    // the rule's shape when the measured one cannot hold a copy in 16 waves
+    // the rule's shape when the measured one cannot hold a copy in 8 waves
     ValuShape shape{};
     const int ps = pick_shape(h, problem, kernel, (int64_t)K * R, &shape, st);
     if (ps) return ps;
-    if (R > 16 * (kWave / shape.lpp) && !valu_shape(problem->d, (int64_t)K * R, &shape))
+    // a copy runs in one workgroup of at most 8 waves
+    if (R > 8 * (kWave / shape.lpp) && !valu_shape(problem->d, (int64_t)K * R, &shape))
         return fail(OASMC_EUNSUPPORTED, "no kernel shape for d=%d", problem->d);
     const int P = kWave / shape.lpp;
-    if (R > 16 * P)
-        return fail(OASMC_EUNSUPPORTED, "a copy holds at most %d chains at d=%d", 16 * P, problem->d);
+    if (R > 8 * P)
+        return fail(OASMC_EUNSUPPORTED, "a copy holds at most %d chains at d=%d", 8 * P, problem->d);
     const int d = problem->d;
     PtArgs A{};
     A.a.tg = target_dev(problem);

@@ -477,7 +477,7 @@ __device__ __forceinline__ void logreg_slot(LogregShared& sh, const LogregArgs& 
                         if (4 * b < d) {
                             double zz[4];
                             normals4<false>(a.key, n, (uint32_t)t, t > 0 ? kStreamMove : kStreamInit,
-                                     (uint32_t)b, zz);
+                                     (uint32_t)b, zz, 0u, d - 4 * b);
 #pragma unroll
                             for (int u = 0; u < 4; ++u) {
                                 const int f = 4 * b + u;
@@ -946,7 +946,7 @@ __device__ __forceinline__ void logreg_slot_w(LogregSharedW<NP>& sh, const Logre
                 for (int b = r; b < nblocks; b += kTPP) {
                     double zz[4];
                     normals4<false>(a.key, n, (uint32_t)t, t > 0 ? kStreamMove : kStreamInit,
-                                    (uint32_t)b, zz);
+                                    (uint32_t)b, zz, 0u, d - 4 * b);
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const int f = 4 * b + u;

@@ -319,7 +319,7 @@ struct Particle {
         for (int u = 0; u < 4; ++u) q[u] = 0.0;
         if (4 * b < d) {
             double w[4];
-            normals4(key, n, t, stream, (uint32_t)b, w, substep);
+            normals4(key, n, t, stream, (uint32_t)b, w, substep, d - 4 * b);
 #pragma unroll
             for (int u = 0; u < 4; ++u) q[u] = (4 * b + u < d) ? w[u] : 0.0;
         }
@@ -982,8 +982,13 @@ __global__ void __launch_bounds__(256) k_rejuv(RejuvArgs R)
 // ---------------------------------------------------------------------------
 constexpr uint32_t kStreamSwap = 4;
 
+// At most 8 waves per copy (512 threads): two waves per SIMD leave the move
+// arithmetic its registers (at 1024 threads the compiler caps a lane at 128
+// registers and spills several hundred bytes per lane).
+constexpr int kPtMaxThreads = 512;
+
 template <int FAM, int MOVE, int LPP, int DPL>
-__global__ void __launch_bounds__(1024) k_pt(PtArgs A)
+__global__ void __launch_bounds__(kPtMaxThreads) k_pt(PtArgs A)
 {
     constexpr int P = kWave / LPP;
     extern __shared__ __align__(16) char sh_dyn[];
