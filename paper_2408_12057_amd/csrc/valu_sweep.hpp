@@ -307,7 +307,12 @@ struct Particle {
     }
 
     // Normals of this lane's coordinates 4 bb .. 4 bb + 3 (zero beyond d) of
-    // one (particle, step, stream) sequence: block r DPL / 4 + bb of it.
+    // one (particle, step, stream) sequence: block r DPL / 4 + bb of it.  With
+    // one lane per particle the block index is the same in every lane, so the
+    // second Box-Muller pair of a block that ends beyond d is skipped by a
+    // uniform branch; with several lanes per particle the block index differs
+    // across the wave, the branch would diverge (no saving) and its extra live
+    // values cost the wide layouts registers, so the pair is always formed.
     static __device__ __forceinline__ void normals_block(const RngKey& key, uint32_t n,
                                                          uint32_t t, uint32_t stream, int r,
                                                          int d, int bb, double (&q)[4],
@@ -319,7 +324,7 @@ struct Particle {
         for (int u = 0; u < 4; ++u) q[u] = 0.0;
         if (4 * b < d) {
             double w[4];
-            normals4(key, n, t, stream, (uint32_t)b, w, substep, d - 4 * b);
+            normals4(key, n, t, stream, (uint32_t)b, w, substep, LPP == 1 ? d - 4 * b : 4);
 #pragma unroll
             for (int u = 0; u < 4; ++u) q[u] = (4 * b + u < d) ? w[u] : 0.0;
         }
