@@ -658,8 +658,12 @@ def main() -> int:
     else:
         rate = prof["particle_steps"] / (prof["kernel_ms"] * 1e-3) if prof["kernel_ms"] else None
         peak = PEAK_LANE_CYCLES / ALU_WORK[args.workload]
-        kern = ("k_asmc_step + k_asmc_merge + resampler, per step" if spec.kw.get("resample_")
-                else "k_oais_valu_batch")
+        if spec.kw.get("dar"):
+            kern = "k_oais_valu segments + k_seg_merge + resampler, per step"
+        elif spec.kw.get("resample_"):
+            kern = "k_asmc_step + k_asmc_merge + resampler, per step"
+        else:
+            kern = "k_oais_valu_batch"
         roof = {"bound": "alu", "achieved": rate, "peak": peak, "unit": "particle-steps/s",
                 "frac": rate / peak if rate else None, "traffic": None, "kernel": kern,
                 "work_lane_cycles_per_particle_step": ALU_WORK[args.workload],
