@@ -585,8 +585,7 @@ def main() -> int:
                     choices=sorted(WORKLOADS) + ["grad", "rejuv", "batch", "batch_seq", "zja",
                                                  "pt"])
     ap.add_argument("--autotune", action="store_true",
-                    help="measure the VALU sweeps' launch shapes per problem class first "
-                         "(batch, pt)")
+                    help="measure the VALU sweeps' launch shapes per problem class first")
     ap.add_argument("--zja-rounds", type=int, default=10,
                     help="OAIS rounds of the zja workload (T doubles from 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -628,6 +627,13 @@ def main() -> int:
     spec = WORKLOADS[args.workload](oa, wl)
     w = spec.w
     log(f"workload {w.name}: N1={spec.N1} d={w.d} rounds={spec.rounds}")
+    # the resampling path always takes the rule's shape; the autotuner serves
+    # the AIS passes
+    mv, lf = spec.kw.get("move", "rwmh"), spec.kw.get("leapfrog", 5)
+    rule_shape = (oa.shape(spec.prob, spec.N1, move=mv, leapfrog=lf)
+                  if w.family != "logreg" else None)
+    if args.autotune:
+        oa.autotune(1)
     res = None
     for i in range(args.warmup):
         res = oa.run(spec.prob, spec.N1, spec.rounds, seed=args.seed + i, **spec.kw)
@@ -701,6 +707,11 @@ def main() -> int:
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if w.family != "logreg":
+        tuned = args.autotune and not spec.kw.get("resample_")
+        shp = oa.shape(spec.prob, int(res["N"][-1]), move=mv, leapfrog=lf) if tuned else rule_shape
+        line["config"]["shape"] = list(shp)
+        line["config"]["autotune"] = bool(tuned)
     print(json.dumps(line), flush=True)
     return 0
 

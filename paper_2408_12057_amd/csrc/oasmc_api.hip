@@ -777,7 +777,7 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
             hipGraph_t gg = nullptr;
             const hipError_t ce = hipStreamEndCapture(h->cap_stream, &gg);
             if (e != OASMC_OK) {
-                if (gg) hipGraphDestroy(gg);
+                if (gg) (void)hipGraphDestroy(gg);  // the enqueue's error is the one reported
                 return e;
             }
             if (ce != hipSuccess) return fail(OASMC_EHIP, "graph capture failed: %s", hipGetErrorString(ce));
