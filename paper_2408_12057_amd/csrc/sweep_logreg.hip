@@ -204,25 +204,37 @@ __device__ __forceinline__ void put_slice(float (*stc)[kSt], const Slice& t)
     dst[4] = t.v4; dst[5] = t.v5; dst[6] = t.v6; dst[7] = t.v7;
 }
 
-// The 64 gradient accumulators of a lane as 16 float4 (element 4 k + i is
-// G[g][ft][q] with (g * 2 + ft) * 16 + q = 4 k + i), stored lane-interleaved
-// (float4 k of lane l at k * 64 + l) so every 128-bit LDS access is
-// conflict-free.
-__device__ __forceinline__ void store_grad(floatx4* dst, const floatx16 (&G)[2][2], int l)
+// Feature tiles of the gradient product: the packed halves (features
+// [0, KH) in columns 0 .. KH - 1, [KH, 2 KH) in columns 32 .. 32 + KH - 1)
+// take one 32-column tile each, or, for KH <= 16, share one tile whose
+// column j reads packed column col_of(j, KH) (feature j): half the gradient
+// instructions for d <= 32.
+template <int KH>
+struct GradTiles {
+    static constexpr int nft = KH <= 16 ? 1 : 2;
+};
+
+// The 32 NFT gradient accumulators of a lane as 8 NFT float4 (element 4 k + i
+// is G[g][ft][q] with (g * NFT + ft) * 16 + q = 4 k + i), stored
+// lane-interleaved (float4 k of lane l at k * 64 + l) so every 128-bit LDS
+// access is conflict-free.
+template <int NFT>
+__device__ __forceinline__ void store_grad(floatx4* dst, const floatx16 (&G)[2][NFT], int l)
 {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const floatx16& v = G[k / 8][(k / 4) % 2];
+    for (int k = 0; k < 8 * NFT; ++k) {
+        const floatx16& v = G[k / (4 * NFT)][(k / 4) % NFT];
         const int q = 4 * (k % 4);
         dst[k * kWave + l] = floatx4{v[q], v[q + 1], v[q + 2], v[q + 3]};
     }
 }
 
-__device__ __forceinline__ void add_grad(floatx16 (&G)[2][2], const floatx4* src, int l)
+template <int NFT>
+__device__ __forceinline__ void add_grad(floatx16 (&G)[2][NFT], const floatx4* src, int l)
 {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        floatx16& v = G[k / 8][(k / 4) % 2];
+    for (int k = 0; k < 8 * NFT; ++k) {
+        floatx16& v = G[k / (4 * NFT)][(k / 4) % NFT];
         const int q = 4 * (k % 4);
         const floatx4 u = src[k * kWave + l];
         v[q] += u[0];
@@ -243,17 +255,20 @@ __device__ __forceinline__ void contraction(LogregShared& sh, const float* __res
 {
     constexpr int kLWaves = LCfg::waves;
     constexpr double kLn2 = 0.693147180559945309;
+    constexpr int NFT = GradTiles<KH>::nft;
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
     const int l = tid % kWave;
     const int h = l / 32;
     const int j = l % 32;
+    // packed column of this lane's gradient column in each feature tile
+    const int cb0 = (NFT == 1) ? col_of(j, KH) : j;
 
-    floatx16 G[2][2];
+    floatx16 G[2][NFT];
 #pragma unroll
     for (int g = 0; g < 2; ++g)
 #pragma unroll
-        for (int ft = 0; ft < 2; ++ft)
+        for (int ft = 0; ft < NFT; ++ft)
 #pragma unroll
             for (int q = 0; q < 16; ++q) G[g][ft][q] = 0.f;
     double llacc[2] = {0.0, 0.0};
@@ -294,26 +309,52 @@ __device__ __forceinline__ void contraction(LogregShared& sh, const float* __res
         acc[0][0] = epi_b(acc[0][0], t0, lin[0], prod[0]);
         epi_a(acc[1][0], t1);
         acc[1][0] = epi_b(acc[1][0], t1, lin[1], prod[1]);
-        float bx0 = stc[slot_row(0, h)][j], bx1 = stc[slot_row(0, h)][32 + j];
+        if constexpr (NFT == 2) {
+            float bx0 = stc[slot_row(0, h)][j], bx1 = stc[slot_row(0, h)][32 + j];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int qn = (q < 15) ? q + 1 : 15;
-            const int in = slot_row(qn, h);
-            const float nbx0 = stc[in][j], nbx1 = stc[in][32 + j];
-            G[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[0][q], bx0, G[0][0], 0, 0, 0);
-            if (q < 15) epi_a(acc[0][qn], t0);
-            __builtin_amdgcn_sched_barrier(0);
-            G[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[1][q], bx0, G[1][0], 0, 0, 0);
-            if (q < 15) acc[0][qn] = epi_b(acc[0][qn], t0, lin[0], prod[0]);
-            __builtin_amdgcn_sched_barrier(0);
-            G[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[0][q], bx1, G[0][1], 0, 0, 0);
-            if (q < 15) epi_a(acc[1][qn], t1);
-            __builtin_amdgcn_sched_barrier(0);
-            G[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[1][q], bx1, G[1][1], 0, 0, 0);
-            if (q < 15) acc[1][qn] = epi_b(acc[1][qn], t1, lin[1], prod[1]);
-            __builtin_amdgcn_sched_barrier(0);
-            bx0 = nbx0;
-            bx1 = nbx1;
+            for (int q = 0; q < 16; ++q) {
+                const int qn = (q < 15) ? q + 1 : 15;
+                const int in = slot_row(qn, h);
+                const float nbx0 = stc[in][j], nbx1 = stc[in][32 + j];
+                G[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[0][q], bx0, G[0][0], 0, 0, 0);
+                if (q < 15) epi_a(acc[0][qn], t0);
+                __builtin_amdgcn_sched_barrier(0);
+                G[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[1][q], bx0, G[1][0], 0, 0, 0);
+                if (q < 15) acc[0][qn] = epi_b(acc[0][qn], t0, lin[0], prod[0]);
+                __builtin_amdgcn_sched_barrier(0);
+                G[0][NFT - 1] =
+                    __builtin_amdgcn_mfma_f32_32x32x2f32(acc[0][q], bx1, G[0][NFT - 1], 0, 0, 0);
+                if (q < 15) epi_a(acc[1][qn], t1);
+                __builtin_amdgcn_sched_barrier(0);
+                G[1][NFT - 1] =
+                    __builtin_amdgcn_mfma_f32_32x32x2f32(acc[1][q], bx1, G[1][NFT - 1], 0, 0, 0);
+                if (q < 15) acc[1][qn] = epi_b(acc[1][qn], t1, lin[1], prod[1]);
+                __builtin_amdgcn_sched_barrier(0);
+                bx0 = nbx0;
+                bx1 = nbx1;
+            }
+        } else {
+            // one feature tile: the two halves of each slot's epilogue go
+            // between its two gradient products
+            float bx = stc[slot_row(0, h)][cb0];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int qn = (q < 15) ? q + 1 : 15;
+                const float nbx = stc[slot_row(qn, h)][cb0];
+                G[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[0][q], bx, G[0][0], 0, 0, 0);
+                if (q < 15) {
+                    epi_a(acc[0][qn], t0);
+                    epi_a(acc[1][qn], t1);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                G[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[1][q], bx, G[1][0], 0, 0, 0);
+                if (q < 15) {
+                    acc[0][qn] = epi_b(acc[0][qn], t0, lin[0], prod[0]);
+                    acc[1][qn] = epi_b(acc[1][qn], t1, lin[1], prod[1]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                bx = nbx;
+            }
         }
         // the chunk's data rows: the sum of min(u, 0) plus the log of the
         // product (the padding rows' exact factors of 1/2 divided out), one log
@@ -339,7 +380,7 @@ __device__ __forceinline__ void contraction(LogregShared& sh, const float* __res
     // gradient: G_w + G_{w+4} on waves 0..3, then wave 0 adds waves 1, 2, 3
     // in that order (fixed tree), through four 16 KB slots of the staging area
     floatx4* red = reinterpret_cast<floatx4*>(&sh.stage[0][0][0]);
-    constexpr int kSlot = 16 * kWave;  // float4 per slot
+    constexpr int kSlot = 8 * NFT * kWave;  // float4 per slot
     if (w >= 4) store_grad(red + (w - 4) * kSlot, G, l);
     if (tid < kLP) {
         double s = 0.0;
@@ -352,11 +393,11 @@ __device__ __forceinline__ void contraction(LogregShared& sh, const float* __res
         store_grad(red + w * kSlot, G, l);  // slot w is read only by wave w
     }
     lsync();
-    // ((slot 0 + slot 1) + slot 2) + slot 3: wave w sums float4 2w, 2w + 1 of
-    // every lane and writes those gradient entries
+    // ((slot 0 + slot 1) + slot 2) + slot 3: wave w sums float4 NFT w ..
+    // NFT w + NFT - 1 of every lane and writes those gradient entries
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-        const int k = 2 * w + kk;
+    for (int kk = 0; kk < NFT; ++kk) {
+        const int k = NFT * w + kk;
         floatx4 v = red[k * kWave + l];
 #pragma unroll
         for (int sl = 1; sl < 4; ++sl) {
@@ -366,10 +407,11 @@ __device__ __forceinline__ void contraction(LogregShared& sh, const float* __res
             v[2] += u[2];
             v[3] += u[3];
         }
-        // float4 k holds G[g][ft][q .. q + 3], (g * 2 + ft) * 16 + q = 4 k
-        const int g = k / 8, ft = (k / 4) % 2, q0 = 4 * (k % 4);
+        // float4 k holds G[g][ft][q .. q + 3], (g * NFT + ft) * 16 + q = 4 k
+        const int g = k / (4 * NFT), ft = (k / 4) % NFT, q0 = 4 * (k % 4);
+        const int col = (NFT == 1) ? cb0 : 32 * ft + j;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) sh.glp[32 * g + slot_row(q0 + i, h)][32 * ft + j] = v[i];
+        for (int i = 0; i < 4; ++i) sh.glp[32 * g + slot_row(q0 + i, h)][col] = v[i];
     }
     // chunk 0 of the next evaluation (the rows do not change between steps)
     first = fetch_slice(Xp, n_pad, 0);
@@ -818,12 +860,23 @@ __device__ __forceinline__ void contraction_w(LogregSharedW<NP>& sh, const float
                 ahead = fetch_slice_w(Xp, n_pad, cols, c, p + 1);
             else
                 ahead = fetch_slice_w(Xp, n_pad, cols, min(c + 1, nchunks - 1), 0);
+            if (NP == 1 && khw <= 16) {
+                // a single panel of at most 32 features: one gradient tile,
+                // whose column j reads packed column col_of(j, khw) (feature
+                // j): half the gradient instructions (wave-uniform branch)
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int row = slot_row(q, h);
-                G[p][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[q], stc[row][j], G[p][0], 0, 0, 0);
-                G[p][1] =
-                    __builtin_amdgcn_mfma_f32_32x32x2f32(acc[q], stc[row][32 + j], G[p][1], 0, 0, 0);
+                for (int q = 0; q < 16; ++q)
+                    G[p][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                        acc[q], stc[slot_row(q, h)][col_of(j, khw)], G[p][0], 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int row = slot_row(q, h);
+                    G[p][0] =
+                        __builtin_amdgcn_mfma_f32_32x32x2f32(acc[q], stc[row][j], G[p][0], 0, 0, 0);
+                    G[p][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(acc[q], stc[row][32 + j], G[p][1],
+                                                                 0, 0, 0);
+                }
             }
             wsync();
         }
@@ -842,17 +895,22 @@ __device__ __forceinline__ void contraction_w(LogregSharedW<NP>& sh, const float
     // waves in order and writes those entries
     floatx4* red = reinterpret_cast<floatx4*>(&sh.stage[0][0][0]);
     constexpr int kSlot = 8 * kWave;  // float4 per wave slot
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
+    if constexpr (NP == 1) {
+        // a single panel; with one gradient tile (khw <= 16) the 4 float4 of
+        // tile 0 only, summed by waves 0..3, written at packed column
+        // col_of(j, khw) (waves 4..7 would otherwise overwrite real columns
+        // 32 .. with the empty second tile)
+        const bool one = khw <= 16;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const floatx16& v = G[p][k / 4];
+            const floatx16& v = G[0][k / 4];
             const int q = 4 * (k % 4);
-            red[w * kSlot + k * kWave + l] = floatx4{v[q], v[q + 1], v[q + 2], v[q + 3]};
+            if (!one || k < 4)
+                red[w * kSlot + k * kWave + l] = floatx4{v[q], v[q + 1], v[q + 2], v[q + 3]};
         }
         lsync();
-        {
-            const int k = w;  // float4 k holds G[p][k / 4][q .. q + 3], q = 4 (k % 4)
+        if (!one || w < 4) {
+            const int k = w;
             floatx4 v = red[k * kWave + l];
             for (int ww = 1; ww < kW; ++ww) {
                 const floatx4 u = red[ww * kSlot + k * kWave + l];
@@ -862,14 +920,43 @@ __device__ __forceinline__ void contraction_w(LogregSharedW<NP>& sh, const float
                 v[3] += u[3];
             }
             const int ft = k / 4, q0 = 4 * (k % 4);
+            const int col = one ? col_of(j, khw) : 32 * ft + j;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                glp[(size_t)(pbase + slot_row(q0 + i, h)) * cols + 64 * p + 32 * ft + j] = v[i];
+                glp[(size_t)(pbase + slot_row(q0 + i, h)) * cols + col] = v[i];
         }
-        // the stores complete before the barrier: after it, other waves of
-        // the tile read these entries (through the CU's shared L1)
         __threadfence_block();
         lsync();
+    } else {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const floatx16& v = G[p][k / 4];
+                const int q = 4 * (k % 4);
+                red[w * kSlot + k * kWave + l] = floatx4{v[q], v[q + 1], v[q + 2], v[q + 3]};
+            }
+            lsync();
+            {
+                const int k = w;  // float4 k holds G[p][k / 4][q .. q + 3], q = 4 (k % 4)
+                floatx4 v = red[k * kWave + l];
+                for (int ww = 1; ww < kW; ++ww) {
+                    const floatx4 u = red[ww * kSlot + k * kWave + l];
+                    v[0] += u[0];
+                    v[1] += u[1];
+                    v[2] += u[2];
+                    v[3] += u[3];
+                }
+                const int ft = k / 4, q0 = 4 * (k % 4);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    glp[(size_t)(pbase + slot_row(q0 + i, h)) * cols + 64 * p + 32 * ft + j] = v[i];
+            }
+            // the stores complete before the barrier: after it, other waves of
+            // the tile read these entries (through the CU's shared L1)
+            __threadfence_block();
+            lsync();
+        }
     }
 }
 

@@ -56,6 +56,9 @@ def _bounds(X, y, theta):
                                    (512, 50, 100),    # no padding rows
                                    (257, 20, 70),     # one data row in the last chunk
                                    (2048, 64, 64),    # widest 64-column layout
+                                   # one gradient tile (d <= 32): half-widths 16 and 12,
+                                   # and the one-panel layout's (N >= 4096: tiles of 32)
+                                   (700, 32, 90), (300, 29, 64), (600, 24, 4500),
                                    # panel layouts above 64 features: 2, 3 and 4 panels,
                                    # ragged panels and tiles, one data row past a chunk
                                    (1000, 80, 70), (777, 130, 33), (2000, 200, 100),
@@ -167,11 +170,12 @@ def test_mala_round_matches_oracle(oa, n, d, N, T):
         assert abs(g["logZ"] - o["logZ"]) < 2 * tau
 
 
-@pytest.mark.parametrize("N,d", [(4096, 50), (8000, 20), (20000, 64)])
+@pytest.mark.parametrize("N,d", [(4096, 50), (8000, 20), (5000, 7), (20000, 64)])
 def test_one_panel_layout_when_tiles_are_few(oa, N, d):
     """Up to 64 features with 4096 <= N particles whose 64-particle tiles would
-    leave CUs idle, the sweep runs the one-panel layout (tiles of 32): a round
-    against the oracle on a sample of particles spread over the tiles."""
+    leave CUs idle, the sweep runs the one-panel layout (tiles of 32; one
+    gradient tile up to 32 features): a round against the oracle on a sample
+    of particles spread over the tiles."""
     n, T = 200, 3
     rows = np.unique(np.linspace(0, N - 1, 40).astype(int))
     X, y, beta, g, o = _round(oa, n, d, N, T, seed=N + d, subset=rows)
