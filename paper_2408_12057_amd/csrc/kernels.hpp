@@ -216,8 +216,9 @@ bool valu_shape(int d, int64_t N, ValuShape* s);
 struct ValuBatch {
     const SweepArgs* args;   // device [nprob]
     const ParView* views;    // device [nprob]
-    const int2* items;       // device [nitems]: (problem, slot)
+    const int2* items;       // device [nitems]: (problem, slot), longest first
     int64_t nitems;
+    uint32_t* next;          // device work counter, zero at the launch; null: round robin
 };
 hipError_t launch_oais_valu_batch(int family, int move, const ValuShape& s, const ValuBatch& b,
                                   int grid_waves, hipStream_t st);
@@ -354,8 +355,11 @@ void logreg_layout(const TargetDev& tg, int64_t N, int kh, void* ws, LogregArgs*
 hipError_t logreg_pack_into(const TargetDev& tg, int64_t N, int kh, void* ws, hipStream_t st);
 hipError_t logreg_prepare(const TargetDev& tg, int64_t N, int kh, void* ws, hipStream_t st);
 hipError_t launch_oais_logreg(const SweepArgs& a, int kh, int cus, void* ws, hipStream_t st);
+// items longest first; next: a device work counter that is zero at the launch
+// (each workgroup claims the next item when it becomes idle), or null for a
+// static round robin over the workgroups
 hipError_t launch_oais_logreg_batch(int kh, const LogregArgs* args, const int2* items,
-                                   int64_t nitems, int grid, hipStream_t st);
+                                   int64_t nitems, uint32_t* next, int grid, hipStream_t st);
 hipError_t launch_logreg_eval(const TargetDev& tg, int kh, const float* theta, int64_t N,
                               double* ell, float* grad, void* ws, hipStream_t st);
 // Sets / clears the message oasmc_last_error() returns on this thread.

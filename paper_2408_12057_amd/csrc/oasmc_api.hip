@@ -599,6 +599,9 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
     const size_t d_round = dsz; dsz += align256(sizeof(RoundDev) * R * P);
     const size_t d_tg = dsz; dsz += align256(sizeof(TargetDev) * P);
     const size_t d_pp = dsz; dsz += align256(sizeof(BatchParam) * P);
+    // one work counter per class, zeroed at the start of every round by a
+    // fill kernel (capturable, unlike a memset node)
+    const size_t d_next = dsz; dsz += align256(sizeof(uint32_t) * classes.size());
     std::vector<size_t> d_items(classes.size());
     for (size_t c = 0; c < classes.size(); ++c) { d_items[c] = dsz; dsz += align256(sizeof(int2) * items[c].size()); }
     char* dd;
@@ -731,6 +734,13 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
         }
     auto enqueue = [&](hipStream_t s) -> int {
         for (int k = 0; k < R; ++k) {
+            // one problem's items (its slots) are equal: the static round
+            // robin already balances them, and no counter is needed
+            uint32_t* next = P > 1 ? reinterpret_cast<uint32_t*>(dd + d_next) : nullptr;
+            const int nc = (int)classes.size();
+            for (int c0 = 0; next && c0 < nc; c0 += 64)
+                HIP_TRY(launch_zero(nullptr, 0, reinterpret_cast<int*>(next + c0),
+                                    std::min(64, nc - c0), s));
             if (time_sweeps) HIP_TRY(hipEventRecord(h->evpool[2 * k], s));
             for (size_t c = 0; c < classes.size(); ++c) {
                 const int64_t n = (int64_t)items[c].size();
@@ -738,13 +748,15 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
                 if (classes[c].logreg) {
                     const LogregArgs* la = reinterpret_cast<const LogregArgs*>(dd + d_lr) + (size_t)k * P;
                     const int grid = (int)std::min<int64_t>(n, h->cus);
-                    HIP_TRY(launch_oais_logreg_batch(classes[c].kh, la, it, n, grid, s));
+                    HIP_TRY(launch_oais_logreg_batch(classes[c].kh, la, it, n, next ? next + c : nullptr,
+                                                     grid, s));
                 } else {
                     ValuBatch b{};
                     b.args = reinterpret_cast<const SweepArgs*>(dd + d_sweep) + (size_t)k * P;
                     b.views = reinterpret_cast<const ParView*>(dd + d_view);
                     b.items = it;
                     b.nitems = n;
+                    b.next = next ? next + c : nullptr;
                     ValuShape sh{classes[c].lpp, classes[c].dpl};
                     const int gw = (int)std::min<int64_t>(n, (int64_t)h->cus * 8);
                     HIP_TRY(launch_oais_valu_batch(classes[c].fam, classes[c].move, sh, b, gw, s));

@@ -78,6 +78,7 @@ struct LogregShared {
     double fwd[kLP], dle[kLP], logu[kLP];
     float m[64];
     uint32_t cnt;
+    uint32_t item;  // the batch item claimed by the workgroup
 };
 
 static_assert(sizeof(LogregShared::stage) >= sizeof(float) * (LCfg::waves / 2) * 64 * kWave,
@@ -650,16 +651,33 @@ __global__ void __launch_bounds__(LCfg::threads) k_oais_logreg(LogregArgs A)
     for (int64_t slot = blockIdx.x; slot < A.a.S; slot += gridDim.x) logreg_slot<KH>(sh, A, slot);
 }
 
+// The next work item of a batched launch for the whole workgroup: claimed
+// from the work counter (zero at the launch; the items come longest first, so
+// each one goes to the first workgroup that becomes idle, a greedy balance of
+// items whose lengths differ by their problems' T, N and n), or, without a
+// counter, the static round robin.  Every thread calls it; a claim passes
+// through LDS (the workgroup's previous reads of `slot` lie behind barriers).
+__device__ __forceinline__ int64_t next_item(uint32_t* next, uint32_t& slot, int64_t prev)
+{
+    if (next == nullptr) return prev < 0 ? (int64_t)blockIdx.x : prev + gridDim.x;
+    if (threadIdx.x == 0) slot = atomicAdd(next, 1u);
+    lsync();
+    return (int64_t)slot;
+}
+
 // Many logistic-regression problems with the same column half-width in one
-// launch: each workgroup walks the work list of (problem, slot) items.
-template <int KH>
+// launch: the workgroups walk the work list of (problem, slot) items, claimed
+// from the work counter (DYN) or in the static round robin (one problem,
+// whose slots are equal; that instantiation carries no claiming code).
+template <int KH, bool DYN>
 __global__ void __launch_bounds__(LCfg::threads)
     k_oais_logreg_batch(const LogregArgs* __restrict__ args, const int2* __restrict__ items,
-                        int64_t nitems)
+                        int64_t nitems, uint32_t* next)
 {
     extern __shared__ __align__(16) char sh_raw[];
     LogregShared& sh = *reinterpret_cast<LogregShared*>(sh_raw);
-    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    for (int64_t it = DYN ? next_item(next, sh.item, -1) : (int64_t)blockIdx.x; it < nitems;
+         it = DYN ? next_item(next, sh.item, it) : it + gridDim.x) {
         const int2 item = items[it];
         const LogregArgs A = args[item.x];
         logreg_setup<KH>(sh, A);
@@ -739,6 +757,7 @@ struct LogregSharedW {
     double fwd[kLPW], dle[kLPW], logu[kLPW];
     float m[NP * 64];
     uint32_t cnt;
+    uint32_t item;  // the batch item claimed by the workgroup
 };
 
 static_assert(sizeof(LogregSharedW<4>::stage) >= 16 * 8 * LCfgW::waves * kWave,
@@ -1148,14 +1167,15 @@ __global__ void __launch_bounds__(LCfgW::threads) k_oais_logreg_wide(LogregArgs 
     for (int64_t slot = blockIdx.x; slot < A.a.S; slot += gridDim.x) logreg_slot_w<NP>(sh, A, slot);
 }
 
-template <int NP>
+template <int NP, bool DYN>
 __global__ void __launch_bounds__(LCfgW::threads)
     k_oais_logreg_wide_batch(const LogregArgs* __restrict__ args, const int2* __restrict__ items,
-                             int64_t nitems)
+                             int64_t nitems, uint32_t* next)
 {
     extern __shared__ __align__(16) char sh_raw[];
     LogregSharedW<NP>& sh = *reinterpret_cast<LogregSharedW<NP>*>(sh_raw);
-    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    for (int64_t it = DYN ? next_item(next, sh.item, -1) : (int64_t)blockIdx.x; it < nitems;
+         it = DYN ? next_item(next, sh.item, it) : it + gridDim.x) {
         const int2 item = items[it];
         const LogregArgs A = args[item.x];
         logreg_setup_w<NP>(sh, A);
@@ -1331,27 +1351,37 @@ hipError_t logreg_pack_into(const TargetDev& tg, int64_t N, int kh, void* ws, hi
 
 template <int KH>
 static hipError_t launch_batch_kh(const LogregArgs* args, const int2* items, int64_t nitems,
-                                  int grid, hipStream_t st)
+                                  uint32_t* next, int grid, hipStream_t st)
 {
     const size_t shb = sizeof(LogregShared);
-    hipError_t e = hipFuncSetAttribute((const void*)k_oais_logreg_batch<KH>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb);
+    const void* f = next ? (const void*)k_oais_logreg_batch<KH, true>
+                         : (const void*)k_oais_logreg_batch<KH, false>;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_oais_logreg_batch<KH>), dim3(grid), dim3(LCfg::threads), shb, st, args,
-                       items, nitems);
+    if (next)
+        hipLaunchKernelGGL((k_oais_logreg_batch<KH, true>), dim3(grid), dim3(LCfg::threads), shb,
+                           st, args, items, nitems, next);
+    else
+        hipLaunchKernelGGL((k_oais_logreg_batch<KH, false>), dim3(grid), dim3(LCfg::threads), shb,
+                           st, args, items, nitems, next);
     return hipGetLastError();
 }
 
 template <int NP>
 static hipError_t launch_batch_w(const LogregArgs* args, const int2* items, int64_t nitems,
-                                 int grid, hipStream_t st)
+                                 uint32_t* next, int grid, hipStream_t st)
 {
     const size_t shb = sizeof(LogregSharedW<NP>);
-    hipError_t e = hipFuncSetAttribute((const void*)k_oais_logreg_wide_batch<NP>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb);
+    const void* f = next ? (const void*)k_oais_logreg_wide_batch<NP, true>
+                         : (const void*)k_oais_logreg_wide_batch<NP, false>;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shb);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_oais_logreg_wide_batch<NP>), dim3(grid), dim3(LCfgW::threads), shb, st,
-                       args, items, nitems);
+    if (next)
+        hipLaunchKernelGGL((k_oais_logreg_wide_batch<NP, true>), dim3(grid), dim3(LCfgW::threads),
+                           shb, st, args, items, nitems, next);
+    else
+        hipLaunchKernelGGL((k_oais_logreg_wide_batch<NP, false>), dim3(grid), dim3(LCfgW::threads),
+                           shb, st, args, items, nitems, next);
     return hipGetLastError();
 }
 
@@ -1409,13 +1439,14 @@ hipError_t launch_oais_logreg(const SweepArgs& a, int kh, int cus, void* ws, hip
 }
 
 hipError_t launch_oais_logreg_batch(int kh, const LogregArgs* args, const int2* items,
-                                   int64_t nitems, int grid, hipStream_t st)
+                                   int64_t nitems, uint32_t* next, int grid, hipStream_t st)
 {
     switch (kh) {
-#define OASMC_KH_CASE(K) case K: return launch_batch_kh<K>(args, items, nitems, grid, st);
+#define OASMC_KH_CASE(K) case K: return launch_batch_kh<K>(args, items, nitems, next, grid, st);
         OASMC_KH_LIST(OASMC_KH_CASE)
 #undef OASMC_KH_CASE
-#define OASMC_NP_CASE(K) case 1000 + K: return launch_batch_w<K>(args, items, nitems, grid, st);
+#define OASMC_NP_CASE(K) \
+    case 1000 + K: return launch_batch_w<K>(args, items, nitems, next, grid, st);
         OASMC_NP_LIST(OASMC_NP_CASE)
 #undef OASMC_NP_CASE
     default:

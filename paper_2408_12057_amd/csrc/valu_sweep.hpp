@@ -742,7 +742,7 @@ template <int FAM, int MOVE, int LPP, int DPL>
 __global__ void __launch_bounds__(256) k_oais_valu_batch(const SweepArgs* __restrict__ args,
                                                          const ParView* __restrict__ views,
                                                          const int2* __restrict__ items,
-                                                         int64_t nitems)
+                                                         int64_t nitems, uint32_t* next)
 {
     __shared__ double2 sh_rec[kWavesPerBlock][kTC][kWave / LPP];
     __shared__ uint32_t sh_cnt[kWavesPerBlock][kTC];
@@ -753,7 +753,16 @@ __global__ void __launch_bounds__(256) k_oais_valu_batch(const SweepArgs* __rest
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + wv;
     const int64_t W = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t it = gw; it < nitems; it += W) {
+    // each wave claims its next item from the work counter (zero at the
+    // launch; items longest first: a greedy balance), or without one takes
+    // the static round robin; the claim is read back wave-uniform
+    auto claim = [&](int64_t prev) -> int64_t {
+        if (next == nullptr) return prev < 0 ? gw : prev + W;
+        uint32_t v = 0u;
+        if ((threadIdx.x & (kWave - 1)) == 0) v = atomicAdd(next, 1u);
+        return (int64_t)__builtin_amdgcn_readfirstlane(v);
+    };
+    for (int64_t it = claim(-1); it < nitems; it = claim(it)) {
         const int2 item = items[it];
         const SweepArgs a = args[item.x];
         const ParView pv = views[item.x];
@@ -1174,11 +1183,11 @@ struct Launch {
         return hipGetLastError();
     }
     static hipError_t batch(const SweepArgs* args, const ParView* views, const int2* items,
-                            int64_t nitems, int grid_waves, hipStream_t st)
+                            int64_t nitems, uint32_t* next, int grid_waves, hipStream_t st)
     {
         const int blocks = (grid_waves + kWavesPerBlock - 1) / kWavesPerBlock;
         hipLaunchKernelGGL((k_oais_valu_batch<FAM, MOVE, LPP, DPL>), dim3(blocks), dim3(256), 0, st,
-                           args, views, items, nitems);
+                           args, views, items, nitems, next);
         return hipGetLastError();
     }
     static hipError_t init(const SweepArgs& a, const AsmcState& z, hipStream_t st)
@@ -1241,7 +1250,7 @@ hipError_t valu_dispatch(int what, const SweepArgs& a, const ValuShape& s, int g
         if (what == 1) return Launch<FAM, MOVE, L, D>::init(a, *z, st);      \
         if (what == 3)                                                       \
             return Launch<FAM, MOVE, L, D>::batch(b->args, b->views, b->items, \
-                                                  b->nitems, gw, st);        \
+                                                  b->nitems, b->next, gw, st); \
         if (what == 4) return Launch<FAM, MOVE, L, D>::rejuv(*rj, st);       \
         if (what == 5) return Launch<FAM, MOVE, L, D>::pt(*pt, st);          \
         if (what == 6) return Launch<FAM, MOVE, L, D>::eval(*ev, st);        \
