@@ -157,3 +157,48 @@ def test_batch_against_oracle_runs(oa):
         lam_T = np.array([o["Lambda"][k][o["T"][k]] for k in range(rounds)])
         np.testing.assert_allclose(b["Lambda_T"][i], lam_T, rtol=1e-6, atol=1e-8,
                                    err_msg=f"problem {i}")
+
+
+def test_more_kernel_classes_than_one_counter_fill(oa):
+    """A batch spanning more than 64 kernel classes (families x moves x lane
+    layouts x logistic-regression layouts): the per-class work counters are
+    zeroed in fills of 64, and every problem still equals its plain run."""
+    rng = np.random.default_rng(64)
+    rounds = 2
+    specs = []
+    # small N: lane layouts (1, 4), (1, 8), (8, 4), (4, 16), (16, 8), (16, 16)
+    for fam in ("gauss", "gmm"):
+        for move in ("rwmh", "mala", "hmc", "rwmh3"):
+            for d in (3, 7, 20, 50, 100, 150):
+                params = wl.random_gauss(rng, d) if fam == "gauss" else wl.random_gmm(rng, d, 3)
+                specs.append(dict(family=fam, d=d, N=64, T=4, move=move, params=params,
+                                  eps0=0.2, eps_adapt=False, eps_kappa=0.0))
+    # many particles: one lane of 12 .. 24 coordinates, two lanes of 16
+    for d, N in ((12, 131072), (16, 131072), (20, 131072), (24, 131072), (30, 65536)):
+        specs.append(dict(family="gauss", d=d, N=N, T=2, move="rwmh",
+                          params=wl.random_gauss(rng, d), eps0=0.2, eps_adapt=False,
+                          eps_kappa=0.0))
+    # logistic regression: the seven 64-column half-widths, the one-panel
+    # layout (N >= 4096) and two to four panels
+    for d, N in ((7, 64), (15, 64), (22, 64), (31, 64), (39, 64), (50, 64), (60, 64),
+                 (20, 4096), (100, 40), (150, 40), (200, 40)):
+        X, y, _ = wl.logreg_data(200, d, 3000 + d)
+        specs.append(dict(family="logreg", d=d, N=N, T=2, move="mala", params=dict(X=X, y=y),
+                          eps0=0.1, eps_adapt=False, eps_kappa=0.0))
+    probs = [_problem(oa, s) for s in specs]
+    unid = [(oa.Problem.unid(1e4, 2e3, 10.0), mv) for mv in ("rwmh", "rwmh3")]
+    valu = {(s["family"], s["move"]) + oa.shape(p, s["N"], move=s["move"], leapfrog=3)
+            for p, s in zip(probs, specs) if s["family"] != "logreg"}
+    n_logreg_layouts = 11  # half-widths 4 8 12 16 20 25 32, one panel, 2, 3 and 4 panels
+    assert len(valu) + n_logreg_layouts + len(unid) > 64
+    items = [oa.BatchItem(problem=p, N=s["N"], T=s["T"], move=s["move"], leapfrog=3,
+                          eps0=s["eps0"], seed=70 + i, problem_id=i)
+             for i, (p, s) in enumerate(zip(probs, specs))]
+    for j, (p, mv) in enumerate(unid):
+        items.append(oa.BatchItem(problem=p, N=64, T=4, move=mv, eps0=0.5, seed=900 + j,
+                                  problem_id=len(specs) + j))
+    b = oa.run_batch(items, rounds, use_graph=True)
+    assert np.all(b["status"] == 0)
+    for i, (p, s) in enumerate(zip(probs, specs)):
+        r = _plain(oa, p, s, rounds, 70 + i, i)
+        np.testing.assert_array_equal(b["logZ"][i], r["logZ"], err_msg=f"problem {i}")
