@@ -79,6 +79,11 @@ struct oasmc_handle_s {
     hipGraphExec_t graph_exec = nullptr;
     hipStream_t cap_stream = nullptr;
     std::vector<char> graph_key;
+    // side streams (default priority) on which the kernel classes of a batch
+    // round run concurrently, forked from and joined back into the caller's
+    // stream by events (captured as parallel branches of the graph)
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> fork_join;  // [0]: fork, [1 + i]: join of side stream i
     // live kernel timing
     bool prof = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -732,6 +737,20 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
             HIP_TRY(hipEventCreate(&e));
             h->evpool.push_back(e);
         }
+    // the classes of a round run concurrently on up to kSideStreams streams
+    // (their problems' buffers and work counters are disjoint)
+    constexpr int kSideStreams = 4;
+    const int nside = (P > 1) ? std::min<int>(kSideStreams, (int)classes.size()) : 0;
+    while ((int)h->side.size() < nside) {
+        hipStream_t ss;
+        HIP_TRY(hipStreamCreateWithFlags(&ss, hipStreamNonBlocking));
+        h->side.push_back(ss);
+    }
+    while ((int)h->fork_join.size() < 1 + nside) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        h->fork_join.push_back(e);
+    }
     auto enqueue = [&](hipStream_t s) -> int {
         for (int k = 0; k < R; ++k) {
             // one problem's items (its slots) are equal: the static round
@@ -742,14 +761,19 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
                 HIP_TRY(launch_zero(nullptr, 0, reinterpret_cast<int*>(next + c0),
                                     std::min(64, nc - c0), s));
             if (time_sweeps) HIP_TRY(hipEventRecord(h->evpool[2 * k], s));
+            if (nside > 1) {
+                HIP_TRY(hipEventRecord(h->fork_join[0], s));
+                for (int i = 0; i < nside; ++i) HIP_TRY(hipStreamWaitEvent(h->side[i], h->fork_join[0], 0));
+            }
             for (size_t c = 0; c < classes.size(); ++c) {
+                const hipStream_t cs = (nside > 1) ? h->side[c % nside] : s;
                 const int64_t n = (int64_t)items[c].size();
                 const int2* it = reinterpret_cast<const int2*>(dd + d_items[c]);
                 if (classes[c].logreg) {
                     const LogregArgs* la = reinterpret_cast<const LogregArgs*>(dd + d_lr) + (size_t)k * P;
                     const int grid = (int)std::min<int64_t>(n, h->cus);
                     HIP_TRY(launch_oais_logreg_batch(classes[c].kh, la, it, n, next ? next + c : nullptr,
-                                                     grid, s));
+                                                     grid, cs));
                 } else {
                     ValuBatch b{};
                     b.args = reinterpret_cast<const SweepArgs*>(dd + d_sweep) + (size_t)k * P;
@@ -759,9 +783,14 @@ int run_device(oasmc_handle* h, std::vector<DevProblem>& ps, int R, bool use_gra
                     b.next = next ? next + c : nullptr;
                     ValuShape sh{classes[c].lpp, classes[c].dpl};
                     const int gw = (int)std::min<int64_t>(n, (int64_t)h->cus * 8);
-                    HIP_TRY(launch_oais_valu_batch(classes[c].fam, classes[c].move, sh, b, gw, s));
+                    HIP_TRY(launch_oais_valu_batch(classes[c].fam, classes[c].move, sh, b, gw, cs));
                 }
             }
+            if (nside > 1)
+                for (int i = 0; i < nside; ++i) {
+                    HIP_TRY(hipEventRecord(h->fork_join[1 + i], h->side[i]));
+                    HIP_TRY(hipStreamWaitEvent(s, h->fork_join[1 + i], 0));
+                }
             if (time_sweeps) HIP_TRY(hipEventRecord(h->evpool[2 * k + 1], s));
             const RoundDev* rd = reinterpret_cast<const RoundDev*>(dd + d_round) + (size_t)k * P;
             HIP_TRY(launch_round_merge(rd, P, Tmax, s));
@@ -894,6 +923,8 @@ int oasmc_handle_destroy(oasmc_handle* h)
     if (h->ev1) hipEventDestroy(h->ev1);
     if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
     for (auto e : h->evpool) hipEventDestroy(e);
+    for (auto e : h->fork_join) hipEventDestroy(e);
+    for (auto s : h->side) hipStreamDestroy(s);
     if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     for (auto& b : h->bufs)
         if (b.p) hipFree(b.p);
