@@ -380,9 +380,13 @@ typedef struct {
 /*
  * Alg. 2 for P independent problems at once (AIS passes, N fixed, T doubling
  * per round).  Problems are grouped by kernel class; each round launches one
- * kernel per class over a work list of (problem, slot) items, then merges
- * every problem's moments and runs Alg. 3 and the step-size update on the
- * device, one workgroup per problem — no host round trip between rounds.
+ * kernel per class over a work list of (problem, slot) items, longest first,
+ * claimed by the workgroups from a per-class counter, then merges every
+ * problem's moments and runs Alg. 3 and the step-size update on the device,
+ * one workgroup per problem — no host round trip between rounds.  With more
+ * than one problem the classes of a round run on up to four streams of the
+ * handle, forked from `stream` and joined back into it by events before the
+ * round's merge (so all work stays ordered after earlier work on `stream`).
  * use_graph = 1 captures all rounds as one hipGraph (kept in the handle and
  * replayed while the batch is unchanged).  Each problem's results are bitwise
  * those of oasmc_run on it alone (budget DOUBLE_T, T1 = max(1, T >> (R-1)),
