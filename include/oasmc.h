@@ -384,7 +384,7 @@ typedef struct {
  * claimed by the workgroups from a per-class counter, then merges every
  * problem's moments and runs Alg. 3 and the step-size update on the device,
  * one workgroup per problem — no host round trip between rounds.  With more
- * than one problem the classes of a round run on up to four streams of the
+ * than one problem the classes of a round run on two streams of the
  * handle, forked from `stream` and joined back into it by events before the
  * round's merge (so all work stays ordered after earlier work on `stream`).
  * use_graph = 1 captures all rounds as one hipGraph (kept in the handle and
