@@ -919,16 +919,18 @@ int oasmc_handle_create(oasmc_handle** h, int device)
 int oasmc_handle_destroy(oasmc_handle* h)
 {
     if (!h) return OASMC_OK;
-    hipSetDevice(h->device);
-    if (h->ev0) hipEventDestroy(h->ev0);
-    if (h->ev1) hipEventDestroy(h->ev1);
-    if (h->graph_exec) hipGraphExecDestroy(h->graph_exec);
-    for (auto e : h->evpool) hipEventDestroy(e);
-    for (auto e : h->fork_join) hipEventDestroy(e);
-    for (auto s : h->side) hipStreamDestroy(s);
-    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    // teardown releases everything it can; a failing release leaves nothing
+    // for the caller to act on, so the statuses are discarded on purpose
+    (void)hipSetDevice(h->device);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    for (auto e : h->evpool) (void)hipEventDestroy(e);
+    for (auto e : h->fork_join) (void)hipEventDestroy(e);
+    for (auto s : h->side) (void)hipStreamDestroy(s);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     for (auto& b : h->bufs)
-        if (b.p) hipFree(b.p);
+        if (b.p) (void)hipFree(b.p);
     delete h;
     return OASMC_OK;
 }

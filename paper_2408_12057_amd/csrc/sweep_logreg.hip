@@ -850,7 +850,7 @@ __device__ __forceinline__ void contraction_w(LogregSharedW<NP>& sh, const float
             put_slice(stc, ahead);
             wsync();
             ahead = fetch_slice_w(Xp, n_pad, cols, c, (p + 1) % NP);
-#pragma unroll 4
+#pragma nounroll
             for (int s = 0; s < khw; ++s)
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(stc[j][32 * h + s],
                                                            sh.prop[j][64 * p + 32 * h + s], acc,
